@@ -1,0 +1,340 @@
+"""Pore decomposition: primary grids, contact interfaces, dual grids.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Paper, Section 3.2.1 (domain decomposition) and the permutation paragraph of
+Section 3.2.2: the void space is split into non-overlapping primary grids
+(pores); contact interfaces separate adjacent primaries; a face with at least
+one flanking cell in a primary belongs to that primary, and a face flanked by
+neither belongs to the interface ("f" unknowns); dual grids are successive
+dilations of each interface and may overlap.  Section 4 tags the faces near
+the interfaces, where the modified residual carries no inertia.
+
+The caller's pore labels stand in for the paper's watershed; the rules that
+turn labels into interfaces are this project's reading of the paper (the
+paper asks only for a thinnest separating set, which it does not construct):
+
+* gauge / connectivity: only the largest face-connected void component is
+  kept (periodic wrap included); the rest is treated as grain;
+* carving: a cell is an interface cell iff a face neighbour has a smaller
+  positive label; its interface is the pair (smallest such neighbour label,
+  own label); interfaces are numbered by sorting the pairs; a primary is the
+  set of its label's cells that are not interface cells (empty ones are
+  dropped), numbered in label order;
+* admissibility: the closure of a primary replaces every coupling to an
+  f-face or another primary by a zero normal gradient, so a group of the
+  primary's same-axis faces that are linked to each other through the viscous
+  stencil, and none of which touches a grain (or the image edge), would leave
+  a uniform velocity on that group undetermined.  Each such primary's label is
+  merged into the face-adjacent label it shares the most faces with (lowest
+  label on ties; all offending labels in one pass, chains followed) and the
+  carving is redone, until every primary is admissible;
+* an interface with no face to any primary cell is merged into the interface
+  it shares the most faces with (lowest id on ties), lowest id first, until
+  none is left; ids are then compacted keeping their order;
+* the pin c* is the first fluid cell in raster order that is not an interface
+  cell;
+* tags: a face is tagged iff one of its two cells lies within Chebyshev
+  distance ``tag_layers`` of an interface cell;
+* dual grid j: the cells of interface j, grown ``dual_dilations`` times by
+  face neighbours through the void space (default 2 in 2D, 0 in 3D: a 3D
+  interface sheet already covers a large share of the cells, and the default
+  keeps the union of the dual grids near the 10-30% of the void space the
+  paper reports in its complexity discussion);
+* the unknowns of a cell set: its cells plus every active face with at least
+  one flanking cell in the set.
+"""
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+from scipy import ndimage as ndi
+
+from .mac import MacGrid
+
+
+def largest_component(mask, periodic=(True, False, False)):
+    """Keep the largest face-connected void component (periodic-aware)."""
+    m = np.asarray(mask).astype(bool)
+    if m.ndim == 2:
+        m = m[None]
+    two_d = m.shape[0] == 1
+    st = ndi.generate_binary_structure(3, 1)
+    if two_d:
+        st[0] = False
+        st[2] = False
+    lab, n = ndi.label(m, structure=st)
+    if n <= 1:
+        return m.astype(np.uint8)
+    parent = np.arange(n + 1)
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for d, per in enumerate(periodic):
+        if not per or (two_d and d == 2):
+            continue
+        ax = 2 - d
+        a = np.take(lab, 0, axis=ax).ravel()
+        b = np.take(lab, -1, axis=ax).ravel()
+        for x, y in zip(a[(a > 0) & (b > 0)], b[(a > 0) & (b > 0)]):
+            rx, ry = find(x), find(y)
+            if rx != ry:
+                parent[max(rx, ry)] = min(rx, ry)
+    root = np.array([find(a) for a in range(n + 1)])
+    comp = root[lab]
+    sizes = np.bincount(comp.ravel(), minlength=n + 1)
+    sizes[0] = 0
+    keep = np.argmax(sizes)
+    return (comp == keep).astype(np.uint8)
+
+
+def cell_neighbours(g: MacGrid):
+    """nbr[c, 2*d + (s>0)]: cell number across the active face in direction
+    s*e_d of fluid cell c, or -1."""
+    cid = g.cid - g.nu
+    cid[~g.fluid] = -1
+    cells = np.flatnonzero(g.fluid)
+    nbr = np.full((g.nc, 2 * g.ndim), -1, dtype=np.int64)
+    for d in g.comps:
+        for t, s in enumerate((-1, +1)):
+            nb = g.shift(cid, d, s, -1).ravel()[cells]
+            nbr[:, 2 * d + t] = nb
+    return nbr
+
+
+def cell_faces(g: MacGrid):
+    """fc[c, 2*d + t]: global unknown of the lower (t=0) / upper (t=1) d-face of
+    cell c, or -1 when that face is not active."""
+    cells = np.flatnonzero(g.fluid)
+    fc = np.full((g.nc, 2 * g.ndim), -1, dtype=np.int64)
+    for d in g.comps:
+        fc[:, 2 * d] = g.fid[d].ravel()[cells]
+        fc[:, 2 * d + 1] = g.shift(g.fid[d], d, +1, -1).ravel()[cells]
+    return fc
+
+
+@dataclass
+class Decomp:
+    g: MacGrid
+    label: np.ndarray           # per cell (p-block numbering), >0
+    iface: np.ndarray           # per cell: interface id or -1
+    prim: np.ndarray            # per cell: primary id or -1
+    Nc: int
+    Np: int
+    pairs: np.ndarray           # (Nc, 2) label pair of each interface
+    pin: int
+    owner: np.ndarray           # per velocity unknown (0..nu-1): primary id or -1 (f-face)
+    Cp: List[np.ndarray]        # interfaces adjacent to each primary
+    tags: List[np.ndarray]      # per face axis: bool per active face
+    S: List[np.ndarray]         # unknowns of each primary (sorted global)
+    D: List[np.ndarray]         # unknowns of each dual grid (sorted global)
+    dual_cells: List[np.ndarray]
+    icells: List[np.ndarray]    # global unknowns of each interface's cells
+    f_faces: np.ndarray
+
+
+def unknowns_of_cells(g, fc, cells):
+    """Cells of the set plus every active face with a flanking cell in it."""
+    faces = fc[cells].ravel()
+    faces = faces[faces >= 0]
+    return np.unique(np.concatenate([faces, g.nu + np.asarray(cells, dtype=np.int64)]))
+
+
+def walled_faces(g: MacGrid):
+    """Per face axis: True for an active face whose viscous stencil reaches a
+    position that is not an active face of the same axis (grain, grain surface
+    or image edge)."""
+    out = []
+    for c in g.comps:
+        act = g.act[c]
+        w = np.zeros(int(act.sum()), dtype=bool)
+        for d in g.comps:
+            for s in (-1, +1):
+                w |= g.shift(g.fid[c], d, s, -1)[act] < 0
+        out.append(w)
+    return out
+
+
+def carve(L, nbr):
+    nbL = np.where(nbr >= 0, L[np.maximum(nbr, 0)], 0)
+    lower = (nbL > 0) & (nbL < L[:, None])
+    is_if = lower.any(1)
+    minlow = np.where(lower, nbL, np.iinfo(np.int64).max).min(1)
+    return is_if, minlow
+
+
+def _bad_labels(g, L, is_if, fc, walled):
+    """Labels of primaries that own a viscous-connected group of same-axis
+    faces with no walled face."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    bad = set()
+    cell_lab = np.where(is_if, 0, L)
+    for c in g.comps:
+        nc = g.ncomp[c]
+        lab_face = np.zeros(nc, dtype=np.int64)
+        for t in (0, 1):
+            f = fc[:, 2 * c + t]
+            ok = (f >= 0) & (cell_lab > 0)
+            lab_face[f[ok] - g.off[c]] = cell_lab[ok]
+        act = g.act[c]
+        me = g.fid[c][act] - g.off[c]
+        rr, cc = [], []
+        for d in g.comps:
+            nb = g.shift(g.fid[c], d, +1, -1)[act]
+            ok = nb >= 0
+            a, b = me[ok], nb[ok] - g.off[c]
+            same = (lab_face[a] > 0) & (lab_face[a] == lab_face[b])
+            rr.append(a[same])
+            cc.append(b[same])
+        rr, cc = np.concatenate(rr), np.concatenate(cc)
+        A = csr_matrix((np.ones(rr.size), (rr, cc)), shape=(nc, nc))
+        _, grp = connected_components(A, directed=False)
+        owned = lab_face > 0
+        has_wall = np.zeros(grp.max() + 1 if grp.size else 0, dtype=bool)
+        has_wall[grp[owned & walled[c]]] = True
+        free = owned & ~has_wall[grp]
+        bad.update(np.unique(lab_face[free]).tolist())
+    return sorted(bad)
+
+
+def _merge_labels(L, nbr, bad):
+    """Map each bad label to the adjacent label sharing the most faces."""
+    Lmax = int(L.max())
+    a = L[:, None].repeat(nbr.shape[1], 1)
+    b = np.where(nbr >= 0, L[np.maximum(nbr, 0)], 0)
+    sel = (b > 0) & (a != b)
+    pa, pb = a[sel], b[sel]
+    target = np.arange(Lmax + 1)
+    for l in bad:
+        m = pa == l
+        if not np.any(m):
+            continue
+        cnt = np.bincount(pb[m], minlength=Lmax + 1)
+        target[l] = int(np.argmax(cnt))
+    # follow chains; a cycle collapses to its smallest label
+    final = target.copy()
+    for l in bad:
+        seen = [l]
+        cur = target[l]
+        while cur != target[cur] and cur not in seen:
+            seen.append(cur)
+            cur = target[cur]
+        if cur in seen:
+            cyc = seen[seen.index(cur):]
+            cur = min(cyc)
+        final[l] = cur
+    return final[L]
+
+
+def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
+    if dual_dilations is None:
+        dual_dilations = 2 if g.ndim == 2 else 0
+    lab_grid = np.asarray(labels)
+    if lab_grid.ndim == 2:
+        lab_grid = lab_grid[None]
+    cells = np.flatnonzero(g.fluid)
+    L = lab_grid.ravel()[cells].astype(np.int64)
+    if np.any(L <= 0):
+        raise ValueError("every fluid cell needs a positive pore label")
+    nbr = cell_neighbours(g)
+    fc = cell_faces(g)
+    nc = g.nc
+    walled = walled_faces(g)
+    # --- carving, repeated until every primary is admissible
+    while True:
+        is_if, minlow = carve(L, nbr)
+        bad = _bad_labels(g, L, is_if, fc, walled)
+        if not bad:
+            break
+        L = _merge_labels(L, nbr, bad)
+    pr = np.stack([minlow[is_if], L[is_if]], 1)
+    upairs, inv = np.unique(pr, axis=0, return_inverse=True)
+    iface = np.full(nc, -1, dtype=np.int64)
+    iface[is_if] = inv.ravel()
+    # --- merge interfaces that touch no primary cell
+    while True:
+        nif = upairs.shape[0]
+        prim_cell = iface < 0
+        a_if = iface[:, None].repeat(nbr.shape[1], 1)
+        valid = (nbr >= 0) & (a_if >= 0)
+        nb_prim = valid & prim_cell[np.maximum(nbr, 0)]
+        touches = np.zeros(nif, dtype=bool)
+        touches[a_if[nb_prim]] = True
+        bad = np.nonzero(~touches)[0]
+        if bad.size == 0:
+            break
+        j = bad[0]
+        nb_if = np.where(valid, iface[np.maximum(nbr, 0)], -1)
+        sel = (a_if == j) & (nb_if >= 0) & (nb_if != j)
+        cand = nb_if[sel]
+        if cand.size == 0:
+            raise ValueError("interface %d touches neither a primary nor another interface" % j)
+        cnt = np.bincount(cand, minlength=nif)
+        k = int(np.argmax(cnt))          # argmax returns the lowest id on ties
+        iface[iface == j] = k
+        keep = np.ones(nif, dtype=bool)
+        keep[j] = False
+        remap = np.cumsum(keep) - 1
+        iface = np.where(iface >= 0, remap[np.maximum(iface, 0)], -1)
+        upairs = upairs[keep]
+    Nc = upairs.shape[0]
+    # --- primaries
+    prim_labels = np.unique(L[iface < 0])
+    pmap = {int(l): n for n, l in enumerate(prim_labels)}
+    prim = np.full(nc, -1, dtype=np.int64)
+    pc = iface < 0
+    prim[pc] = np.searchsorted(prim_labels, L[pc])
+    Np = prim_labels.size
+    pin = int(np.flatnonzero(iface < 0)[0])
+    # --- face ownership (D3)
+    owner = np.full(g.nu, -1, dtype=np.int64)
+    for d in g.comps:
+        for t in (0, 1):
+            f = fc[:, 2 * d + t]
+            ok = (f >= 0) & (prim >= 0)
+            prev = owner[f[ok]]
+            clash = (prev >= 0) & (prev != prim[ok])
+            if np.any(clash):
+                raise AssertionError("a face lies between two different primaries")
+            owner[f[ok]] = prim[ok]
+    f_faces = np.flatnonzero(owner < 0)
+    # --- C^{p_i}: interfaces sharing a face with primary i (D4)
+    a_pr = prim[:, None].repeat(nbr.shape[1], 1)
+    nb_if = np.where(nbr >= 0, iface[np.maximum(nbr, 0)], -1)
+    sel = (a_pr >= 0) & (nb_if >= 0)
+    pairs_pi = np.unique(np.stack([a_pr[sel], nb_if[sel]], 1), axis=0)
+    Cp = [pairs_pi[pairs_pi[:, 0] == i, 1] for i in range(Np)]
+    # --- tags (D5)
+    ifgrid = np.zeros(g.fluid.shape, dtype=bool)
+    ifgrid.ravel()[cells[iface >= 0]] = True
+    near = ifgrid.copy()
+    for d in g.comps:
+        acc = near.copy()
+        for s in range(1, tag_layers + 1):
+            acc |= g.shift(near, d, s, False) | g.shift(near, d, -s, False)
+        near = acc
+    tags = []
+    for d in g.comps:
+        act = g.act[d]
+        t = near[act] | g.shift(near, d, -1, False)[act]
+        tags.append(t)
+    # --- unknown sets
+    S = [unknowns_of_cells(g, fc, np.flatnonzero(prim == i)) for i in range(Np)]
+    icell_sets = [np.flatnonzero(iface == j) for j in range(Nc)]
+    icells = [g.nu + c for c in icell_sets]
+    dual_cells, D = [], []
+    for j in range(Nc):
+        cur = icell_sets[j]
+        for _ in range(dual_dilations):
+            nb = nbr[cur].ravel()
+            cur = np.unique(np.concatenate([cur, nb[nb >= 0]]))
+        dual_cells.append(cur)
+        D.append(unknowns_of_cells(g, fc, cur))
+    return Decomp(g=g, label=L, iface=iface, prim=prim, Nc=Nc, Np=Np, pairs=upairs,
+                  pin=pin, owner=owner, Cp=Cp, tags=tags, S=S, D=D,
+                  dual_cells=dual_cells, icells=icells, f_faces=f_faces)

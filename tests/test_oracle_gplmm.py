@@ -1,0 +1,229 @@
+"""Pins of the oracle's decomposition, gPLMM preconditioner and FGMRES (CPU).
+
+* the sparse preconditioner against a literal dense transcription of the
+  paper's matrices W, Q, P, R, csum and the Schwarz sums (brute force, tiny
+  grids);
+* special cases with exact answers: one pore (M^-1 = X^-1), a channel cut into
+  slabs (M_G^-1 reproduces Poiseuille flow exactly), the Remark-1 coarse
+  operator as an oblique projection, sign invariance in b_B, partition of
+  unity of the shape vectors, zero row sums of the coarse operator;
+* FGMRES with a fixed preconditioner against textbook right-preconditioned
+  GMRES (same residual history);
+* decomposition invariants (carving separates primaries, p/c/f partition).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle.mac import MacGrid, Operators, Phys, build_matrix, origin_rhs, residual
+from oracle.decomp import decompose, largest_component
+from oracle import gplmm as G
+from oracle.literal import literal_preconditioner
+from oracle.krylov import fgmres, gmres_right_history
+from synth import make_workload, channel
+from synth.packing import boolean_packing
+from synth.watershed import watershed_labels
+
+
+def _case(mask, labels, body=(1.0, 0.0, 0.0), periodic=(True, False, False), wind_seed=None,
+          dt=None):
+    mask = largest_component(mask, periodic)
+    g = MacGrid(mask, periodic=periodic)
+    ops = Operators(g)
+    dc = decompose(g, labels)
+    ph = Phys(1.0, 1.0, body, dt, dc.pin)
+    wind = None
+    if wind_seed is not None:
+        wind = np.random.default_rng(wind_seed).standard_normal(g.N)
+    X = build_matrix(ops, ph, wind=wind, tags=dc.tags)
+    bB = origin_rhs(ops, ph)
+    return g, ops, dc, ph, X, bB
+
+
+def _tiny_2d(seed=0):
+    w = make_workload("disks2d_32", seed)
+    m = w["mask"][:, 2:14, 3:21].copy()
+    lab = watershed_labels(m, footprint=5, min_size=6)
+    return m, lab
+
+
+def _tiny_3d(seed=1):
+    m = boolean_packing((6, 8, 9), 2.2, 0.3, 0.5, seed)
+    lab = watershed_labels(m, footprint=3, min_size=6)
+    return m, lab
+
+
+@pytest.mark.parametrize("maker,wind_seed,dt", [(_tiny_2d, None, None), (_tiny_2d, 5, None),
+                                                (_tiny_3d, None, None), (_tiny_3d, 7, 0.5)])
+def test_sparse_gplmm_matches_literal_matrices(maker, wind_seed, dt):
+    m, lab = maker()
+    g, ops, dc, ph, X, bB = _case(m, lab, body=(1.0, 0.2, 0.1), wind_seed=wind_seed, dt=dt)
+    assert dc.Np >= 2 and dc.Nc >= 1
+    M = G.build(X, dc, bB)
+    Mlit, MGlit = literal_preconditioner(X.toarray(), dc, bB)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        v = rng.standard_normal(g.N)
+        z = G.apply(M, v)
+        zl = Mlit @ v
+        assert np.linalg.norm(z - zl) <= 1e-11 * np.linalg.norm(zl)
+        zg = G.apply_MG(M, v)
+        assert np.linalg.norm(zg - MGlit @ v) <= 1e-11 * np.linalg.norm(MGlit @ v)
+
+
+def test_single_pore_preconditioner_is_exact_inverse():
+    m = np.ones((5, 7, 8), np.uint8)
+    m[1:3, 3, 3:5] = 0
+    g, ops, dc, ph, X, bB = _case(m, np.ones_like(m, dtype=np.int32))
+    assert dc.Nc == 0 and dc.Np == 1
+    M = G.build(X, dc, bB)
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(g.N)
+    z = G.apply(M, v)
+    assert np.linalg.norm(X @ z - v) <= 1e-12 * np.linalg.norm(v)
+    x, its, ok = fgmres(lambda a: X @ a, bB, lambda a: G.apply(M, a), 1e-12 * np.linalg.norm(bB))
+    assert ok and its == 1
+
+
+@pytest.mark.parametrize("dims,per", [((1, 8, 24), (True, False, False)),
+                                      ((6, 8, 24), (True, False, False)),
+                                      ((6, 8, 24), (True, False, True))])
+def test_slab_channel_coarse_solve_is_poiseuille(dims, per):
+    nz, ny, nx = dims
+    m = channel(nx, ny, nz)
+    lab = np.zeros_like(m, dtype=np.int32)
+    for s in range(4):
+        lab[:, :, s * 6:(s + 1) * 6] = s + 1
+    g, ops, dc, ph, X, bB = _case(m, lab, periodic=per)
+    assert dc.Np == 4 and dc.Nc == 4
+    M = G.build(X, dc, bB)
+    xg = G.apply_MG(M, bB)
+    xs = spla.spsolve(X.tocsc(), bB)
+    assert np.linalg.norm(xg - xs) <= 1e-12 * np.linalg.norm(xs)
+    x, its, ok = fgmres(lambda a: X @ a, bB, lambda a: G.apply(M, a), 1e-12 * np.linalg.norm(bB))
+    assert ok and its == 1
+
+
+def test_remark1_coarse_operator_is_a_projection():
+    m, lab = _tiny_3d()
+    g, ops, dc, ph, X, bB = _case(m, lab, wind_seed=3)
+    M = G.build(X, dc, bB)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal(g.N)
+    a = G.apply_MG(M, X @ v)
+    b = G.apply_MG(M, X @ a)
+    assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(a)
+
+
+def test_correction_sign_does_not_change_coarse_operator():
+    m, lab = _tiny_2d()
+    g, ops, dc, ph, X, bB = _case(m, lab)
+    M1 = G.build(X, dc, bB)
+    M2 = G.build(X, dc, -bB)
+    v = np.random.default_rng(5).standard_normal(g.N)
+    a, b = G.apply_MG(M1, v), G.apply_MG(M2, v)
+    assert np.linalg.norm(a - b) <= 1e-11 * np.linalg.norm(a)
+
+
+def test_shape_vectors_partition_of_unity():
+    m, lab = _tiny_3d()
+    g, ops, dc, ph, X, bB = _case(m, lab, wind_seed=9)
+    M = G.build(X, dc, bB)
+    pin_prim = dc.prim[dc.pin]
+    for i in range(dc.Np):
+        if i == pin_prim or dc.Cp[i].size == 0:
+            continue
+        s = M.phi[i].sum(1)
+        S = dc.S[i]
+        want = (S >= g.nu).astype(float)       # u = 0, p = 1
+        assert np.max(np.abs(s - want)) <= 1e-11
+
+
+def test_coarse_interface_columns_sum_to_zero_away_from_pin():
+    m, lab = _tiny_2d(1)
+    g, ops, dc, ph, X, bB = _case(m, lab)
+    M = G.build(X, dc, bB)
+    rows = M.Ao[:, :dc.Nc].sum(1)
+    # rows whose restriction stencil never reaches the pin's primary
+    pin_prim = dc.prim[dc.pin]
+    Spin = set(dc.S[pin_prim].tolist())
+    far = []
+    Xc = X.tocsr()
+    for q in range(M.Ao.shape[0]):
+        rowset = dc.icells[q] if q < dc.Nc else dc.S[M.ycols[q - dc.Nc]]
+        cols = set(np.unique(Xc[rowset].indices).tolist())
+        if not (cols & Spin) and not (set(rowset.tolist()) & Spin):
+            far.append(q)
+    assert far
+    scale = np.abs(M.Ao).max()
+    assert np.max(np.abs(rows[far])) <= 1e-11 * scale
+
+
+def test_fgmres_fixed_preconditioner_equals_right_gmres():
+    m, lab = _tiny_2d(2)
+    g, ops, dc, ph, X, bB = _case(m, lab, wind_seed=1)
+    M = G.build(X, dc, bB)
+    Xd = X.toarray()
+    Minv = np.stack([G.apply(M, e) for e in np.eye(g.N)], 1)
+    b = np.random.default_rng(3).standard_normal(g.N)
+    ref = gmres_right_history(Xd, Minv, b, 12)
+    hist = []
+    fgmres(lambda a: Xd @ a, b, lambda a: Minv @ a, 0.0, m=12, maxit=12, history=hist)
+    hist = np.array(hist[:13])
+    # the same minimal-residual iterates: histories agree to rounding
+    assert np.max(np.abs(hist - ref)) <= 1e-12 * ref[0]
+    ok = ref > 1e-6 * ref[0]
+    assert np.max(np.abs(hist[ok] - ref[ok]) / ref[ok]) <= 1e-10
+
+
+@pytest.mark.parametrize("name,seed", [("disks2d_64", 0), ("spheres3d_24", 0), ("spheres3d_24", 2)])
+def test_decomposition_invariants(name, seed):
+    w = make_workload(name, seed)
+    mask = largest_component(w["mask"])
+    g = MacGrid(mask)
+    dc = decompose(g, w["labels"])
+    # p (primaries' unknowns), c (interface cells), f (faces between interface cells) partition
+    allp = np.concatenate(dc.S)
+    allc = np.concatenate(dc.icells)
+    parts = np.concatenate([allp, allc, dc.f_faces])
+    assert np.array_equal(np.sort(parts), np.arange(g.N))
+    # an f-face has two interface cells; a primary face at least one primary cell
+    from oracle.decomp import cell_faces
+    fc = cell_faces(g)
+    for d in g.comps:
+        for t in (0, 1):
+            f = fc[:, 2 * d + t]
+            ok = f >= 0
+            own = dc.owner[f[ok]]
+            pr = dc.prim[ok]
+            assert np.all((pr < 0) | (own == pr))
+    # every interface touches a primary, every primary's closure is nonsingular
+    X = build_matrix(Operators(g), Phys(1, 1, (1, 0, 0), None, dc.pin), tags=dc.tags)
+    M = G.build(X, dc, origin_rhs(Operators(g), Phys(1, 1, (1, 0, 0), None, dc.pin)))
+    for i, Ab in enumerate(M.Abar):
+        if Ab.shape[0] <= 1500:
+            s = np.linalg.svd(Ab.toarray(), compute_uv=False)
+            assert s[-1] > 1e-10 * s[0]
+    touched = np.zeros(dc.Nc, dtype=bool)
+    for i in range(dc.Np):
+        touched[dc.Cp[i]] = True
+    assert touched.all()
+    # the pin is a primary cell; each dual grid contains its interface
+    assert dc.iface[dc.pin] < 0
+    for j in range(dc.Nc):
+        assert np.all(np.isin(dc.icells[j] - g.nu, dc.dual_cells[j]))
+
+
+def test_slab_carving_puts_interfaces_on_the_higher_label_side():
+    m = channel(24, 5, 1)
+    lab = np.zeros_like(m, dtype=np.int32)
+    for s in range(4):
+        lab[:, :, s * 6:(s + 1) * 6] = s + 1
+    g = MacGrid(m)
+    dc = decompose(g, lab)
+    iface = np.full(m.shape, -1)
+    iface[g.fluid] = dc.iface
+    # label 2 starts at column 6, label 3 at 12, label 4 at 18; label 4 also
+    # touches label 1 across the periodic wrap (column 23)
+    assert set(np.unique(np.nonzero(iface[0] >= 0)[1]).tolist()) == {6, 12, 18, 23}
+    assert [tuple(p) for p in dc.pairs] == [(1, 2), (1, 4), (2, 3), (3, 4)]
