@@ -1,0 +1,211 @@
+/*
+ * gplmm.h -- C ABI of the MI355X gPLMM Newton-Krylov solver.
+ *
+ * The library solves the MAC-staggered incompressible Navier-Stokes equations
+ * on a voxel image of a porous material (Li & Mehmani, "Preconditioning and
+ * Reduced-Order Modeling of Navier-Stokes Equations in Complex Porous
+ * Microstructures"):
+ *   Section 1, the governing equations and the Newton system
+ *     J^k delta^k = -r^k,  J = [F G^T; G O];
+ *   Section 2, the MAC discretisation on the image voxels;
+ *   Sections 3.1-3.2, the two-level monolithic preconditioner
+ *     M^-1 = M_G^-1 + M_dp^-1 (I - A M_G^-1)
+ *   with the PLMM coarse operator M_G (reduction, prolongation, restriction,
+ *   Remark 1) and the dual-primary Schwarz smoother M_dp;
+ *   Section 4, gPLMM: A := J~_w, the Jacobian of the modified residual with
+ *   the inertia linearised about a wind w and removed on faces near the
+ *   contact interfaces;
+ *   Section 7, right-preconditioned (flexible) GMRES with the tolerance
+ *   measured against ||r(u = 0, p = 0)||.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Image arrays are indexed [k][j][i] (z, y, x) with x fastest, nx*ny*nz bytes
+ * or int32 words; nz = 1 means a 2D image.  mask[v] = 1 marks a void (fluid)
+ * voxel.  pore_labels[v] > 0 on every void voxel (the watershed pores).
+ * Only the largest face-connected void component is kept (periodic axes
+ * wrap); every other voxel is treated as grain.
+ *
+ * Unknown layout ("cell records"): the kept fluid cells are numbered
+ * c = 0..ncell-1 in raster order; cell c owns the record
+ *   slots [nrec*c, nrec*c + nrec),  nrec = ndim + 1,
+ * holding the velocity on the LOWER face of the cell along x, y (, z) and then
+ * the pressure.  The lower x-face of cell (k,j,i) lies between cells
+ * (k,j,i-1) and (k,j,i).  A face is an unknown only when both its cells are
+ * kept fluid; the slot of an inactive face is a "void slot" that must hold 0
+ * in every vector passed in, and holds 0 in every vector the library writes.
+ * N = nrec * ncell.  gplmm_get_maps() returns the voxel of each cell.
+ *
+ * Vectors named *_dev are caller-owned device buffers of N doubles on the
+ * context's stream, which the library reads or writes in stream order.  The
+ * library owns every internal buffer (factors, Krylov basis, coarse operator)
+ * and frees them in gplmm_destroy().  Host arrays passed to setup are copied.
+ *
+ * Errors: every call returns 0 on success, a positive value when a solve ran
+ * but missed its tolerance, and a negative GPLMM_E* code on failure; nothing
+ * throws across the ABI.  gplmm_last_error() describes the last failure.  One
+ * context serves one stream; calls on one context must not overlap.
+ */
+#ifndef GPLMM_H
+#define GPLMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gplmm_ctx gplmm_ctx;
+
+enum {
+    GPLMM_OK = 0,
+    GPLMM_E_ARG = -1,        /* bad argument (null pointer, size, label) */
+    GPLMM_E_GEOMETRY = -2,   /* no fluid, or a decomposition that cannot be built */
+    GPLMM_E_HIP = -3,        /* a HIP runtime call failed */
+    GPLMM_E_BREAKDOWN = -4,  /* zero or non-finite pivot in a local factorisation */
+    GPLMM_E_STATE = -5       /* call order (e.g. apply before build) */
+};
+
+enum { GPLMM_FP64 = 0, GPLMM_FP32 = 1 };
+
+/* Wind of the build matrix X = J~_w (Section 4).  The paper uses the velocity
+ * at a nearby state and falls back to the Stokes velocity. */
+enum {
+    GPLMM_WIND_ZERO = 0,     /* w = 0: X is the Stokes (or transient Stokes) matrix, built once */
+    GPLMM_WIND_STOKES = 1,   /* w = 0 for the first Newton step, then rebuilt once with the
+                                velocity after that step (the Stokes solution) */
+    GPLMM_WIND_CALLER = 2    /* w set by gplmm_build(ctx, w_dev) and kept */
+};
+
+typedef struct {
+    int nx, ny, nz;          /* image size; nz = 1 for 2D */
+    double h;                /* voxel edge (default 1) */
+    int periodic[3];         /* per axis x, y, z (default 1, 0, 0) */
+    int precision;           /* GPLMM_FP64 (plain) or GPLMM_FP32: local factorisations, shape
+                                vectors and the preconditioner's inner stencils in FP32 with FP32
+                                accumulation; Newton residual, Arnoldi and coarse solve in FP64 */
+    int wind_mode;           /* GPLMM_WIND_* (default GPLMM_WIND_STOKES) */
+    int tag_layers;          /* faces within this Chebyshev distance of an interface cell carry
+                                no inertia in X (default 1) */
+    int dual_dilations;      /* face-neighbour growths of each interface into its dual grid;
+                                -1 = default (2 in 2D, 0 in 3D) */
+    int restart;             /* FGMRES restart length (default 30, at most 64) */
+    double newton_tol;       /* stop when ||r(x)|| <= newton_tol * ||r(0)|| (default 1e-8) */
+    double lin_tol;          /* FGMRES stops when ||J d + r|| <= lin_tol * ||r(0)|| (default 1e-9) */
+    int newton_maxit;        /* default 30 */
+    int lin_maxit;           /* FGMRES iterations per Newton step (default 600) */
+    int tile;                /* local factor tile edge: 0 = default (32) */
+    int host_only;           /* 1: build the decomposition and index maps on the host only
+                                (no device memory; compute calls return GPLMM_E_STATE) */
+    void* stream;            /* hipStream_t, NULL = default stream */
+} gplmm_options;
+
+typedef struct {
+    int ndim, nrec;
+    int64_t ncell, N;        /* kept fluid cells; vector length */
+    int64_t nface_active;    /* velocity unknowns */
+    int Np, Nc, Ny;          /* primaries, contact interfaces, coarse correction unknowns */
+    int64_t pin;             /* cell whose mass row is replaced by p = 0 */
+    int64_t ndual_cells;     /* cells covered by at least one dual grid */
+    int64_t local_unknowns;  /* sum of the local problem sizes (closure, primary, dual) */
+    int64_t factor_bytes;    /* device bytes held by the local factors */
+    int ncolors;             /* probing colours used to assemble the coarse operator */
+} gplmm_layout;
+
+typedef struct {
+    int newton_its;
+    int lin_its_total;
+    int lin_its[64];         /* FGMRES iterations of each Newton step */
+    double res_hist[65];     /* ||r(x_k)|| / ||r(0)||, k = 0..newton_its */
+    double r0_norm;
+    double t_build_ms;       /* preconditioner builds (local factorisations + coarse) */
+    double t_solve_ms;       /* FGMRES time */
+    double t_total_ms;
+    int builds;
+    int converged;
+} gplmm_stats;
+
+/* Fill *opt with the defaults listed above. */
+void gplmm_default_options(gplmm_options* opt);
+
+/* Build the geometry, the unknown numbering and the pore decomposition
+ * (Section 3.2.1: primary grids, contact interfaces, dual grids; Section 4:
+ * tagged faces) from a host mask and host pore labels, and upload them.
+ * rho, mu: density and viscosity; body[3]: body force per unit mass;
+ * dt > 0 selects one backward-Euler step of that size, dt <= 0 the steady
+ * equations.  On success *out receives a new context.
+ * Errors: GPLMM_E_ARG (null pointers, dims, labels <= 0 on fluid voxels),
+ * GPLMM_E_GEOMETRY (no fluid), GPLMM_E_HIP. */
+int gplmm_setup(const uint8_t* mask, const int32_t* pore_labels, double rho, double mu,
+                const double body[3], double dt, const gplmm_options* opt, gplmm_ctx** out);
+
+/* Sizes of the layout and of the decomposition. */
+int gplmm_layout_info(const gplmm_ctx* ctx, gplmm_layout* out);
+
+/* Host copies of the index maps (arrays sized by gplmm_layout_info):
+ * cell_voxel[ncell]   voxel (raster index) of each kept fluid cell;
+ * cell_iface[ncell]   contact interface of each cell, -1 for primary cells;
+ * cell_prim[ncell]    primary grid of each cell, -1 for interface cells;
+ * face_owner[N]       for velocity slots: owning primary, -1 for f-faces (both cells
+ *                     in interfaces), -2 for void slots; for pressure slots: -3;
+ * face_tag[N]         1 where the velocity slot carries no inertia in X, else 0.
+ * Any pointer may be NULL to skip that map. */
+int gplmm_get_maps(const gplmm_ctx* ctx, int32_t* cell_voxel, int32_t* cell_iface,
+                   int32_t* cell_prim, int32_t* face_owner, int8_t* face_tag);
+
+/* Dual grid membership: dual_ptr[Nc+1], dual_cells[dual_ptr[Nc]] (cells of each dual
+ * grid, ascending).  Call with dual_cells = NULL to get dual_ptr only. */
+int gplmm_get_duals(const gplmm_ctx* ctx, int64_t* dual_ptr, int32_t* dual_cells);
+
+/* r = r(x): the MAC residual of the momentum and mass equations (Section 1;
+ * backward Euler against x_prev when dt > 0, x_prev may be NULL = 0; the pinned
+ * cell's mass row is p = 0).  All pointers are device vectors of N doubles. */
+int gplmm_residual(gplmm_ctx* ctx, const double* x_dev, const double* x_prev_dev, double* r_dev);
+
+/* y = J(xlin) v: the Newton Jacobian of gplmm_residual at xlin, upwind
+ * branches frozen at xlin (Section 1, the Newton system). */
+int gplmm_matvec(gplmm_ctx* ctx, const double* xlin_dev, const double* v_dev, double* y_dev);
+
+/* y = X v with the current build matrix X = J~_w (Section 4). */
+int gplmm_build_matvec(gplmm_ctx* ctx, const double* v_dev, double* y_dev);
+
+/* Build the gPLMM preconditioner from X = J~_w with wind w (device vector, NULL
+ * = zero wind): assemble and factorise every local problem (closure matrices of
+ * the primaries, primary and dual Schwarz blocks), form shape and correction
+ * vectors (Section 3.2.2, prolongation), assemble and invert the coarse operator
+ * Rhat X Phat (Remark 1).  Errors: GPLMM_E_BREAKDOWN, GPLMM_E_HIP. */
+int gplmm_build(gplmm_ctx* ctx, const double* wind_dev);
+
+/* z = M^-1 v (Section 3.1 with Section 3.2.3: coarse correction, then the dual
+ * and the primary additive-Schwarz smoothers).  Requires gplmm_build.  v_dev and
+ * z_dev must not alias. */
+int gplmm_precond_apply(gplmm_ctx* ctx, const double* v_dev, double* z_dev);
+
+/* Newton-FGMRES with gPLMM.  x_dev: in = initial guess, out = solution.
+ * x_prev_dev: previous time level for dt > 0 (NULL = 0).  Builds the
+ * preconditioner as wind_mode asks.  stats may be NULL.  Returns 0 when
+ * ||r|| <= newton_tol ||r(0)||, 1 when the iteration limit was reached. */
+int gplmm_newton_solve(gplmm_ctx* ctx, const double* x_prev_dev, double* x_dev, gplmm_stats* stats);
+
+/* Record HIP events around the preconditioner application, the Jacobian
+ * stencil and the Arnoldi step (on = 1) or stop recording (on = 0). */
+int gplmm_set_timing(gplmm_ctx* ctx, int on);
+
+/* Average device time (ms) of the last k launches of a named kernel group,
+ * recorded with HIP events on the context's stream; used for roofline
+ * reporting.  name: "precond_apply", "trsv", "jv", "xv", "arnoldi".
+ * Returns the number of samples. */
+int gplmm_kernel_time(gplmm_ctx* ctx, const char* name, double* avg_ms, double* bytes);
+
+/* Reset the kernel timers. */
+void gplmm_reset_timers(gplmm_ctx* ctx);
+
+const char* gplmm_last_error(const gplmm_ctx* ctx);
+
+void gplmm_destroy(gplmm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPLMM_H */

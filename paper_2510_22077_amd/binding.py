@@ -1,0 +1,273 @@
+"""ctypes binding of libgplmm.so (the C ABI declared in include/gplmm.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device vectors are torch CUDA tensors (float64, length N, cell-record
+layout); the library works on torch's current stream.  There is no CPU
+fallback: when the library is missing or no GPU is present the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgplmm.so")
+
+GPLMM_FP64, GPLMM_FP32 = 0, 1
+WIND = {"zero": 0, "stokes": 1, "caller": 2}
+ERRORS = {-1: "bad argument", -2: "geometry", -3: "HIP error", -4: "breakdown", -5: "call order"}
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("h", ctypes.c_double), ("periodic", ctypes.c_int * 3),
+                ("precision", ctypes.c_int), ("wind_mode", ctypes.c_int),
+                ("tag_layers", ctypes.c_int), ("dual_dilations", ctypes.c_int),
+                ("restart", ctypes.c_int), ("newton_tol", ctypes.c_double),
+                ("lin_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int),
+                ("lin_maxit", ctypes.c_int), ("tile", ctypes.c_int), ("host_only", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("nrec", ctypes.c_int), ("ncell", ctypes.c_int64),
+                ("N", ctypes.c_int64), ("nface_active", ctypes.c_int64), ("Np", ctypes.c_int),
+                ("Nc", ctypes.c_int), ("Ny", ctypes.c_int), ("pin", ctypes.c_int64),
+                ("ndual_cells", ctypes.c_int64), ("local_unknowns", ctypes.c_int64),
+                ("factor_bytes", ctypes.c_int64), ("ncolors", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int), ("lin_its_total", ctypes.c_int),
+                ("lin_its", ctypes.c_int * 64), ("res_hist", ctypes.c_double * 65),
+                ("r0_norm", ctypes.c_double), ("t_build_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("builds", ctypes.c_int), ("converged", ctypes.c_int)]
+
+    def as_dict(self):
+        n = self.newton_its
+        return dict(newton_its=n, lin_its_total=self.lin_its_total,
+                    lin_its=[self.lin_its[k] for k in range(n)],
+                    res_hist=[self.res_hist[k] for k in range(n + 1)],
+                    r0_norm=self.r0_norm, t_build_ms=self.t_build_ms, t_solve_ms=self.t_solve_ms,
+                    t_total_ms=self.t_total_ms, builds=self.builds, converged=bool(self.converged))
+
+
+EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",
+           "gplmm_get_duals", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
+           "gplmm_precond_apply", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
+           "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy"]
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libgplmm.so is not built; run __graft_entry__.build() or "
+                           "python paper_2510_22077_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, None
+    lib.gplmm_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.gplmm_default_options.restype = V
+    lib.gplmm_setup.argtypes = [P, P, D, D, ctypes.POINTER(ctypes.c_double), D, ctypes.POINTER(Options),
+                                ctypes.POINTER(ctypes.c_void_p)]
+    lib.gplmm_setup.restype = I
+    lib.gplmm_layout_info.argtypes = [P, ctypes.POINTER(Layout)]
+    lib.gplmm_layout_info.restype = I
+    lib.gplmm_get_maps.argtypes = [P, P, P, P, P, P]
+    lib.gplmm_get_maps.restype = I
+    lib.gplmm_get_duals.argtypes = [P, P, P]
+    lib.gplmm_get_duals.restype = I
+    for f in ("gplmm_residual", "gplmm_matvec"):
+        getattr(lib, f).argtypes = [P, P, P, P]
+        getattr(lib, f).restype = I
+    lib.gplmm_build_matvec.argtypes = [P, P, P]
+    lib.gplmm_build_matvec.restype = I
+    lib.gplmm_build.argtypes = [P, P]
+    lib.gplmm_build.restype = I
+    lib.gplmm_precond_apply.argtypes = [P, P, P]
+    lib.gplmm_precond_apply.restype = I
+    lib.gplmm_newton_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
+    lib.gplmm_newton_solve.restype = I
+    lib.gplmm_set_timing.argtypes = [P, I]
+    lib.gplmm_set_timing.restype = I
+    lib.gplmm_kernel_time.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.gplmm_kernel_time.restype = I
+    lib.gplmm_reset_timers.argtypes = [P]
+    lib.gplmm_reset_timers.restype = V
+    lib.gplmm_last_error.argtypes = [P]
+    lib.gplmm_last_error.restype = ctypes.c_char_p
+    lib.gplmm_destroy.argtypes = [P]
+    lib.gplmm_destroy.restype = V
+    _lib = lib
+    return lib
+
+
+class GplmmError(RuntimeError):
+    pass
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Solver:
+    """One gplmm context (one sample, one stream)."""
+
+    def __init__(self, mask, labels, rho=1.0, mu=1.0, body=(1.0, 0.0, 0.0), dt=0.0, h=1.0,
+                 periodic=(1, 0, 0), precision="fp64", wind="stokes", tag_layers=1,
+                 dual_dilations=-1, restart=30, newton_tol=1e-8, lin_tol=1e-9,
+                 newton_maxit=30, lin_maxit=600, host_only=False, stream=None):
+        lib = load()
+        self.lib = lib
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+        if mask.ndim == 2:
+            mask = mask[None]
+            labels = labels[None]
+        if mask.shape != labels.shape:
+            raise ValueError("mask and labels must have the same shape")
+        nz, ny, nx = mask.shape
+        o = Options()
+        lib.gplmm_default_options(ctypes.byref(o))
+        o.nx, o.ny, o.nz = nx, ny, nz
+        o.h = h
+        for k in range(3):
+            o.periodic[k] = int(periodic[k])
+        o.precision = GPLMM_FP32 if precision == "fp32" else GPLMM_FP64
+        o.wind_mode = WIND[wind]
+        o.tag_layers = tag_layers
+        o.dual_dilations = dual_dilations
+        o.restart = restart
+        o.newton_tol = newton_tol
+        o.lin_tol = lin_tol
+        o.newton_maxit = newton_maxit
+        o.lin_maxit = lin_maxit
+        o.host_only = 1 if host_only else 0
+        self.torch = None
+        if not host_only:
+            import torch
+            if not torch.cuda.is_available():
+                raise GplmmError("no GPU: the gPLMM library runs on the device only")
+            self.torch = torch
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            o.stream = ctypes.c_void_p(stream.cuda_stream)
+            self.stream = stream
+        b = (ctypes.c_double * 3)(*[float(v) for v in body])
+        ctx = ctypes.c_void_p()
+        rc = lib.gplmm_setup(mask.ctypes.data, labels.ctypes.data, float(rho), float(mu), b, float(dt),
+                             ctypes.byref(o), ctypes.byref(ctx))
+        self.ctx = ctx
+        if rc != 0:
+            msg = lib.gplmm_last_error(ctx).decode() if ctx.value else ""
+            if ctx.value:
+                lib.gplmm_destroy(ctx)
+                self.ctx = ctypes.c_void_p()
+            raise GplmmError("gplmm_setup failed (%d, %s): %s" % (rc, ERRORS.get(rc, "?"), msg))
+        self.opts = o
+        self.shape = mask.shape
+        L = Layout()
+        lib.gplmm_layout_info(ctx, ctypes.byref(L))
+        self.layout = L
+        self.N = L.N
+
+    # ---- housekeeping
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.gplmm_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise GplmmError("%s failed (%d, %s): %s" % (what, rc, ERRORS.get(rc, "?"),
+                                                         self.lib.gplmm_last_error(self.ctx).decode()))
+        return rc
+
+    def info(self):
+        L = self.layout
+        return {f: getattr(L, f) for f, _ in Layout._fields_}
+
+    def maps(self):
+        L = self.layout
+        out = dict(cell_voxel=np.zeros(L.ncell, np.int32), cell_iface=np.zeros(L.ncell, np.int32),
+                   cell_prim=np.zeros(L.ncell, np.int32), face_owner=np.zeros(L.N, np.int32),
+                   face_tag=np.zeros(L.N, np.int8))
+        self._check(self.lib.gplmm_get_maps(self.ctx, *[a.ctypes.data for a in out.values()]), "get_maps")
+        return out
+
+    def duals(self):
+        ptr = np.zeros(self.layout.Nc + 1, np.int64)
+        self.lib.gplmm_get_duals(self.ctx, ptr.ctypes.data, None)
+        cells = np.zeros(max(int(ptr[-1]), 1), np.int32)
+        self.lib.gplmm_get_duals(self.ctx, ptr.ctypes.data, cells.ctypes.data)
+        return [cells[ptr[j]:ptr[j + 1]].copy() for j in range(self.layout.Nc)]
+
+    # ---- device vectors
+    def zeros(self):
+        return self.torch.zeros(self.N, dtype=self.torch.float64, device="cuda")
+
+    def _vec(self, t):
+        if t is None:
+            return None
+        if not (t.is_cuda and t.dtype == self.torch.float64 and t.is_contiguous() and t.numel() == self.N):
+            raise ValueError("expected a contiguous float64 CUDA tensor of length %d" % self.N)
+        return t
+
+    def residual(self, x, x_prev=None, out=None):
+        out = self.zeros() if out is None else out
+        self._check(self.lib.gplmm_residual(self.ctx, _ptr(self._vec(x)), _ptr(self._vec(x_prev)),
+                                            _ptr(self._vec(out))), "residual")
+        return out
+
+    def matvec(self, xlin, v, out=None):
+        out = self.zeros() if out is None else out
+        self._check(self.lib.gplmm_matvec(self.ctx, _ptr(self._vec(xlin)), _ptr(self._vec(v)),
+                                          _ptr(self._vec(out))), "matvec")
+        return out
+
+    def build_matvec(self, v, out=None):
+        out = self.zeros() if out is None else out
+        self._check(self.lib.gplmm_build_matvec(self.ctx, _ptr(self._vec(v)), _ptr(self._vec(out))),
+                    "build_matvec")
+        return out
+
+    def build(self, wind=None):
+        self._check(self.lib.gplmm_build(self.ctx, _ptr(self._vec(wind))), "build")
+
+    def precond_apply(self, v, out=None):
+        out = self.zeros() if out is None else out
+        self._check(self.lib.gplmm_precond_apply(self.ctx, _ptr(self._vec(v)), _ptr(self._vec(out))),
+                    "precond_apply")
+        return out
+
+    def newton_solve(self, x0=None, x_prev=None):
+        x = self.zeros() if x0 is None else self._vec(x0).clone()
+        st = Stats()
+        rc = self._check(self.lib.gplmm_newton_solve(self.ctx, _ptr(self._vec(x_prev)), _ptr(x),
+                                                     ctypes.byref(st)), "newton_solve")
+        d = st.as_dict()
+        d["rc"] = rc
+        return x, d
+
+    def set_timing(self, on=True):
+        self.lib.gplmm_set_timing(self.ctx, 1 if on else 0)
+
+    def kernel_time(self, name):
+        ms, by = ctypes.c_double(), ctypes.c_double()
+        n = self.lib.gplmm_kernel_time(self.ctx, name.encode(), ctypes.byref(ms), ctypes.byref(by))
+        return dict(samples=n, avg_ms=ms.value, bytes=by.value)
+
+    def reset_timers(self):
+        self.lib.gplmm_reset_timers(self.ctx)

@@ -1,0 +1,598 @@
+// C ABI: context life cycle, device uploads, FGMRES and Newton drivers.
+//
+// Paper: Newton x^{k+1} = x^k + delta^k with J^k delta^k = -r^k (Section 1);
+// right-preconditioned GMRES stopped at ||A x - b|| / ||r(u=0,p=0)|| < tol
+// (Section 7), here in its flexible form so that an FP32 preconditioner can sit
+// inside the FP64 outer iteration; gPLMM built once from J~_w and reused for all
+// Newton iterations, with the Stokes velocity as the fallback wind (Section 4).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace gp {
+void cgs2(gplmm_ctx* c, const double* V, int64_t ldv, int k, double* w, int64_t n, double* hout);
+void lincomb(gplmm_ctx* c, const double* Z, int64_t ldz, int k, const double* y_host, double* x, int64_t n);
+int64_t red_scratch_doubles();
+
+void timer_begin(gplmm_ctx* c, const char* name) {
+    if (!c->timing) return;
+    Timer& t = c->timers[name];
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, c->stream);
+    t.ev0.push_back(e);
+}
+
+void timer_end(gplmm_ctx* c, const char* name, double bytes) {
+    if (!c->timing) return;
+    Timer& t = c->timers[name];
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, c->stream);
+    t.ev1.push_back(e);
+    t.bytes = bytes;
+}
+}  // namespace gp
+
+using namespace gp;
+
+namespace {
+
+template <typename V>
+int upload(gplmm_ctx* c, V** dst, const std::vector<V>& src) {
+    size_t bytes = sizeof(V) * std::max<size_t>(src.size(), 1);
+    GP_HIP(c, hipMalloc((void**)dst, bytes));
+    if (!src.empty()) GP_HIP(c, hipMemcpy(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice));
+    return GPLMM_OK;
+}
+
+#define GP_TRY(x)                    \
+    do {                             \
+        int rc_ = (x);               \
+        if (rc_ != GPLMM_OK) return rc_; \
+    } while (0)
+
+int alloc(gplmm_ctx* c, void** p, size_t bytes) {
+    GP_HIP(c, hipMalloc(p, std::max<size_t>(bytes, 16)));
+    GP_HIP(c, hipMemset(*p, 0, std::max<size_t>(bytes, 16)));
+    return GPLMM_OK;
+}
+
+size_t real_size(const gplmm_ctx* c) { return c->opt.precision == GPLMM_FP32 ? 4 : 8; }
+
+int upload_all(gplmm_ctx* c) {
+    const int64_t nc = c->ncell, N = c->N;
+    const int T = c->tile;
+    // geometry
+    std::vector<uint32_t> coord(nc);
+    for (int64_t q = 0; q < nc; ++q) {
+        int64_t v = c->cell_voxel[q];
+        uint32_t i = (uint32_t)(v % c->nx), j = (uint32_t)((v / c->nx) % c->ny),
+                 k = (uint32_t)(v / ((int64_t)c->nx * c->ny));
+        coord[q] = i | (j << 10) | (k << 20);
+    }
+    GP_TRY(upload(c, &c->d_cidx, c->cidx));
+    GP_TRY(upload(c, &c->d_coord, coord));
+    GP_TRY(upload(c, &c->d_tag, c->tagcell));
+    c->geo = DevGeo{c->nx, c->ny, c->nz, c->ndim, c->nrec, {c->opt.periodic[0], c->opt.periodic[1], c->opt.periodic[2]},
+                    nc, (int)c->pin, c->opt.h, c->d_cidx, c->d_coord, c->d_tag};
+    // local problems
+    const int nsub = c->Np + c->Nc;
+    std::vector<int32_t> row_sub(c->sub_slots.size()), sorted_slot(c->sub_slots.size()), sorted_loc(c->sub_slots.size());
+    std::vector<int64_t> local_off(nsub + 1, 0);
+    for (int s = 0; s < nsub; ++s) {
+        const Sub& sb = c->subs[s];
+        std::vector<std::pair<int32_t, int32_t>> p(sb.n);
+        for (int r = 0; r < sb.n; ++r) {
+            row_sub[sb.slot_off + r] = s;
+            p[r] = {c->sub_slots[sb.slot_off + r], r};
+        }
+        std::sort(p.begin(), p.end());
+        for (int r = 0; r < sb.n; ++r) {
+            sorted_slot[sb.slot_off + r] = p[r].first;
+            sorted_loc[sb.slot_off + r] = p[r].second;
+        }
+        local_off[s + 1] = local_off[s] + (int64_t)sb.nT * T;
+    }
+    std::vector<int32_t> slot_class(N);
+    for (int64_t s = 0; s < N; ++s) {
+        int64_t q = s / c->nrec;
+        int comp = (int)(s % c->nrec);
+        slot_class[s] = comp < c->ndim ? c->owner[s] : (c->prim[q] >= 0 ? c->prim[q] : -4);
+    }
+    std::vector<int32_t> sub_ids(nsub);
+    for (int s = 0; s < nsub; ++s) sub_ids[s] = s;
+    GP_TRY(upload(c, &c->d_subs, c->subs));
+    GP_TRY(upload(c, &c->d_sub_slots, c->sub_slots));
+    GP_TRY(upload(c, &c->d_row_sub, row_sub));
+    GP_TRY(upload(c, &c->d_sorted_slot, sorted_slot));
+    GP_TRY(upload(c, &c->d_sorted_loc, sorted_loc));
+    GP_TRY(upload(c, &c->d_slot_class, slot_class));
+    GP_TRY(upload(c, &c->d_local_off, local_off));
+    GP_TRY(upload(c, &c->d_sub_ids, sub_ids));
+    GP_TRY(upload(c, &c->d_tfc, c->env_tfc));
+    GP_TRY(upload(c, &c->d_tfr, c->env_tfr));
+    GP_TRY(upload(c, &c->d_lrow, c->env_lrow));
+    GP_TRY(upload(c, &c->d_ucol, c->env_ucol));
+    for (int set = 0; set < 2; ++set) {
+        GP_TRY(upload(c, &c->d_step_pairs[set], c->lu_step_pairs[set]));
+        GP_TRY(upload(c, &c->d_sub_list[set], c->lu_sub_list[set]));
+    }
+    c->prim_factor_elems = c->Nc > 0 ? c->subs[c->Np].diag_off : c->factor_elems;
+    c->prim_rows = c->Nc > 0 ? c->subs[c->Np].slot_off : (int64_t)c->sub_slots.size();
+    GP_TRY(alloc(c, &c->d_factor, real_size(c) * c->factor_elems));
+    GP_TRY(alloc(c, &c->d_local, real_size(c) * local_off[nsub]));
+    // shape/correction blocks: column-major with ld = nT * T, right-hand sides built here
+    std::vector<int64_t> phi_off(c->Np + 1, 0);
+    std::vector<int32_t> phi_ncols(std::max(nsub, 1), 0);
+    c->max_phi_cols = 0;
+    for (int i = 0; i < c->Np; ++i) {
+        int nck = (int)c->Cp[i].size() + 1;
+        phi_ncols[i] = nck;
+        c->max_phi_cols = std::max(c->max_phi_cols, nck);
+        phi_off[i + 1] = phi_off[i] + (int64_t)c->subs[i].nT * T * nck;
+    }
+    c->phi_elems = phi_off[c->Np];
+    std::vector<double> rhs(c->phi_elems, 0.0);
+    const double ih = 1.0 / c->opt.h;
+    for (int i = 0; i < c->Np; ++i) {
+        const Sub& sb = c->subs[i];
+        const int ld = sb.nT * T;
+        const int ncp = (int)c->Cp[i].size();
+        for (int r = 0; r < sb.n; ++r) {
+            int64_t s = c->sub_slots[sb.slot_off + r];
+            int64_t q = s / c->nrec;
+            int comp = (int)(s % c->nrec);
+            if (comp >= c->ndim) continue;
+            int64_t L = c->nbr[q * 6 + 2 * comp];
+            int jq = c->iface[q], jl = L >= 0 ? c->iface[L] : -1;
+            for (int k = 0; k < ncp; ++k) {
+                int j = c->Cp[i][k];
+                double g = 0.0;
+                if (jq == j) g -= ih;   // -X[F, p_R] with X[F, p_R] = +1/h
+                if (jl == j) g += ih;   // -X[F, p_L] with X[F, p_L] = -1/h
+                rhs[phi_off[i] + (int64_t)k * ld + r] = g;
+            }
+            rhs[phi_off[i] + (int64_t)ncp * ld + r] = c->phys.rho * c->phys.body[comp];
+        }
+    }
+    if (c->opt.precision == GPLMM_FP32) {
+        std::vector<float> rf(rhs.begin(), rhs.end());
+        GP_TRY(alloc(c, &c->d_phi_rhs, sizeof(float) * rf.size()));
+        if (!rf.empty()) GP_HIP(c, hipMemcpy(c->d_phi_rhs, rf.data(), sizeof(float) * rf.size(), hipMemcpyHostToDevice));
+    } else {
+        GP_TRY(alloc(c, &c->d_phi_rhs, sizeof(double) * rhs.size()));
+        if (!rhs.empty()) GP_HIP(c, hipMemcpy(c->d_phi_rhs, rhs.data(), sizeof(double) * rhs.size(), hipMemcpyHostToDevice));
+    }
+    GP_TRY(alloc(c, &c->d_phi, real_size(c) * c->phi_elems));
+    phi_off.resize(std::max(nsub, 1) + 1, phi_off.back());
+    GP_TRY(upload(c, &c->d_phi_off, phi_off));
+    GP_TRY(upload(c, &c->d_phi_ncols, phi_ncols));
+    GP_TRY(upload(c, &c->d_phi_cols, c->phi_cols));
+    GP_TRY(upload(c, &c->d_phi_cols_off, c->phi_cols_off));
+    // row groups of Rhat: interfaces (their cells' pressures), then corrections (every slot of S_i)
+    std::vector<int64_t> gptr(1, 0);
+    std::vector<int32_t> gslot;
+    for (int j = 0; j < c->Nc; ++j) {
+        for (int32_t q : c->icells[j]) gslot.push_back((int32_t)((int64_t)c->nrec * q + c->ndim));
+        gptr.push_back((int64_t)gslot.size());
+    }
+    for (int i = 0; i < c->Np; ++i) {
+        if (c->ycol[i] < 0) continue;
+        const Sub& sb = c->subs[i];
+        for (int r = 0; r < sb.n; ++r) gslot.push_back(c->sub_slots[sb.slot_off + r]);
+        gptr.push_back((int64_t)gslot.size());
+    }
+    GP_TRY(upload(c, &c->d_grp_ptr, gptr));
+    GP_TRY(upload(c, &c->d_grp_slot, gslot));
+    // dual gather lists: for each slot, the local rows of the dual grids that contain it
+    std::vector<int64_t> dcount(N + 1, 0);
+    for (int s = c->Np; s < nsub; ++s) {
+        const Sub& sb = c->subs[s];
+        for (int r = 0; r < sb.n; ++r) dcount[c->sub_slots[sb.slot_off + r] + 1]++;
+    }
+    for (int64_t s = 0; s < N; ++s) dcount[s + 1] += dcount[s];
+    std::vector<int64_t> dsrc(dcount[N]);
+    std::vector<int64_t> fillp(dcount.begin(), dcount.end() - 1);
+    for (int s = c->Np; s < nsub; ++s) {   // ascending dual id, so each slot's order is fixed
+        const Sub& sb = c->subs[s];
+        for (int r = 0; r < sb.n; ++r) dsrc[fillp[c->sub_slots[sb.slot_off + r]]++] = local_off[s] + r;
+    }
+    GP_TRY(upload(c, &c->d_dinv_ptr, dcount));
+    GP_TRY(upload(c, &c->d_dinv, dsrc));
+    // probing
+    GP_TRY(upload(c, &c->d_probe, c->probe));
+    GP_TRY(upload(c, &c->d_color_cols, c->color_cols));
+    const int nco = c->nco;
+    GP_TRY(alloc(c, (void**)&c->d_Ao, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_Aowork, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_piv, sizeof(int32_t) * std::max(nco, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_cv, sizeof(double) * 2 * std::max(nco, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_flag, sizeof(int) * 4));
+    // vectors
+    const int m = c->opt.restart;
+    GP_TRY(alloc(c, (void**)&c->d_wind, sizeof(double) * N));
+    if (c->opt.precision == GPLMM_FP32) GP_TRY(alloc(c, (void**)&c->d_wind_f, sizeof(float) * N));
+    GP_TRY(alloc(c, (void**)&c->d_r, sizeof(double) * N));
+    GP_TRY(alloc(c, (void**)&c->d_tmp, sizeof(double) * N));
+    GP_TRY(alloc(c, (void**)&c->d_dx, sizeof(double) * N));
+    GP_TRY(alloc(c, (void**)&c->d_zero, sizeof(double) * N));
+    GP_TRY(alloc(c, (void**)&c->d_V, sizeof(double) * (int64_t)(m + 1) * N));
+    GP_TRY(alloc(c, (void**)&c->d_Z, sizeof(double) * (int64_t)m * N));
+    GP_TRY(alloc(c, (void**)&c->d_red, sizeof(double) * red_scratch_doubles()));
+    GP_HIP(c, hipHostMalloc((void**)&c->h_red, sizeof(double) * 4 * (kMaxRestart + 2), hipHostMallocDefault));
+    GP_TRY(alloc(c, &c->d_pv, real_size(c) * 6 * N));
+    return GPLMM_OK;
+}
+
+int do_build(gplmm_ctx* c) {
+    auto t0 = std::chrono::steady_clock::now();
+    int rc;
+    if (c->opt.precision == GPLMM_FP32) {
+        convert<double, float>(c, c->d_wind, c->d_wind_f, c->N);
+        rc = build_precond<float>(c);
+    } else {
+        rc = build_precond<double>(c);
+    }
+    c->last_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int do_apply(gplmm_ctx* c, const double* v, double* z) {
+    timer_begin(c, "precond_apply");
+    int rc = c->opt.precision == GPLMM_FP32 ? apply_precond<float>(c, v, z) : apply_precond<double>(c, v, z);
+    timer_end(c, "precond_apply", c->apply_bytes);
+    return rc;
+}
+
+// FGMRES(m) for J(xk) d = b, d = 0 initially; |residual| <= tol_abs.  Returns iterations.
+int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double tol_abs, int maxit, bool* ok) {
+    const int64_t N = c->N;
+    const int m = c->opt.restart;
+    double* V = c->d_V;
+    double* Z = c->d_Z;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 2);
+    hipMemsetAsync(d, 0, sizeof(double) * N, c->stream);
+    hipMemcpyAsync(V, b, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream);
+    double beta = nrm2(c, V, N);
+    int total = 0;
+    *ok = beta <= tol_abs;
+    while (!*ok && total < maxit) {
+        scal_copy(c, 1.0 / beta, V, V, N);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool stop = false;
+        for (int j = 0; j < m && total < maxit; ++j) {
+            double* vj = V + (int64_t)j * N;
+            double* zj = Z + (int64_t)j * N;
+            double* w = V + (int64_t)(j + 1) * N;
+            int rc = do_apply(c, vj, zj);
+            if (rc) return -1;
+            timer_begin(c, "jv");
+            launch_jv(c, xk, zj, w, c->stream);
+            timer_end(c, "jv", c->jv_bytes);
+            timer_begin(c, "arnoldi");
+            cgs2(c, V, N, j + 1, w, N, hcol.data());
+            timer_end(c, "arnoldi", 0.0);
+            double hn = hcol[j + 1];
+            for (int i = 0; i <= j; ++i) H[i * m + j] = hcol[i];
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0.0) scal_copy(c, 1.0 / hn, w, w, N);
+            for (int i = 0; i < j; ++i) {
+                double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = H[j * m + j] / den;
+            sn[j] = H[(j + 1) * m + j] / den;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= tol_abs || hn == 0.0) {
+                stop = true;
+                break;
+            }
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < k; ++l) s -= H[i * m + l] * y[l];
+            y[i] = s / H[i * m + i];
+        }
+        lincomb(c, Z, N, k, y.data(), d, N);
+        if (stop) {
+            *ok = true;
+            break;
+        }
+        // restart from the true residual b - J d
+        launch_jv(c, xk, d, c->d_tmp, c->stream);
+        scal_copy(c, -1.0, c->d_tmp, V, N);
+        axpy(c, 1.0, b, V, N);
+        beta = nrm2(c, V, N);
+        if (beta <= tol_abs) *ok = true;
+    }
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gplmm_default_options(gplmm_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->nx = o->ny = 0;
+    o->nz = 1;
+    o->h = 1.0;
+    o->periodic[0] = 1;
+    o->precision = GPLMM_FP64;
+    o->wind_mode = GPLMM_WIND_STOKES;
+    o->tag_layers = 1;
+    o->dual_dilations = -1;
+    o->restart = 30;
+    o->newton_tol = 1e-8;
+    o->lin_tol = 1e-9;
+    o->newton_maxit = 30;
+    o->lin_maxit = 600;
+    o->tile = 0;
+    o->stream = nullptr;
+}
+
+int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double mu, const double body[3], double dt,
+                const gplmm_options* opt, gplmm_ctx** out) {
+    if (!mask || !labels || !opt || !out || !body) return GPLMM_E_ARG;
+    *out = nullptr;
+    gplmm_ctx* c = new gplmm_ctx();
+    c->opt = *opt;
+    if (c->opt.restart <= 0) c->opt.restart = 30;
+    if (c->opt.tile == 0) c->opt.tile = 32;
+    auto bad = [&](const char* m) {
+        c->err = m;
+        *out = c;
+        return GPLMM_E_ARG;
+    };
+    if (c->opt.restart > kMaxRestart) return bad("restart must be <= 64");
+    if (c->opt.tile != 32) return bad("only tile = 32 is supported");
+    if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return bad("image dimensions must be positive");
+    if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024) return bad("image dimensions must be <= 1024");
+    if (!(rho > 0) || !(mu > 0) || !(opt->h > 0)) return bad("rho, mu and h must be positive");
+    c->tile = 32;
+    c->nx = opt->nx;
+    c->ny = opt->ny;
+    c->nz = opt->nz;
+    c->ndim = opt->nz == 1 ? 2 : 3;
+    c->nrec = c->ndim + 1;
+    c->nvox = (int64_t)c->nx * c->ny * c->nz;
+    c->phys = Phys{rho, mu, {body[0], body[1], c->ndim == 3 ? body[2] : 0.0}, dt > 0 ? dt : 0.0};
+    c->stream = (hipStream_t)opt->stream;
+    int rc = build_decomposition(c, mask, labels);
+    if (rc == GPLMM_OK) rc = build_local_problems(c);
+    if (rc == GPLMM_OK) rc = build_probing(c);
+    if (rc == GPLMM_OK && !c->opt.host_only) rc = upload_all(c);
+    if (rc == GPLMM_OK && !c->opt.host_only) {
+        // algorithmic bytes of one preconditioner application (for roofline reporting):
+        // every local factor read once, the shape vectors once, the coarse inverse once,
+        // and about 16 vector passes over N slots
+        const double rs = (double)real_size(c);
+        c->apply_bytes = rs * (double)c->factor_elems + rs * (double)c->phi_elems +
+                         8.0 * (double)c->nco * c->nco + 16.0 * rs * (double)c->N;
+        c->jv_bytes = 8.0 * 3.0 * (double)c->N + 4.0 * (double)c->nvox;
+        c->ready = true;
+    }
+    *out = c;
+    return rc;
+}
+
+int gplmm_layout_info(const gplmm_ctx* c, gplmm_layout* o) {
+    if (!c || !o) return GPLMM_E_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->ndim = c->ndim;
+    o->nrec = c->nrec;
+    o->ncell = c->ncell;
+    o->N = c->N;
+    o->nface_active = c->nface;
+    o->Np = c->Np;
+    o->Nc = c->Nc;
+    o->Ny = c->Ny;
+    o->pin = c->pin;
+    std::vector<uint8_t> cov(c->ncell, 0);
+    for (auto& d : c->dual_cells)
+        for (int32_t q : d) cov[q] = 1;
+    o->ndual_cells = std::count(cov.begin(), cov.end(), 1);
+    int64_t lu = 0;
+    for (int i = 0; i < c->Np; ++i) lu += 2 * (int64_t)c->subs[i].n;
+    for (int j = 0; j < c->Nc; ++j) lu += c->subs[c->Np + j].n;
+    o->local_unknowns = lu;
+    o->factor_bytes = (int64_t)(c->opt.precision == GPLMM_FP32 ? 4 : 8) * c->factor_elems;
+    o->ncolors = c->ncolors;
+    return GPLMM_OK;
+}
+
+int gplmm_get_maps(const gplmm_ctx* c, int32_t* cell_voxel, int32_t* cell_iface, int32_t* cell_prim,
+                   int32_t* face_owner, int8_t* face_tag) {
+    if (!c) return GPLMM_E_ARG;
+    if (cell_voxel) std::copy(c->cell_voxel.begin(), c->cell_voxel.end(), cell_voxel);
+    if (cell_iface) std::copy(c->iface.begin(), c->iface.end(), cell_iface);
+    if (cell_prim) std::copy(c->prim.begin(), c->prim.end(), cell_prim);
+    if (face_owner) std::copy(c->owner.begin(), c->owner.end(), face_owner);
+    if (face_tag) std::copy(c->tagslot.begin(), c->tagslot.end(), face_tag);
+    return GPLMM_OK;
+}
+
+int gplmm_get_duals(const gplmm_ctx* c, int64_t* ptr, int32_t* cells) {
+    if (!c || !ptr) return GPLMM_E_ARG;
+    ptr[0] = 0;
+    for (int j = 0; j < c->Nc; ++j) {
+        ptr[j + 1] = ptr[j] + (int64_t)c->dual_cells[j].size();
+        if (cells) std::copy(c->dual_cells[j].begin(), c->dual_cells[j].end(), cells + ptr[j]);
+    }
+    return GPLMM_OK;
+}
+
+int gplmm_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!x || !r) return GPLMM_E_ARG;
+    launch_residual(c, x, xprev, r, c->stream);
+    GP_HIP(c, hipGetLastError());
+    return GPLMM_OK;
+}
+
+int gplmm_matvec(gplmm_ctx* c, const double* xlin, const double* v, double* y) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!xlin || !v || !y) return GPLMM_E_ARG;
+    launch_jv(c, xlin, v, y, c->stream);
+    GP_HIP(c, hipGetLastError());
+    return GPLMM_OK;
+}
+
+int gplmm_build_matvec(gplmm_ctx* c, const double* v, double* y) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!v || !y) return GPLMM_E_ARG;
+    launch_xv<double>(c, v, y, nullptr, c->stream);
+    GP_HIP(c, hipGetLastError());
+    return GPLMM_OK;
+}
+
+int gplmm_build(gplmm_ctx* c, const double* wind) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (wind) GP_HIP(c, hipMemcpyAsync(c->d_wind, wind, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
+    else GP_HIP(c, hipMemsetAsync(c->d_wind, 0, sizeof(double) * c->N, c->stream));
+    int rc = do_build(c);
+    if (rc == GPLMM_OK) GP_HIP(c, hipGetLastError());
+    return rc;
+}
+
+int gplmm_precond_apply(gplmm_ctx* c, const double* v, double* z) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!v || !z || v == z) return GPLMM_E_ARG;
+    if (!c->built) return fail(c, GPLMM_E_STATE, "gplmm_build must precede gplmm_precond_apply");
+    int rc = do_apply(c, v, z);
+    if (rc == GPLMM_OK) GP_HIP(c, hipGetLastError());
+    return rc;
+}
+
+int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats* st) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!x) return GPLMM_E_ARG;
+    gplmm_stats loc;
+    gplmm_stats* S = st ? st : &loc;
+    std::memset(S, 0, sizeof(*S));
+    auto T0 = std::chrono::steady_clock::now();
+    const int64_t N = c->N;
+    // ||r(0)||: the residual at the origin (previous time level also zero)
+    launch_residual(c, c->d_zero, c->d_zero, c->d_r, c->stream);
+    const double r0 = nrm2(c, c->d_r, N);
+    S->r0_norm = r0;
+    if (!(r0 > 0)) return fail(c, GPLMM_E_ARG, "the residual at the origin is zero (no driving force)");
+    const int mode = c->opt.wind_mode;
+    if (mode != GPLMM_WIND_CALLER || !c->built) {
+        if (mode != GPLMM_WIND_CALLER) hipMemsetAsync(c->d_wind, 0, sizeof(double) * N, c->stream);
+        int rc = do_build(c);
+        S->t_build_ms += c->last_build_ms;
+        S->builds++;
+        if (rc) return rc;
+    }
+    launch_residual(c, x, xprev, c->d_r, c->stream);
+    double rn = nrm2(c, c->d_r, N);
+    S->res_hist[0] = rn / r0;
+    int rcode = 1;
+    for (int k = 0; k < c->opt.newton_maxit && k < 64; ++k) {
+        if (rn <= c->opt.newton_tol * r0) {
+            rcode = 0;
+            break;
+        }
+        if (k == 1 && mode == GPLMM_WIND_STOKES) {
+            hipMemcpyAsync(c->d_wind, x, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream);
+            int rc = do_build(c);
+            S->t_build_ms += c->last_build_ms;
+            S->builds++;
+            if (rc) return rc;
+        }
+        scal_copy(c, -1.0, c->d_r, c->d_r, N);   // b = -r (fgmres leaves d_r alone)
+        auto t1 = std::chrono::steady_clock::now();
+        bool ok = false;
+        int its = fgmres(c, x, c->d_r, c->d_dx, c->opt.lin_tol * r0, c->opt.lin_maxit, &ok);
+        if (its < 0) return GPLMM_E_HIP;
+        S->t_solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+        S->lin_its[k] = its;
+        S->lin_its_total += its;
+        axpy(c, 1.0, c->d_dx, x, N);
+        S->newton_its = k + 1;
+        launch_residual(c, x, xprev, c->d_r, c->stream);
+        rn = nrm2(c, c->d_r, N);
+        S->res_hist[k + 1] = rn / r0;
+    }
+    if (rn <= c->opt.newton_tol * r0) rcode = 0;
+    S->converged = rcode == 0;
+    GP_HIP(c, hipStreamSynchronize(c->stream));
+    GP_HIP(c, hipGetLastError());
+    S->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
+    return rcode;
+}
+
+int gplmm_set_timing(gplmm_ctx* c, int on) {
+    if (!c) return GPLMM_E_ARG;
+    c->timing = on != 0;
+    return GPLMM_OK;
+}
+
+int gplmm_kernel_time(gplmm_ctx* c, const char* name, double* avg_ms, double* bytes) {
+    if (!c || !name) return GPLMM_E_ARG;
+    auto it = c->timers.find(name);
+    if (it == c->timers.end()) return 0;
+    hipStreamSynchronize(c->stream);
+    Timer& t = it->second;
+    size_t n = std::min(t.ev0.size(), t.ev1.size());
+    double sum = 0.0;
+    for (size_t k = 0; k < n; ++k) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t.ev0[k], t.ev1[k]);
+        sum += ms;
+    }
+    if (avg_ms) *avg_ms = n ? sum / n : 0.0;
+    if (bytes) *bytes = t.bytes;
+    return (int)n;
+}
+
+void gplmm_reset_timers(gplmm_ctx* c) {
+    if (!c) return;
+    for (auto& kv : c->timers) {
+        for (auto e : kv.second.ev0) hipEventDestroy(e);
+        for (auto e : kv.second.ev1) hipEventDestroy(e);
+    }
+    c->timers.clear();
+}
+
+const char* gplmm_last_error(const gplmm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void gplmm_destroy(gplmm_ctx* c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    gplmm_reset_timers(c);
+    void* ptrs[] = {c->d_cidx, c->d_coord, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
+                    c->d_ucol, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
+                    c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
+                    c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
+                    c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_wind_f, c->d_r, c->d_tmp,
+                    c->d_dx, c->d_zero, c->d_V, c->d_Z, c->d_red, c->d_pv, c->d_local, c->d_cv, c->d_row_sub,
+                    c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    if (c->h_red) hipHostFree(c->h_red);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Internal state of a gplmm context: host decomposition, device buffers and
+// the launch helpers shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gplmm.h"
+
+namespace gp {
+
+constexpr int kMaxRestart = 64;
+
+// Geometry as the device kernels see it.
+struct DevGeo {
+    int nx, ny, nz, ndim, nrec;
+    int per[3];
+    int64_t ncell;
+    int pin;                 // pinned cell
+    double h;
+    const int32_t* cidx;     // voxel -> cell or -1 (nx*ny*nz)
+    const uint32_t* coord;   // cell -> i | j << 10 | k << 20
+    const uint8_t* tag;      // cell -> bit a: lower a-face carries no inertia in X
+};
+
+struct Phys {
+    double rho, mu, body[3], dt;   // dt <= 0: steady
+};
+
+// One local problem (primary closure / primary block / dual block).
+struct Sub {
+    int kind;                // 0 primary (closure and Schwarz block), 1 dual
+    int id;                  // primary or interface id
+    int n;                   // local unknowns
+    int nT;                  // tiles per side
+    int64_t slot_off;        // into sub_slots
+    int64_t env_off;         // into env arrays (tfc, tfr, lrow, ucol), nT entries each
+    int64_t diag_off;        // element offset of the first diagonal tile in the factor buffer
+};
+
+// Coarse probing: one colour = set of coarse columns whose restricted images do not overlap.
+struct ProbeEntry {
+    int32_t row, col;
+};
+
+struct Timer {
+    std::vector<hipEvent_t> ev0, ev1;
+    double bytes = 0.0;      // algorithmic bytes per launch
+};
+
+}  // namespace gp
+
+struct gplmm_ctx {
+    gplmm_options opt;
+    gp::Phys phys;
+    int ndim = 2, nrec = 3;
+    int nx = 0, ny = 0, nz = 0;
+    int64_t nvox = 0, ncell = 0, N = 0, nface = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // ---- host decomposition
+    std::vector<int32_t> cidx;        // voxel -> cell
+    std::vector<int32_t> cell_voxel;  // cell -> voxel
+    std::vector<int32_t> nbr;         // cell * 6 + 2*d + (s>0) -> cell or -1
+    std::vector<int32_t> iface, prim; // per cell
+    std::vector<int32_t> owner;       // per slot (see gplmm_get_maps)
+    std::vector<int8_t> tagslot;      // per slot
+    std::vector<uint8_t> tagcell;     // per cell bits
+    int Np = 0, Nc = 0, Ny = 0;
+    int64_t pin = 0;
+    std::vector<std::vector<int32_t>> Cp;          // interfaces of each primary
+    std::vector<std::vector<int32_t>> icells;      // cells of each interface
+    std::vector<std::vector<int32_t>> dual_cells;  // cells of each dual grid
+    std::vector<int32_t> ycol;        // primary -> coarse y column (or -1)
+
+    // ---- local problems
+    int tile = 32;
+    std::vector<gp::Sub> subs;        // [0, Np): primaries, [Np, Np + Nc): duals
+    std::vector<int32_t> sub_slots;   // global slot of each local unknown, local order
+    std::vector<int32_t> env_tfc, env_tfr;   // per tile row/col: first tile col/row of L/U
+    std::vector<int64_t> env_lrow, env_ucol; // element offsets of L tile-row / U tile-col starts
+    int64_t factor_elems = 0;
+    int maxT = 0;
+    // LU schedule: per step K, (sub, I) pairs for the row-update kernel
+    std::vector<int64_t> lu_step_off[2];     // [set][K], set 0 = primaries, 1 = primaries + duals
+    std::vector<int32_t> lu_step_pairs[2];
+    std::vector<int64_t> lu_sub_off[2];
+    std::vector<int32_t> lu_sub_list[2];
+
+    // ---- shape vectors
+    std::vector<int64_t> phi_off;     // per primary: element offset of its |S| x (|Cp|+1) block
+    int64_t phi_elems = 0;
+    std::vector<int32_t> phi_cols;    // per primary: coarse column of each shape column (concat)
+    std::vector<int64_t> phi_cols_off;
+
+    // ---- coarse operator probing
+    int ncolors = 0;
+    std::vector<int64_t> color_off;   // entries of colour c: [color_off[c], color_off[c+1])
+    std::vector<gp::ProbeEntry> probe;
+    std::vector<int64_t> color_col_off;
+    std::vector<int32_t> color_cols;
+    int nco = 0;                      // coarse size Nc + Ny
+
+    // ---- device buffers
+    gp::DevGeo geo{};
+    int32_t* d_cidx = nullptr;
+    uint32_t* d_coord = nullptr;
+    uint8_t* d_tag = nullptr;
+    int32_t* d_sub_slots = nullptr;      // local order, concatenated over subs
+    int32_t* d_row_sub = nullptr;        // sub of each concatenated row
+    int32_t* d_sorted_slot = nullptr;    // per sub: its slots ascending ...
+    int32_t* d_sorted_loc = nullptr;     // ... and their local indices
+    int32_t* d_slot_class = nullptr;     // per slot: owner primary, -1 f-face, -2 void, -4 interface cell
+    int64_t* d_local_off = nullptr;      // per sub: offset of its padded local vector
+    int32_t* d_sub_ids = nullptr;        // 0 .. Np+Nc-1
+    gp::Sub* d_subs = nullptr;
+    int32_t* d_tfc = nullptr;
+    int32_t* d_tfr = nullptr;
+    int64_t* d_lrow = nullptr;
+    int64_t* d_ucol = nullptr;
+    int32_t* d_step_pairs[2] = {nullptr, nullptr};
+    int32_t* d_sub_list[2] = {nullptr, nullptr};
+    void* d_factor = nullptr;            // real (float or double) tiles
+    int64_t prim_factor_elems = 0;       // primaries' tiles come first
+    int64_t prim_rows = 0;               // primaries' rows come first in the slot lists
+    void* d_phi = nullptr;               // real shape/correction vectors (column-major, ld = nT*T)
+    void* d_phi_rhs = nullptr;           // their right-hand sides
+    int max_phi_cols = 0;
+    int64_t* d_phi_off = nullptr;
+    int32_t* d_phi_ncols = nullptr;
+    int32_t* d_phi_cols = nullptr;
+    int64_t* d_phi_cols_off = nullptr;
+    int64_t* d_grp_ptr = nullptr;        // Rhat row groups: interfaces, then corrections
+    int32_t* d_grp_slot = nullptr;
+    int64_t* d_dinv_ptr = nullptr;       // per slot: local rows of the dual grids holding it
+    int64_t* d_dinv = nullptr;
+    double* d_Ao = nullptr;              // coarse operator, then its inverse (nco x nco, row-major)
+    double* d_Aowork = nullptr;
+    int32_t* d_piv = nullptr;
+    gp::ProbeEntry* d_probe = nullptr;
+    int32_t* d_color_cols = nullptr;
+    int* d_flag = nullptr;               // breakdown flags
+
+    // work vectors (FP64 unless noted)
+    double* d_wind = nullptr;            // N
+    float* d_wind_f = nullptr;           // N (FP32 builds)
+    double* d_r = nullptr;
+    double* d_tmp = nullptr;
+    double* d_dx = nullptr;
+    double* d_zero = nullptr;
+    double* d_V = nullptr;               // (m+1) x N
+    double* d_Z = nullptr;               // m x N
+    double* d_red = nullptr;             // reduction scratch
+    double* h_red = nullptr;             // pinned host mirror
+    void* d_pv = nullptr;                // preconditioner vectors (real): 6 x N
+    void* d_local = nullptr;             // local solutions (real)
+    double* d_cv = nullptr;              // coarse vectors (2 x nco)
+    bool ready = false;
+    bool built = false;
+    int builds = 0;
+    double last_build_ms = 0.0;
+    bool timing = false;
+    double apply_bytes = 0.0, jv_bytes = 0.0;
+
+    std::map<std::string, gp::Timer> timers;
+};
+
+namespace gp {
+
+int fail(gplmm_ctx* c, int code, const std::string& msg);
+#define GP_HIP(ctx, call)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return gp::fail(ctx, GPLMM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// setup.cpp
+int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels);
+int build_local_problems(gplmm_ctx* c);
+int build_probing(gplmm_ctx* c);
+
+// stencil.hip
+void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s);
+void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s);
+template <typename T>
+void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s);
+void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s);
+
+// krylov.hip
+double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n);
+double nrm2(gplmm_ctx* c, const double* a, int64_t n);
+void axpy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n);
+void scal_copy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n);
+template <typename A, typename B>
+void convert(gplmm_ctx* c, const A* x, B* y, int64_t n);
+
+// precond.hip
+template <typename T>
+int build_precond(gplmm_ctx* c);
+template <typename T>
+int apply_precond(gplmm_ctx* c, const double* v, double* z);
+
+// coarse.hip
+int coarse_invert(gplmm_ctx* c);
+
+// timing (api.cpp)
+void timer_begin(gplmm_ctx* c, const char* name);
+void timer_end(gplmm_ctx* c, const char* name, double bytes);
+
+}  // namespace gp

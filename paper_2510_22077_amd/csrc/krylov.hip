@@ -1,0 +1,166 @@
+// Vector kernels for FGMRES: multi-vector dot products and updates for
+// classical Gram-Schmidt (applied twice), norms, linear combinations and
+// precision casts.  Reductions are two-pass with a fixed block count, so
+// results do not depend on scheduling (bitwise reproducible run to run).
+#include "internal.h"
+
+namespace gp {
+
+namespace {
+
+constexpr int kRedBlocks = 1024;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    // wavefront (64 lanes) shuffle reduction, then across the block's waves in LDS
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+    __syncthreads();
+    return s;
+}
+
+// partial[j * nblk + b] = sum over block b's rows of V_j . w
+__global__ void multidot_kernel(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ w,
+                                int64_t n, double* __restrict__ partial) {
+    __shared__ double sh[16];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    for (int j = 0; j < k; ++j) {
+        const double* v = V + (int64_t)j * ldv;
+        double acc = 0.0;
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) acc += v[r] * w[r];
+        double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// out[j] = sum_b partial[j * nblk + b]   (one block per j)
+__global__ void reduce_kernel(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+    __shared__ double sh[16];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partial[(int64_t)j * nblk + b];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[j] = s;
+}
+
+// w -= sum_j V_j h_j ; optionally partial sums of w_new^2
+__global__ void update_kernel(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ hcoef,
+                              double* __restrict__ w, int64_t n, double* __restrict__ partial_nrm) {
+    __shared__ double sh[16];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    double acc = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        double x = w[r];
+        for (int j = 0; j < k; ++j) x -= V[(int64_t)j * ldv + r] * hcoef[j];
+        w[r] = x;
+        acc += x * x;
+    }
+    if (partial_nrm) {
+        double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial_nrm[blockIdx.x] = s;
+    }
+}
+
+__global__ void axpy_kernel(double alpha, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += alpha * x[i];
+}
+
+__global__ void scal_copy_kernel(double alpha, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = alpha * x[i];
+}
+
+// x += sum_j Z_j y_j
+__global__ void lincomb_kernel(const double* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ y,
+                               double* __restrict__ x, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = x[i];
+    for (int j = 0; j < k; ++j) s += Z[(int64_t)j * ldz + i] * y[j];
+    x[i] = s;
+}
+
+template <typename A, typename B>
+__global__ void convert_kernel(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (B)x[i];
+}
+
+inline unsigned nb_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+// Device scratch layout in c->d_red: [0, kRedBlocks*(kMaxRestart+1)) partials, then results.
+static double* partials(gplmm_ctx* c) { return c->d_red; }
+static double* results(gplmm_ctx* c) { return c->d_red + (int64_t)kRedBlocks * (kMaxRestart + 2); }
+
+double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n) {
+    multidot_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(a, 0, 1, b, n, partials(c));
+    reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, results(c));
+    hipMemcpyAsync(c->h_red, results(c), sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    return c->h_red[0];
+}
+
+double nrm2(gplmm_ctx* c, const double* a, int64_t n) { return std::sqrt(std::max(0.0, dot(c, a, a, n))); }
+
+void axpy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n) {
+    axpy_kernel<<<nb_for(n), kThreads, 0, c->stream>>>(alpha, x, y, n);
+}
+
+void scal_copy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n) {
+    scal_copy_kernel<<<nb_for(n), kThreads, 0, c->stream>>>(alpha, x, y, n);
+}
+
+// h = V[0..k)^T w into device results(c)[0..k) (no host sync)
+static void multi_dot_dev(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* w, int64_t n,
+                          double* out_dev) {
+    multidot_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, w, n, partials(c));
+    reduce_kernel<<<k, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, out_dev);
+}
+
+// One CGS2 step: w <- w - V h1 - V h2 with h1 = V^T w, h2 = V^T (w - V h1); returns
+// h = h1 + h2 (k values) and ||w_new|| in hout[k] (host).
+void cgs2(gplmm_ctx* c, const double* V, int64_t ldv, int k, double* w, int64_t n, double* hout) {
+    double* r = results(c);
+    double* h1 = r;
+    double* h2 = r + (kMaxRestart + 2);
+    double* nr = r + 2 * (kMaxRestart + 2);
+    multi_dot_dev(c, V, ldv, k, w, n, h1);
+    update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h1, w, n, nullptr);
+    multi_dot_dev(c, V, ldv, k, w, n, h2);
+    update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h2, w, n, partials(c));
+    reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, nr);
+    hipMemcpyAsync(c->h_red, r, sizeof(double) * 3 * (kMaxRestart + 2), hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    for (int j = 0; j < k; ++j) hout[j] = c->h_red[j] + c->h_red[(kMaxRestart + 2) + j];
+    hout[k] = std::sqrt(std::max(0.0, c->h_red[2 * (kMaxRestart + 2)]));
+}
+
+void lincomb(gplmm_ctx* c, const double* Z, int64_t ldz, int k, const double* y_host, double* x, int64_t n) {
+    double* yd = results(c) + 3 * (kMaxRestart + 2);
+    hipMemcpyAsync(yd, y_host, sizeof(double) * k, hipMemcpyHostToDevice, c->stream);
+    lincomb_kernel<<<nb_for(n), kThreads, 0, c->stream>>>(Z, ldz, k, yd, x, n);
+    hipStreamSynchronize(c->stream);
+}
+
+template <typename A, typename B>
+void convert(gplmm_ctx* c, const A* x, B* y, int64_t n) {
+    convert_kernel<A, B><<<nb_for(n), kThreads, 0, c->stream>>>(x, y, n);
+}
+
+template void convert<double, float>(gplmm_ctx*, const double*, float*, int64_t);
+template void convert<float, double>(gplmm_ctx*, const float*, double*, int64_t);
+template void convert<double, double>(gplmm_ctx*, const double*, double*, int64_t);
+
+int64_t red_scratch_doubles() { return (int64_t)kRedBlocks * (kMaxRestart + 2) + 4 * (kMaxRestart + 2) + 64; }
+
+}  // namespace gp

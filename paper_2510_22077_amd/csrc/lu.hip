@@ -1,0 +1,346 @@
+// Batched local problems of the preconditioner: assembly, no-pivot LU and
+// triangular solves on a tile skyline.
+//
+// Paper: the closure matrices Abar_i of the primaries (Section 3.2.2, the two
+// reduction steps) and the additive-Schwarz blocks of the primary and dual
+// grids (Section 3.2.3) are factorised once and reused for every right-hand
+// side (the paper pre-factorises its local systems with LU).
+//
+// Layout: each local matrix (n x n, unknowns in the pressure-after-faces
+// raster order) is cut into T x T tiles.  Lower tiles (I, J), J < I, exist for
+// J >= tfc[I] and are stored tile-row by tile-row; upper tiles (I, J), I < J,
+// exist for I >= tfr[J] and are stored tile-column by tile-column; tfc and tfr
+// are non-decreasing, so fill-in of an LU without pivoting stays inside (the
+// envelope property).  Tiles are row-major.  Pivoting is not needed in this
+// order: every pressure follows all of its faces, so each leading block is a
+// saddle-point matrix with a positive-real velocity block and a full-rank
+// divergence block.
+#include "internal.h"
+#include "stencil_dev.h"
+
+namespace gp {
+
+constexpr int kT = 32;
+constexpr int kTT = kT * kT;
+
+struct Env {
+    const Sub* subs;
+    const int32_t* tfc;
+    const int32_t* tfr;
+    const int64_t* lrow;
+    const int64_t* ucol;
+};
+
+template <typename T>
+__device__ __forceinline__ T* tile_ptr(T* F, const Env& e, const Sub& sb, int I, int J) {
+    if (I == J) return F + sb.diag_off + (int64_t)I * kTT;
+    if (J < I) return F + e.lrow[sb.env_off + I] + (int64_t)(J - e.tfc[sb.env_off + I]) * kTT;
+    return F + e.ucol[sb.env_off + J] + (int64_t)(I - e.tfr[sb.env_off + J]) * kTT;
+}
+
+// ---------------------------------------------------------------------------------------
+// Assembly: one thread per local row; rows of X = J~_w gathered through the slot lists.
+// closure != 0 (primaries only): entries in columns of f-faces or of other primaries'
+// unknowns are added to the diagonal (Section 3.2.2, both reduction steps).
+// ---------------------------------------------------------------------------------------
+template <typename T, typename W>
+__global__ void assemble_kernel(DevGeo g, Phys ph, const W* __restrict__ wind, Env e, T* __restrict__ F,
+                                const int32_t* __restrict__ row_sub, const int32_t* __restrict__ slots,
+                                const int32_t* __restrict__ sorted_slot, const int32_t* __restrict__ sorted_loc,
+                                const int32_t* __restrict__ slot_class, int64_t nrows, int first_sub, int nsub,
+                                int closure) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows) return;
+    const int s = row_sub[t];
+    if (s < first_sub || s >= first_sub + nsub) return;
+    const Sub sb = e.subs[s];
+    const int r = (int)(t - sb.slot_off);
+    const int64_t gs = slots[t];
+    const int64_t c = gs / g.nrec;
+    const int comp = (int)(gs % g.nrec);
+    Nbhd nb;
+    load_nbhd(g, c, nb);
+    int64_t cols[kMaxRow];
+    double vals[kMaxRow];
+    const int cnt = x_row(g, ph, nb, c, comp, wind, cols, vals);
+    double diag_extra = 0.0;
+    const int32_t* ss = sorted_slot + sb.slot_off;
+    const int32_t* sl = sorted_loc + sb.slot_off;
+    for (int k = 0; k < cnt; ++k) {
+        const int32_t col = (int32_t)cols[k];
+        int lo = 0, hi = sb.n;  // binary search in the sub's sorted slots
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (ss[mid] < col) lo = mid + 1; else hi = mid;
+        }
+        if (lo < sb.n && ss[lo] == col) {
+            const int lc = sl[lo];
+            T* tp = tile_ptr(F, e, sb, r / kT, lc / kT);
+            tp[(r % kT) * kT + (lc % kT)] += (T)vals[k];
+        } else if (closure) {
+            const int32_t cls = slot_class[col];
+            if (cls == -1 || (cls >= 0 && cls != sb.id)) diag_extra += vals[k];
+        }
+    }
+    if (diag_extra != 0.0) {
+        T* tp = tile_ptr(F, e, sb, r / kT, r / kT);
+        tp[(r % kT) * kT + (r % kT)] += (T)diag_extra;
+    }
+}
+
+// Identity on the padding rows of the last diagonal tile.
+template <typename T>
+__global__ void pad_kernel(Env e, T* F, int first_sub, int nsub) {
+    int s = first_sub + blockIdx.x;
+    if (s >= first_sub + nsub) return;
+    const Sub sb = e.subs[s];
+    const int I = sb.nT - 1;
+    T* tp = F + sb.diag_off + (int64_t)I * kTT;
+    for (int r = sb.n - I * kT + threadIdx.x; r < kT; r += blockDim.x) tp[r * kT + r] = (T)1;
+}
+
+// ---------------------------------------------------------------------------------------
+// LU step K, part 1 (one block per active subdomain): factor the diagonal tile and
+// form the U panel U_KJ = L_KK^-1 A_KJ.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, const int32_t* __restrict__ list,
+                                                      int K, int* __restrict__ flag) {
+    __shared__ T D[kT][kT + 1];
+    __shared__ T B[kT][kT + 1];
+    const Sub sb = e.subs[list[blockIdx.x]];
+    const int tid = threadIdx.x;
+    T* dp = F + sb.diag_off + (int64_t)K * kTT;
+    for (int x = tid; x < kTT; x += blockDim.x) D[x / kT][x % kT] = dp[x];
+    __syncthreads();
+    for (int k = 0; k < kT; ++k) {
+        const T piv = D[k][k];
+        if (tid == 0 && (!(piv == piv) || piv == (T)0 || fabs((double)piv) > 1e300)) atomicOr(flag, 1);
+        if (tid > k && tid < kT) D[tid][k] = D[tid][k] / piv;
+        __syncthreads();
+        for (int x = tid; x < kTT; x += blockDim.x) {
+            int i = x / kT, j = x % kT;
+            if (i > k && j > k) D[i][j] -= D[i][k] * D[k][j];
+        }
+        __syncthreads();
+    }
+    for (int x = tid; x < kTT; x += blockDim.x) dp[x] = D[x / kT][x % kT];
+    const int32_t* tfr = e.tfr + sb.env_off;
+    for (int J = K + 1; J < sb.nT && tfr[J] <= K; ++J) {
+        T* up = tile_ptr(F, e, sb, K, J);
+        __syncthreads();
+        for (int x = tid; x < kTT; x += blockDim.x) B[x / kT][x % kT] = up[x];
+        __syncthreads();
+        for (int k = 0; k < kT - 1; ++k) {   // unit lower forward substitution, all columns at once
+            for (int x = tid; x < kTT; x += blockDim.x) {
+                int i = x / kT, j = x % kT;
+                if (i > k) B[i][j] -= D[i][k] * B[k][j];
+            }
+            __syncthreads();
+        }
+        for (int x = tid; x < kTT; x += blockDim.x) up[x] = B[x / kT][x % kT];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// LU step K, part 2 (one block per (subdomain, tile row I > K)): L_IK = A_IK U_KK^-1,
+// then A_IJ -= L_IK U_KJ for every J > K in the envelope.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) lu_row_kernel(Env e, T* __restrict__ F, const int32_t* __restrict__ pairs,
+                                                     int K) {
+    __shared__ T U[kT][kT + 1];
+    __shared__ T Lt[kT][kT + 1];
+    __shared__ T Bt[kT][kT + 1];
+    const Sub sb = e.subs[pairs[2 * blockIdx.x]];
+    const int I = pairs[2 * blockIdx.x + 1];
+    const int tid = threadIdx.x;
+    const T* dp = F + sb.diag_off + (int64_t)K * kTT;
+    T* lp = tile_ptr(F, e, sb, I, K);
+    for (int x = tid; x < kTT; x += blockDim.x) {
+        U[x / kT][x % kT] = dp[x];
+        Lt[x / kT][x % kT] = lp[x];
+    }
+    __syncthreads();
+    // X U = A, column by column (U upper with its diagonal)
+    for (int k = 0; k < kT; ++k) {
+        if (tid < kT) Lt[tid][k] = Lt[tid][k] / U[k][k];
+        __syncthreads();
+        for (int x = tid; x < kTT; x += blockDim.x) {
+            int i = x / kT, j = x % kT;
+            if (j > k) Lt[i][j] -= Lt[i][k] * U[k][j];
+        }
+        __syncthreads();
+    }
+    for (int x = tid; x < kTT; x += blockDim.x) lp[x] = Lt[x / kT][x % kT];
+    const int32_t* tfr = e.tfr + sb.env_off;
+    for (int J = K + 1; J < sb.nT && tfr[J] <= K; ++J) {
+        const T* up = tile_ptr(F, e, sb, K, J);
+        T* ap = tile_ptr(F, e, sb, I, J);
+        __syncthreads();
+        for (int x = tid; x < kTT; x += blockDim.x) Bt[x / kT][x % kT] = up[x];
+        __syncthreads();
+        for (int x = tid; x < kTT; x += blockDim.x) {
+            int i = x / kT, j = x % kT;
+            T acc = 0;
+#pragma unroll 8
+            for (int m = 0; m < kT; ++m) acc += Lt[i][m] * Bt[m][j];
+            ap[x] -= acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Triangular solves, one block (256 threads) per (subdomain, right-hand side).
+// mode 0: b gathered from a global vector through the slot list, x to `out` + local_off[s];
+// mode 1: in place on column `col` of a column-major block (ld = nT*T) at `out` + off[s].
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum8(T v) {
+    v += __shfl_down(v, 4, 8);
+    v += __shfl_down(v, 2, 8);
+    v += __shfl_down(v, 1, 8);
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) trsv_kernel(Env e, const T* __restrict__ F, const int32_t* __restrict__ sub_ids,
+                                                   const int32_t* __restrict__ slots, const T* __restrict__ vin,
+                                                   T* __restrict__ out, const int64_t* __restrict__ off,
+                                                   const int32_t* __restrict__ ncols, int mode) {
+    __shared__ T yt[kT];
+    __shared__ T part[kT];
+    const int s = sub_ids[blockIdx.x];
+    const Sub sb = e.subs[s];
+    const int col = blockIdx.y;
+    if (mode == 1 && col >= ncols[s]) return;
+    const int tid = threadIdx.x;
+    const int ld = sb.nT * kT;
+    T* x = out + off[s] + (mode == 1 ? (int64_t)col * ld : 0);
+    const int32_t* sl = slots + sb.slot_off;
+    const int32_t* tfc = e.tfc + sb.env_off;
+    const int32_t* tfr = e.tfr + sb.env_off;
+    const int r = tid >> 3, q = tid & 7;      // row within a tile, 4-column chunk
+    // forward: L y = b (unit lower), L stored by tile rows
+    for (int I = 0; I < sb.nT; ++I) {
+        T acc = 0;
+        for (int J = tfc[I]; J < I; ++J) {
+            const T* lt = tile_ptr(const_cast<T*>(F), e, sb, I, J);
+            const T* yj = x + J * kT;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc += lt[r * kT + q * 4 + m] * yj[q * 4 + m];
+        }
+        acc = wave_sum8(acc);
+        if (q == 0) {
+            int gr = I * kT + r;
+            T b;
+            if (mode == 0) b = gr < sb.n ? vin[sl[gr]] : (T)0;
+            else b = x[gr];
+            part[r] = b - acc;
+        }
+        __syncthreads();
+        if (tid < 64) {   // one wave: forward substitution inside the diagonal tile
+            const T* dt = F + sb.diag_off + (int64_t)I * kTT;
+            T v = tid < kT ? part[tid] : (T)0;
+            for (int k = 0; k < kT; ++k) {
+                T yk = __shfl(v, k, 64);
+                if (tid > k && tid < kT) v -= dt[tid * kT + k] * yk;
+            }
+            if (tid < kT) x[I * kT + tid] = v;
+        }
+        __syncthreads();
+    }
+    // backward: U x = y, U stored by tile columns
+    for (int J = sb.nT - 1; J >= 0; --J) {
+        if (tid < 64) {
+            const T* dt = F + sb.diag_off + (int64_t)J * kTT;
+            T v = tid < kT ? x[J * kT + tid] : (T)0;
+            for (int k = kT - 1; k >= 0; --k) {
+                T xk = __shfl(v, k, 64) / dt[k * kT + k];
+                if (tid == k) v = xk;
+                if (tid < k) v -= dt[tid * kT + k] * xk;
+            }
+            if (tid < kT) {
+                x[J * kT + tid] = v;
+                yt[tid] = v;
+            }
+        }
+        __syncthreads();
+        for (int I = tfr[J]; I < J; ++I) {
+            const T* ut = tile_ptr(const_cast<T*>(F), e, sb, I, J);
+            T acc = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc += ut[r * kT + q * 4 + m] * yt[q * 4 + m];
+            acc = wave_sum8(acc);
+            if (q == 0) x[I * kT + r] -= acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host drivers
+// ---------------------------------------------------------------------------------------
+static Env make_env(gplmm_ctx* c) { return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow, c->d_ucol}; }
+
+template <typename T>
+int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure) {
+    Env e = make_env(c);
+    T* F = (T*)c->d_factor;
+    const int64_t nrows = (int64_t)c->sub_slots.size();
+    const unsigned nb = (unsigned)((nrows + 255) / 256);
+    if (c->opt.precision == GPLMM_FP32 && c->d_wind_f)
+        assemble_kernel<T, float><<<nb, 256, 0, c->stream>>>(c->geo, c->phys, c->d_wind_f, e, F, c->d_row_sub,
+                                                             c->d_sub_slots, c->d_sorted_slot, c->d_sorted_loc,
+                                                             c->d_slot_class, nrows, first_sub, nsub, closure ? 1 : 0);
+    else
+        assemble_kernel<T, double><<<nb, 256, 0, c->stream>>>(c->geo, c->phys, c->d_wind, e, F, c->d_row_sub,
+                                                              c->d_sub_slots, c->d_sorted_slot, c->d_sorted_loc,
+                                                              c->d_slot_class, nrows, first_sub, nsub, closure ? 1 : 0);
+    if (nsub > 0) pad_kernel<T><<<nsub, 64, 0, c->stream>>>(e, F, first_sub, nsub);
+    return GPLMM_OK;
+}
+
+template <typename T>
+int factor_set(gplmm_ctx* c, int set) {
+    Env e = make_env(c);
+    T* F = (T*)c->d_factor;
+    const auto& soff = c->lu_sub_off[set];
+    const auto& poff = c->lu_step_off[set];
+    for (int K = 0; K + 1 < (int)soff.size(); ++K) {
+        int ns = (int)(soff[K + 1] - soff[K]);
+        if (ns == 0) break;
+        lu_diag_kernel<T><<<ns, 256, 0, c->stream>>>(e, F, c->d_sub_list[set] + soff[K], K, c->d_flag);
+        int np = (int)(poff[K + 1] - poff[K]);
+        if (np > 0) lu_row_kernel<T><<<np, 256, 0, c->stream>>>(e, F, c->d_step_pairs[set] + 2 * poff[K], K);
+    }
+    return GPLMM_OK;
+}
+
+template <typename T>
+void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vin, T* out_local) {
+    if (nsub <= 0) return;
+    Env e = make_env(c);
+    trsv_kernel<T><<<dim3(nsub, 1), 256, 0, c->stream>>>(e, (const T*)c->d_factor, sub_ids_dev, c->d_sub_slots, vin,
+                                                        out_local, c->d_local_off, nullptr, 0);
+}
+
+template <typename T>
+void trsv_phi(gplmm_ctx* c, int maxcols) {
+    if (c->Np <= 0 || maxcols <= 0) return;
+    Env e = make_env(c);
+    trsv_kernel<T><<<dim3(c->Np, maxcols), 256, 0, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_ids,
+                                                               c->d_sub_slots, nullptr, (T*)c->d_phi, c->d_phi_off,
+                                                               c->d_phi_ncols, 1);
+}
+
+template int assemble_subs<float>(gplmm_ctx*, int, int, bool);
+template int assemble_subs<double>(gplmm_ctx*, int, int, bool);
+template int factor_set<float>(gplmm_ctx*, int);
+template int factor_set<double>(gplmm_ctx*, int);
+template void trsv_gather<float>(gplmm_ctx*, const int32_t*, int, const float*, float*);
+template void trsv_gather<double>(gplmm_ctx*, const int32_t*, int, const double*, double*);
+template void trsv_phi<float>(gplmm_ctx*, int);
+template void trsv_phi<double>(gplmm_ctx*, int);
+
+}  // namespace gp

@@ -1,0 +1,269 @@
+// gPLMM build and apply on the device.
+//
+// Paper: M^-1 = M_G^-1 + M_L^-1 (I - A M_G^-1) with M_L = M_dp (Section 3.1);
+// M_dp^-1 = M_d^-1 + M_p^-1 (I - A M_d^-1) (Section 3.2.3); the compact
+// coarse form M_G^-1 = Phat (Rhat A Phat)^-1 Rhat with A itself in place of the
+// column-summed operator (Section 3.2.2, Remark 1); A = X = J~_w for gPLMM
+// (Section 4).  Phat puts the shape vectors phi_ij and correction vectors chi_i
+// on each primary, the coarse pressure on each interface's cells and zero on
+// the f-faces; Rhat sums over each interface's cells and over every row of
+// each primary.
+//
+// The coarse operator Rhat X Phat is assembled by probing: the columns of one
+// colour have restricted images on disjoint coarse rows, so one prolongation,
+// one stencil application and one restriction of the colour's indicator give
+// all of their entries.
+#include "internal.h"
+
+namespace gp {
+
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+    __syncthreads();
+    return s;
+}
+
+// coarse[g] = sum of v over the slots of row group g (interfaces: their cells' pressures;
+// correction unknowns: every slot of the primary).
+template <typename V>
+__global__ void restrict_kernel(const V* __restrict__ v, const int64_t* __restrict__ gptr,
+                                const int32_t* __restrict__ gslot, double* __restrict__ out) {
+    __shared__ double sh[16];
+    const int g = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t t = gptr[g] + threadIdx.x; t < gptr[g + 1]; t += blockDim.x) acc += (double)v[gslot[t]];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[g] = s;
+}
+
+// z on the primaries' slots: sum_k phi_k coef[col_k]; one block per primary.
+template <typename T, typename O>
+__global__ void prolong_prim_kernel(const T* __restrict__ phi, const int64_t* __restrict__ phi_off,
+                                    const int64_t* __restrict__ pcol_off, const int32_t* __restrict__ pcols,
+                                    const Sub* __restrict__ subs, const int32_t* __restrict__ slots,
+                                    const double* __restrict__ coef, O* __restrict__ z, int kT) {
+    const int i = blockIdx.x;
+    const Sub sb = subs[i];
+    const int ld = sb.nT * kT;
+    const int64_t c0 = pcol_off[i], c1 = pcol_off[i + 1];
+    const T* ph = phi + phi_off[i];
+    for (int r = threadIdx.x; r < sb.n; r += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t k = c0; k < c1; ++k) {
+            int32_t col = pcols[k];
+            if (col < 0) continue;
+            double a = coef[col];
+            if (a != 0.0) acc += a * (double)ph[(k - c0) * ld + r];
+        }
+        z[slots[sb.slot_off + r]] = (O)acc;
+    }
+}
+
+// z on interface cells' pressures: the coarse pressure of their interface.
+template <typename O>
+__global__ void prolong_iface_kernel(const int64_t* __restrict__ gptr, const int32_t* __restrict__ gslot, int Nc,
+                                     const double* __restrict__ coef, O* __restrict__ z) {
+    const int j = blockIdx.x;
+    if (j >= Nc) return;
+    for (int64_t t = gptr[j] + threadIdx.x; t < gptr[j + 1]; t += blockDim.x) z[gslot[t]] = (O)coef[j];
+}
+
+// Ao[row, col] = t[row] for the colour's (row, col) entries.
+__global__ void probe_scatter_kernel(const ProbeEntry* __restrict__ ent, int64_t n, const double* __restrict__ t,
+                                     double* __restrict__ Ao, int nco) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    ProbeEntry p = ent[k];
+    Ao[(int64_t)p.row * nco + p.col] = t[p.row];
+}
+
+__global__ void set_ones_kernel(const int32_t* __restrict__ cols, int64_t n, double* __restrict__ e, double val) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) e[cols[k]] = val;
+}
+
+// zp[slot] = local solution (primaries are disjoint)
+template <typename T>
+__global__ void scatter_prim_kernel(const int32_t* __restrict__ slots, const int32_t* __restrict__ row_sub,
+                                    const Sub* __restrict__ subs, const int64_t* __restrict__ local_off,
+                                    const T* __restrict__ loc, T* __restrict__ z, int64_t nrows_prim) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows_prim) return;
+    const int s = row_sub[t];
+    const int r = (int)(t - subs[s].slot_off);
+    z[slots[t]] = loc[local_off[s] + r];
+}
+
+// zd[slot] = sum over the dual grids containing the slot, in a fixed order
+template <typename T>
+__global__ void gather_dual_kernel(const int64_t* __restrict__ ptr, const int64_t* __restrict__ src,
+                                   const T* __restrict__ loc, T* __restrict__ z, int64_t N) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    T acc = 0;
+    for (int64_t k = ptr[s]; k < ptr[s + 1]; ++k) acc += loc[src[k]];
+    z[s] = acc;
+}
+
+template <typename T>
+__global__ void combine_kernel(const T* __restrict__ a, const T* __restrict__ b, const T* __restrict__ c,
+                               double* __restrict__ z, int64_t N) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < N) z[s] = (double)a[s] + (double)b[s] + (double)c[s];
+}
+
+// y = A x for the dense coarse inverse (row-major), one block per row
+__global__ void gemv_kernel(const double* __restrict__ A, const double* __restrict__ x, double* __restrict__ y,
+                            int n) {
+    __shared__ double sh[16];
+    const int i = blockIdx.x;
+    const double* a = A + (int64_t)i * n;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) acc += a[j] * x[j];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) y[i] = s;
+}
+
+inline unsigned nb(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+}  // namespace
+
+template <typename T>
+void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vin, T* out_local);
+template <typename T>
+void trsv_phi(gplmm_ctx* c, int maxcols);
+template <typename T>
+int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure);
+template <typename T>
+int factor_set(gplmm_ctx* c, int set);
+
+template <typename T>
+static T* pvec(gplmm_ctx* c, int k) {
+    return (T*)c->d_pv + (int64_t)k * c->N;
+}
+
+// Phat coef (FP64 coarse vector) -> z (type O)
+template <typename T, typename O>
+static void prolong(gplmm_ctx* c, const double* coef, O* z) {
+    hipMemsetAsync(z, 0, sizeof(O) * c->N, c->stream);
+    if (c->Np > 0)
+        prolong_prim_kernel<T, O><<<c->Np, kB, 0, c->stream>>>((const T*)c->d_phi, c->d_phi_off, c->d_phi_cols_off,
+                                                              c->d_phi_cols, c->d_subs, c->d_sub_slots, coef, z,
+                                                              c->tile);
+    if (c->Nc > 0)
+        prolong_iface_kernel<O><<<c->Nc, 64, 0, c->stream>>>(c->d_grp_ptr, c->d_grp_slot, c->Nc, coef, z);
+}
+
+template <typename V>
+static void restrict_(gplmm_ctx* c, const V* v, double* out) {
+    if (c->nco > 0) restrict_kernel<V><<<c->nco, kB, 0, c->stream>>>(v, c->d_grp_ptr, c->d_grp_slot, out);
+}
+
+template <typename T>
+int build_precond(gplmm_ctx* c) {
+    hipStream_t s = c->stream;
+    T* F = (T*)c->d_factor;
+    GP_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+    // 1. closure matrices of the primaries and the dual blocks, factorised together
+    GP_HIP(c, hipMemsetAsync(F, 0, sizeof(T) * c->factor_elems, s));
+    assemble_subs<T>(c, 0, c->Np, true);
+    assemble_subs<T>(c, c->Np, c->Nc, false);
+    factor_set<T>(c, 1);
+    // 2. shape and correction vectors: Abar_i^-1 [g_i1 .. g_im, b_B]
+    GP_HIP(c, hipMemcpyAsync(c->d_phi, c->d_phi_rhs, sizeof(T) * c->phi_elems, hipMemcpyDeviceToDevice, s));
+    trsv_phi<T>(c, c->max_phi_cols);
+    // 3. primary Schwarz blocks X[S_i, S_i] replace the closure factors
+    GP_HIP(c, hipMemsetAsync(F, 0, sizeof(T) * c->prim_factor_elems, s));
+    assemble_subs<T>(c, 0, c->Np, false);
+    factor_set<T>(c, 0);
+    int flag = 0;
+    GP_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(c, hipStreamSynchronize(s));
+    if (flag) return fail(c, GPLMM_E_BREAKDOWN, "zero or non-finite pivot in a local factorisation");
+    // 4. coarse operator Rhat X Phat by probing, in FP64
+    const int nco = c->nco;
+    if (nco > 0) {
+        GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * (int64_t)nco * nco, s));
+        double* e = c->d_cv;
+        double* tco = c->d_cv + nco;
+        double* pv = c->d_r;     // FP64 scratch vectors
+        double* xv = c->d_tmp;
+        for (int k = 0; k < c->ncolors; ++k) {
+            int64_t c0 = c->color_col_off[k], c1 = c->color_col_off[k + 1];
+            GP_HIP(c, hipMemsetAsync(e, 0, sizeof(double) * nco, s));
+            set_ones_kernel<<<nb(c1 - c0), kB, 0, s>>>(c->d_color_cols + c0, c1 - c0, e, 1.0);
+            prolong<T, double>(c, e, pv);
+            launch_xv<double>(c, pv, xv, nullptr, s);
+            restrict_<double>(c, xv, tco);
+            int64_t p0 = c->color_off[k], p1 = c->color_off[k + 1];
+            probe_scatter_kernel<<<nb(p1 - p0), kB, 0, s>>>(c->d_probe + p0, p1 - p0, tco, c->d_Ao, nco);
+        }
+        int rc = coarse_invert(c);
+        if (rc != GPLMM_OK) return rc;
+    }
+    GP_HIP(c, hipStreamSynchronize(s));
+    c->built = true;
+    c->builds++;
+    return GPLMM_OK;
+}
+
+template <typename T>
+int apply_precond(gplmm_ctx* c, const double* v, double* z) {
+    hipStream_t s = c->stream;
+    const int64_t N = c->N;
+    T* zG = pvec<T>(c, 0);
+    T* vt = pvec<T>(c, 1);
+    T* r1 = pvec<T>(c, 2);
+    T* zd = pvec<T>(c, 3);
+    T* r2 = pvec<T>(c, 4);
+    T* zp = pvec<T>(c, 5);
+    T* loc = (T*)c->d_local;
+    // coarse correction z_G = Phat Ao^-1 Rhat v
+    if (c->nco > 0) {
+        restrict_<double>(c, v, c->d_cv);
+        gemv_kernel<<<c->nco, kB, 0, s>>>(c->d_Ao, c->d_cv, c->d_cv + c->nco, c->nco);
+        prolong<T, T>(c, c->d_cv + c->nco, zG);
+    } else {
+        hipMemsetAsync(zG, 0, sizeof(T) * N, s);
+    }
+    const T* vin;
+    if constexpr (sizeof(T) == sizeof(double)) {
+        vin = (const T*)v;
+    } else {
+        convert<double, T>(c, v, vt, N);
+        vin = vt;
+    }
+    // r1 = v - X z_G ; z_d = M_d^-1 r1 (overlapping duals, deterministic gather-sum)
+    launch_xv<T>(c, zG, r1, vin, s);
+    if (c->Nc > 0) {
+        trsv_gather<T>(c, c->d_sub_ids + c->Np, c->Nc, r1, loc);
+        gather_dual_kernel<T><<<nb(N), kB, 0, s>>>(c->d_dinv_ptr, c->d_dinv, loc, zd, N);
+    } else {
+        hipMemsetAsync(zd, 0, sizeof(T) * N, s);
+    }
+    // r2 = r1 - X z_d ; z_p = M_p^-1 r2 (disjoint primaries)
+    launch_xv<T>(c, zd, r2, r1, s);
+    hipMemsetAsync(zp, 0, sizeof(T) * N, s);
+    trsv_gather<T>(c, c->d_sub_ids, c->Np, r2, loc);
+    scatter_prim_kernel<T><<<nb(c->prim_rows), kB, 0, s>>>(c->d_sub_slots, c->d_row_sub, c->d_subs, c->d_local_off,
+                                                           loc, zp, c->prim_rows);
+    combine_kernel<T><<<nb(N), kB, 0, s>>>(zG, zd, zp, z, N);
+    return GPLMM_OK;
+}
+
+template int build_precond<float>(gplmm_ctx*);
+template int build_precond<double>(gplmm_ctx*);
+template int apply_precond<float>(gplmm_ctx*, const double*, double*);
+template int apply_precond<double>(gplmm_ctx*, const double*, double*);
+
+}  // namespace gp

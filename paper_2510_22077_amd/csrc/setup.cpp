@@ -1,0 +1,648 @@
+// Host setup: fluid cells, pore decomposition, local problems, probing colours.
+//
+// Paper, Section 3.2.1 (primary grids, contact interfaces, dual grids) and the
+// permutation paragraph of Section 3.2.2 (a face with a flanking cell in a
+// primary belongs to it; a face flanked by neither belongs to the interface).
+// The rules that turn pore labels into interfaces (carving on the higher-label
+// side, the admissibility merge, the merge of interfaces that touch no
+// primary, the pin, tags and dual growth) are this library's reading of the
+// paper, stated where each step is implemented.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <queue>
+
+#include "internal.h"
+
+namespace gp {
+
+int fail(gplmm_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+namespace {
+
+struct UF {
+    std::vector<int64_t> p;
+    explicit UF(int64_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+    int64_t find(int64_t a) {
+        while (p[a] != a) {
+            p[a] = p[p[a]];
+            a = p[a];
+        }
+        return a;
+    }
+    void unite(int64_t a, int64_t b) {
+        a = find(a);
+        b = find(b);
+        if (a != b) p[std::max(a, b)] = std::min(a, b);
+    }
+};
+
+inline int64_t slot(const gplmm_ctx* c, int64_t cell, int comp) { return (int64_t)c->nrec * cell + comp; }
+
+}  // namespace
+
+// Voxel neighbour (with periodic wrap) or -1 outside the image.
+static inline int64_t vox_nb(const gplmm_ctx* c, int64_t v, int d, int s) {
+    int64_t i = v % c->nx, j = (v / c->nx) % c->ny, k = v / ((int64_t)c->nx * c->ny);
+    int64_t q[3] = {i, j, k};
+    int64_t n[3] = {c->nx, c->ny, c->nz};
+    q[d] += s;
+    if (q[d] < 0 || q[d] >= n[d]) {
+        if (!c->opt.periodic[d]) return -1;
+        q[d] = (q[d] + n[d]) % n[d];
+    }
+    return (q[2] * c->ny + q[1]) * c->nx + q[0];
+}
+
+int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels) {
+    const int64_t nvox = c->nvox;
+    const int nd = c->ndim;
+    // ---- largest face-connected fluid component (periodic axes wrap); ties: earliest first voxel
+    std::vector<int32_t> comp(nvox, -1);
+    std::vector<int64_t> comp_size;
+    {
+        std::vector<int64_t> stack;
+        for (int64_t v = 0; v < nvox; ++v) {
+            if (!mask[v] || comp[v] >= 0) continue;
+            int32_t id = (int32_t)comp_size.size();
+            int64_t cnt = 0;
+            comp[v] = id;
+            stack.push_back(v);
+            while (!stack.empty()) {
+                int64_t u = stack.back();
+                stack.pop_back();
+                ++cnt;
+                for (int d = 0; d < nd; ++d)
+                    for (int s = -1; s <= 1; s += 2) {
+                        int64_t w = vox_nb(c, u, d, s);
+                        if (w >= 0 && mask[w] && comp[w] < 0) {
+                            comp[w] = id;
+                            stack.push_back(w);
+                        }
+                    }
+            }
+            comp_size.push_back(cnt);
+        }
+    }
+    if (comp_size.empty()) return fail(c, GPLMM_E_GEOMETRY, "the image has no fluid voxel");
+    int32_t keep = (int32_t)(std::max_element(comp_size.begin(), comp_size.end()) - comp_size.begin());
+    c->cidx.assign(nvox, -1);
+    c->cell_voxel.clear();
+    for (int64_t v = 0; v < nvox; ++v)
+        if (comp[v] == keep) {
+            c->cidx[v] = (int32_t)c->cell_voxel.size();
+            c->cell_voxel.push_back((int32_t)v);
+        }
+    const int64_t nc = (int64_t)c->cell_voxel.size();
+    c->ncell = nc;
+    c->N = (int64_t)c->nrec * nc;
+    // ---- cell neighbours through active faces
+    c->nbr.assign(nc * 6, -1);
+    for (int64_t q = 0; q < nc; ++q)
+        for (int d = 0; d < nd; ++d)
+            for (int t = 0; t < 2; ++t) {
+                int64_t w = vox_nb(c, c->cell_voxel[q], d, t ? 1 : -1);
+                c->nbr[q * 6 + 2 * d + t] = w >= 0 ? c->cidx[w] : -1;
+            }
+    auto NB = [&](int64_t q, int d, int t) -> int64_t { return q < 0 ? -1 : c->nbr[q * 6 + 2 * d + t]; };
+    // ---- labels
+    std::vector<int64_t> L(nc);
+    for (int64_t q = 0; q < nc; ++q) {
+        L[q] = labels[c->cell_voxel[q]];
+        if (L[q] <= 0) return fail(c, GPLMM_E_ARG, "a fluid voxel has a non-positive pore label");
+    }
+    std::vector<uint8_t> is_if(nc);
+    std::vector<int64_t> minlow(nc);
+    auto carve = [&]() {
+        for (int64_t q = 0; q < nc; ++q) {
+            int64_t m = INT64_MAX;
+            for (int e = 0; e < 2 * nd; ++e) {
+                int64_t w = c->nbr[q * 6 + e];
+                if (w >= 0 && L[w] > 0 && L[w] < L[q]) m = std::min(m, L[w]);
+            }
+            is_if[q] = m != INT64_MAX;
+            minlow[q] = m;
+        }
+    };
+    // an a-face "at" cell q is its lower a-face; active iff the lower neighbour is fluid
+    auto face_active = [&](int64_t q, int a) { return q >= 0 && NB(q, a, 0) >= 0; };
+    // ---- carving repeated until every primary is admissible: every group of a primary's
+    // same-axis faces linked through the viscous stencil must reach a non-active face position
+    for (int round = 0;; ++round) {
+        carve();
+        std::vector<int64_t> bad;
+        for (int a = 0; a < nd; ++a) {
+            std::vector<int64_t> lab(nc, 0);
+            for (int64_t q = 0; q < nc; ++q) {
+                if (!face_active(q, a)) continue;
+                int64_t lq = is_if[q] ? 0 : L[q];
+                int64_t l0 = NB(q, a, 0);
+                int64_t ll = is_if[l0] ? 0 : L[l0];
+                lab[q] = lq > 0 ? lq : ll;
+            }
+            UF uf(nc);
+            std::vector<uint8_t> walled(nc, 0);
+            for (int64_t q = 0; q < nc; ++q) {
+                if (!face_active(q, a)) continue;
+                for (int d = 0; d < nd; ++d)
+                    for (int t = 0; t < 2; ++t) {
+                        int64_t p = NB(q, d, t);     // the cell at the neighbour face position
+                        bool act = face_active(p, a);
+                        if (!act) walled[q] = 1;
+                        if (t == 1 && act && lab[q] > 0 && lab[q] == lab[p]) uf.unite(q, p);
+                    }
+            }
+            std::vector<uint8_t> root_wall(nc, 0);
+            for (int64_t q = 0; q < nc; ++q)
+                if (lab[q] > 0 && walled[q]) root_wall[uf.find(q)] = 1;
+            for (int64_t q = 0; q < nc; ++q)
+                if (lab[q] > 0 && !root_wall[uf.find(q)]) bad.push_back(lab[q]);
+        }
+        if (bad.empty()) break;
+        std::sort(bad.begin(), bad.end());
+        bad.erase(std::unique(bad.begin(), bad.end()), bad.end());
+        if (round > 1000) return fail(c, GPLMM_E_GEOMETRY, "label merging did not settle");
+        // each offending label goes to the neighbour label it shares the most faces with
+        int64_t Lmax = *std::max_element(L.begin(), L.end());
+        std::vector<int64_t> target(Lmax + 1);
+        std::iota(target.begin(), target.end(), 0);
+        std::vector<uint8_t> isbad(Lmax + 1, 0);
+        for (int64_t l : bad) isbad[l] = 1;
+        std::map<int64_t, std::map<int64_t, int64_t>> cnt;
+        for (int64_t q = 0; q < nc; ++q) {
+            if (!isbad[L[q]]) continue;
+            for (int e = 0; e < 2 * nd; ++e) {
+                int64_t w = c->nbr[q * 6 + e];
+                if (w >= 0 && L[w] > 0 && L[w] != L[q]) cnt[L[q]][L[w]]++;
+            }
+        }
+        for (int64_t l : bad) {
+            auto it = cnt.find(l);
+            if (it == cnt.end()) continue;
+            int64_t best = -1, bc = -1;
+            for (auto& kv : it->second)
+                if (kv.second > bc) {   // map order: lowest label wins ties
+                    bc = kv.second;
+                    best = kv.first;
+                }
+            target[l] = best;
+        }
+        std::vector<int64_t> fin = target;
+        for (int64_t l : bad) {
+            std::vector<int64_t> seen{l};
+            int64_t cur = target[l];
+            while (cur != target[cur] && std::find(seen.begin(), seen.end(), cur) == seen.end()) {
+                seen.push_back(cur);
+                cur = target[cur];
+            }
+            auto f = std::find(seen.begin(), seen.end(), cur);
+            if (f != seen.end()) cur = *std::min_element(f, seen.end());
+            fin[l] = cur;
+        }
+        for (int64_t q = 0; q < nc; ++q) L[q] = fin[L[q]];
+    }
+    // ---- interfaces: sorted (lower label, own label) pairs
+    std::vector<std::pair<int64_t, int64_t>> pairs;
+    for (int64_t q = 0; q < nc; ++q)
+        if (is_if[q]) pairs.push_back({minlow[q], L[q]});
+    std::sort(pairs.begin(), pairs.end());
+    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+    c->iface.assign(nc, -1);
+    for (int64_t q = 0; q < nc; ++q)
+        if (is_if[q])
+            c->iface[q] = (int32_t)(std::lower_bound(pairs.begin(), pairs.end(),
+                                                     std::make_pair(minlow[q], L[q])) - pairs.begin());
+    // ---- an interface with no face to a primary cell joins the interface it shares most faces with
+    for (;;) {
+        int nif = (int)pairs.size();
+        std::vector<uint8_t> touches(nif, 0);
+        for (int64_t q = 0; q < nc; ++q) {
+            if (c->iface[q] < 0) continue;
+            for (int e = 0; e < 2 * nd; ++e) {
+                int64_t w = c->nbr[q * 6 + e];
+                if (w >= 0 && c->iface[w] < 0) touches[c->iface[q]] = 1;
+            }
+        }
+        int j = -1;
+        for (int t = 0; t < nif; ++t)
+            if (!touches[t]) {
+                j = t;
+                break;
+            }
+        if (j < 0) break;
+        std::vector<int64_t> cnt(nif, 0);
+        for (int64_t q = 0; q < nc; ++q) {
+            if (c->iface[q] != j) continue;
+            for (int e = 0; e < 2 * nd; ++e) {
+                int64_t w = c->nbr[q * 6 + e];
+                if (w >= 0 && c->iface[w] >= 0 && c->iface[w] != j) cnt[c->iface[w]]++;
+            }
+        }
+        int k = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
+        if (cnt[k] == 0) return fail(c, GPLMM_E_GEOMETRY, "an interface touches neither a primary nor another interface");
+        for (int64_t q = 0; q < nc; ++q) {
+            if (c->iface[q] == j) c->iface[q] = k;
+            if (c->iface[q] > j) c->iface[q] -= 1;
+        }
+        pairs.erase(pairs.begin() + j);
+    }
+    c->Nc = (int)pairs.size();
+    // ---- primaries in label order
+    std::vector<int64_t> plab;
+    for (int64_t q = 0; q < nc; ++q)
+        if (c->iface[q] < 0) plab.push_back(L[q]);
+    std::sort(plab.begin(), plab.end());
+    plab.erase(std::unique(plab.begin(), plab.end()), plab.end());
+    c->Np = (int)plab.size();
+    c->prim.assign(nc, -1);
+    for (int64_t q = 0; q < nc; ++q)
+        if (c->iface[q] < 0) c->prim[q] = (int32_t)(std::lower_bound(plab.begin(), plab.end(), L[q]) - plab.begin());
+    c->pin = -1;
+    for (int64_t q = 0; q < nc; ++q)
+        if (c->iface[q] < 0) {
+            c->pin = q;
+            break;
+        }
+    if (c->pin < 0) return fail(c, GPLMM_E_GEOMETRY, "no primary cell");
+    // ---- ownership of every slot
+    c->owner.assign(c->N, -3);
+    c->nface = 0;
+    for (int64_t q = 0; q < nc; ++q)
+        for (int a = 0; a < nd; ++a) {
+            int64_t s = slot(c, q, a);
+            if (!face_active(q, a)) {
+                c->owner[s] = -2;
+                continue;
+            }
+            ++c->nface;
+            int64_t l0 = NB(q, a, 0);
+            int pq = c->prim[q], pl = c->prim[l0];
+            if (pq >= 0 && pl >= 0 && pq != pl)
+                return fail(c, GPLMM_E_GEOMETRY, "a face lies between two different primaries");
+            c->owner[s] = pq >= 0 ? pq : (pl >= 0 ? pl : -1);
+        }
+    // ---- interfaces adjacent to each primary
+    c->Cp.assign(c->Np, {});
+    for (int64_t q = 0; q < nc; ++q) {
+        if (c->prim[q] < 0) continue;
+        for (int e = 0; e < 2 * nd; ++e) {
+            int64_t w = c->nbr[q * 6 + e];
+            if (w >= 0 && c->iface[w] >= 0) c->Cp[c->prim[q]].push_back(c->iface[w]);
+        }
+    }
+    for (auto& v : c->Cp) {
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    c->icells.assign(c->Nc, {});
+    for (int64_t q = 0; q < nc; ++q)
+        if (c->iface[q] >= 0) c->icells[c->iface[q]].push_back((int32_t)q);
+    // ---- tags: faces with a cell within Chebyshev distance tag_layers of an interface cell
+    {
+        std::vector<uint8_t> near(nvox, 0);
+        for (int64_t q = 0; q < nc; ++q)
+            if (c->iface[q] >= 0) near[c->cell_voxel[q]] = 1;
+        for (int d = 0; d < nd; ++d) {
+            std::vector<uint8_t> acc = near;
+            for (int64_t v = 0; v < nvox; ++v) {
+                if (!near[v]) continue;
+                for (int s = -1; s <= 1; s += 2) {
+                    int64_t w = v;
+                    for (int r = 1; r <= c->opt.tag_layers; ++r) {
+                        w = vox_nb(c, w, d, s);
+                        if (w < 0) break;
+                        acc[w] = 1;
+                    }
+                }
+            }
+            near.swap(acc);
+        }
+        c->tagslot.assign(c->N, 0);
+        c->tagcell.assign(nc, 0);
+        for (int64_t q = 0; q < nc; ++q)
+            for (int a = 0; a < nd; ++a) {
+                if (!face_active(q, a)) continue;
+                int64_t l0 = NB(q, a, 0);
+                if (near[c->cell_voxel[q]] || near[c->cell_voxel[l0]]) {
+                    c->tagslot[slot(c, q, a)] = 1;
+                    c->tagcell[q] |= (uint8_t)(1u << a);
+                }
+            }
+    }
+    // ---- dual grids: each interface grown dual_dilations times through face neighbours
+    int dd = c->opt.dual_dilations >= 0 ? c->opt.dual_dilations : (nd == 2 ? 2 : 0);
+    c->dual_cells.assign(c->Nc, {});
+    for (int j = 0; j < c->Nc; ++j) {
+        std::vector<int32_t> cur = c->icells[j];
+        for (int it = 0; it < dd; ++it) {
+            std::vector<int32_t> nxt = cur;
+            for (int32_t q : cur)
+                for (int e = 0; e < 2 * nd; ++e) {
+                    int64_t w = c->nbr[(int64_t)q * 6 + e];
+                    if (w >= 0) nxt.push_back((int32_t)w);
+                }
+            std::sort(nxt.begin(), nxt.end());
+            nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
+            cur.swap(nxt);
+        }
+        c->dual_cells[j] = cur;
+    }
+    return GPLMM_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Local problems: unknown sets, pressure-after-faces raster order, tile envelopes, LU schedule
+// ------------------------------------------------------------------------------------------
+
+namespace {
+
+// Unknowns of a cell set: its cells plus every active face with a flanking cell in the set.
+std::vector<int64_t> unknowns_of(const gplmm_ctx* c, const std::vector<int32_t>& cells) {
+    std::vector<int64_t> u;
+    const int nd = c->ndim;
+    for (int32_t q : cells) {
+        u.push_back(slot(c, q, nd));
+        for (int a = 0; a < nd; ++a) {
+            if (c->nbr[(int64_t)q * 6 + 2 * a] >= 0) u.push_back(slot(c, q, a));
+            int64_t up = c->nbr[(int64_t)q * 6 + 2 * a + 1];
+            if (up >= 0) u.push_back(slot(c, up, a));
+        }
+    }
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    return u;
+}
+
+// Sort key: faces at their record cell's raster position (axis order within it);
+// a pressure right after the last face of its cell, i.e. after the upper face
+// along the slowest axis (position unwrapped), so that each pressure follows all
+// of its faces and the velocity-first leading blocks stay nonsingular.
+int64_t order_key(const gplmm_ctx* c, int64_t s) {
+    int64_t q = s / c->nrec;
+    int comp = (int)(s % c->nrec);
+    int64_t v = c->cell_voxel[q];
+    if (comp < c->ndim) return v * 8 + comp;
+    int64_t stride = c->ndim == 3 ? (int64_t)c->nx * c->ny : (int64_t)c->nx;
+    return (v + stride) * 8 + 7;
+}
+
+// Structural columns of row s of X (viscous/convective neighbours, gradient, divergence).
+void row_pattern(const gplmm_ctx* c, int64_t s, std::vector<int64_t>& cols) {
+    cols.clear();
+    const int nd = c->ndim;
+    int64_t q = s / c->nrec;
+    int comp = (int)(s % c->nrec);
+    auto NB = [&](int64_t x, int d, int t) -> int64_t { return x < 0 ? -1 : c->nbr[x * 6 + 2 * d + t]; };
+    cols.push_back(s);
+    if (comp < nd) {
+        int a = comp;
+        int64_t l0 = NB(q, a, 0);
+        for (int d = 0; d < nd; ++d)
+            for (int t = 0; t < 2; ++t) {
+                int64_t p = (d == a && t == 0) ? l0 : NB(q, d, t);
+                if (p >= 0 && NB(p, a, 0) >= 0) cols.push_back(slot(c, p, a));
+            }
+        cols.push_back(slot(c, q, nd));
+        cols.push_back(slot(c, l0, nd));
+    } else if (q != c->pin) {
+        for (int a = 0; a < nd; ++a) {
+            if (NB(q, a, 0) >= 0) cols.push_back(slot(c, q, a));
+            int64_t up = NB(q, a, 1);
+            if (up >= 0) cols.push_back(slot(c, up, a));
+        }
+    }
+}
+
+}  // namespace
+
+int build_local_problems(gplmm_ctx* c) {
+    const int T = c->tile;
+    const int nsub = c->Np + c->Nc;
+    c->subs.assign(nsub, {});
+    c->sub_slots.clear();
+    c->env_tfc.clear();
+    c->env_tfr.clear();
+    c->env_lrow.clear();
+    c->env_ucol.clear();
+    std::vector<std::vector<int32_t>> prim_cells(c->Np);
+    for (int64_t q = 0; q < c->ncell; ++q)
+        if (c->prim[q] >= 0) prim_cells[c->prim[q]].push_back((int32_t)q);
+    int64_t elems = 0;
+    c->maxT = 0;
+    std::vector<int64_t> cols;
+    for (int sidx = 0; sidx < nsub; ++sidx) {
+        Sub& sb = c->subs[sidx];
+        sb.kind = sidx < c->Np ? 0 : 1;
+        sb.id = sidx < c->Np ? sidx : sidx - c->Np;
+        const std::vector<int32_t>& cells = sb.kind == 0 ? prim_cells[sb.id] : c->dual_cells[sb.id];
+        std::vector<int64_t> u = unknowns_of(c, cells);
+        std::vector<std::pair<int64_t, int64_t>> keyed(u.size());
+        for (size_t t = 0; t < u.size(); ++t) keyed[t] = {order_key(c, u[t]), u[t]};
+        std::sort(keyed.begin(), keyed.end());
+        const int n = (int)u.size();
+        sb.n = n;
+        sb.nT = (n + T - 1) / T;
+        c->maxT = std::max(c->maxT, sb.nT);
+        sb.slot_off = (int64_t)c->sub_slots.size();
+        std::vector<int64_t> sorted_slots(n);
+        for (int t = 0; t < n; ++t) {
+            sorted_slots[t] = keyed[t].second;
+            c->sub_slots.push_back((int32_t)keyed[t].second);
+        }
+        // global slot -> local index (sorted lookup)
+        std::vector<std::pair<int64_t, int>> inv(n);
+        for (int t = 0; t < n; ++t) inv[t] = {sorted_slots[t], t};
+        std::sort(inv.begin(), inv.end());
+        auto local = [&](int64_t s) -> int {
+            auto it = std::lower_bound(inv.begin(), inv.end(), std::make_pair(s, -1));
+            return (it != inv.end() && it->first == s) ? it->second : -1;
+        };
+        std::vector<int> fc(n), fr(n);
+        for (int r = 0; r < n; ++r) fc[r] = fr[r] = r;
+        for (int r = 0; r < n; ++r) {
+            row_pattern(c, sorted_slots[r], cols);
+            for (int64_t s : cols) {
+                int lc = local(s);
+                if (lc < 0) continue;
+                fc[r] = std::min(fc[r], lc);
+                fr[lc] = std::min(fr[lc], r);
+            }
+        }
+        sb.env_off = (int64_t)c->env_tfc.size();
+        std::vector<int> tfc(sb.nT), tfr(sb.nT);
+        for (int I = 0; I < sb.nT; ++I) {
+            tfc[I] = I;
+            tfr[I] = I;
+            for (int r = I * T; r < std::min(n, (I + 1) * T); ++r) {
+                tfc[I] = std::min(tfc[I], fc[r] / T);
+                tfr[I] = std::min(tfr[I], fr[r] / T);
+            }
+        }
+        for (int I = sb.nT - 2; I >= 0; --I) {   // monotone skyline
+            tfc[I] = std::min(tfc[I], tfc[I + 1]);
+            tfr[I] = std::min(tfr[I], tfr[I + 1]);
+        }
+        sb.diag_off = elems;
+        elems += (int64_t)sb.nT * T * T;
+        for (int I = 0; I < sb.nT; ++I) {
+            c->env_tfc.push_back(tfc[I]);
+            c->env_tfr.push_back(tfr[I]);
+            c->env_lrow.push_back(elems);
+            elems += (int64_t)(I - tfc[I]) * T * T;
+        }
+        for (int J = 0; J < sb.nT; ++J) {
+            c->env_ucol.push_back(elems);
+            elems += (int64_t)(J - tfr[J]) * T * T;
+        }
+    }
+    c->factor_elems = elems;
+    // ---- LU schedules: set 0 = primaries, set 1 = primaries and duals
+    for (int set = 0; set < 2; ++set) {
+        int ns = set == 0 ? c->Np : nsub;
+        auto& off = c->lu_step_off[set];
+        auto& pr = c->lu_step_pairs[set];
+        auto& soff = c->lu_sub_off[set];
+        auto& sl = c->lu_sub_list[set];
+        off.assign(1, 0);
+        soff.assign(1, 0);
+        pr.clear();
+        sl.clear();
+        for (int K = 0; K < c->maxT; ++K) {
+            for (int s = 0; s < ns; ++s) {
+                const Sub& sb = c->subs[s];
+                if (sb.nT <= K) continue;
+                sl.push_back(s);
+                const int* tfc = &c->env_tfc[sb.env_off];
+                for (int I = K + 1; I < sb.nT && tfc[I] <= K; ++I) {
+                    pr.push_back(s);
+                    pr.push_back(I);
+                }
+            }
+            off.push_back((int64_t)pr.size() / 2);
+            soff.push_back((int64_t)sl.size());
+        }
+    }
+    // ---- shape/correction blocks: per primary |S| x (|Cp| + 1), column-major
+    c->phi_off.assign(c->Np, 0);
+    c->phi_cols_off.assign(c->Np + 1, 0);
+    c->phi_cols.clear();
+    c->ycol.assign(c->Np, -1);
+    int64_t pe = 0;
+    int ny = 0;
+    for (int i = 0; i < c->Np; ++i) {
+        c->phi_off[i] = pe;
+        pe += (int64_t)c->subs[i].n * ((int64_t)c->Cp[i].size() + 1);
+        for (int32_t j : c->Cp[i]) c->phi_cols.push_back(j);
+        // a correction vector (and a coarse y unknown) only when b_B is nonzero on the primary
+        bool nonzero = false;
+        for (int t = 0; t < c->subs[i].n && !nonzero; ++t) {
+            int64_t s = c->sub_slots[c->subs[i].slot_off + t];
+            int comp = (int)(s % c->nrec);
+            if (comp < c->ndim && c->phys.body[comp] != 0.0) nonzero = true;
+        }
+        if (nonzero) c->ycol[i] = c->Nc + ny++;
+        c->phi_cols.push_back(c->ycol[i]);
+        c->phi_cols_off[i + 1] = (int64_t)c->phi_cols.size();
+    }
+    c->phi_elems = pe;
+    c->Ny = ny;
+    c->nco = c->Nc + ny;
+    return GPLMM_OK;
+}
+
+// Coarse operator by probing: columns whose restricted images Rhat X Phat e_col touch
+// disjoint coarse rows share a colour; Rhat X Phat (sum of a colour's columns) then
+// yields every entry of those columns at once.
+int build_probing(gplmm_ctx* c) {
+    const int nd = c->ndim;
+    const int64_t nc = c->ncell;
+    const int nco = c->nco;
+    // record cells of each row group (interfaces: their cells; primaries: cells holding S_i slots)
+    std::vector<std::vector<int32_t>> group_cells(nco);
+    for (int j = 0; j < c->Nc; ++j) group_cells[j] = c->icells[j];
+    std::vector<std::vector<int32_t>> prim_rec(c->Np);
+    for (int i = 0; i < c->Np; ++i) {
+        const Sub& sb = c->subs[i];
+        std::vector<int32_t> cells;
+        for (int t = 0; t < sb.n; ++t) cells.push_back(c->sub_slots[sb.slot_off + t] / c->nrec);
+        std::sort(cells.begin(), cells.end());
+        cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+        prim_rec[i] = cells;
+        if (c->ycol[i] >= 0) group_cells[c->ycol[i]] = cells;
+    }
+    // cell -> groups containing it
+    std::vector<std::vector<int32_t>> cell_groups(nc);
+    for (int g = 0; g < nco; ++g)
+        for (int32_t q : group_cells[g]) cell_groups[q].push_back(g);
+    // support cells of each coarse column
+    std::vector<std::vector<int32_t>> col_cells(nco);
+    for (int j = 0; j < c->Nc; ++j) col_cells[j] = c->icells[j];
+    for (int i = 0; i < c->Np; ++i) {
+        for (int32_t j : c->Cp[i])
+            col_cells[j].insert(col_cells[j].end(), prim_rec[i].begin(), prim_rec[i].end());
+        if (c->ycol[i] >= 0) col_cells[c->ycol[i]] = prim_rec[i];
+    }
+    std::vector<int32_t> mark_cell(nc, -1), mark_group(nco, -1);
+    std::vector<std::vector<int32_t>> Q(nco);
+    for (int col = 0; col < nco; ++col) {
+        std::vector<int32_t>& q = Q[col];
+        auto visit = [&](int64_t x) {
+            if (x < 0 || mark_cell[x] == col) return;
+            mark_cell[x] = col;
+            for (int32_t g : cell_groups[x])
+                if (mark_group[g] != col) {
+                    mark_group[g] = col;
+                    q.push_back(g);
+                }
+        };
+        for (int32_t x : col_cells[col]) {
+            visit(x);
+            for (int e = 0; e < 2 * nd; ++e) visit(c->nbr[(int64_t)x * 6 + e]);
+        }
+        std::sort(q.begin(), q.end());
+    }
+    // greedy colouring
+    std::vector<std::vector<uint64_t>> used;   // per row: bitset of colours claiming it
+    std::vector<int> color(nco, -1);
+    std::vector<std::vector<uint64_t>> claim;  // claim[color] bitset over rows
+    int ncol = 0;
+    for (int col = 0; col < nco; ++col) {
+        int chosen = -1;
+        for (int k = 0; k < ncol && chosen < 0; ++k) {
+            bool ok = true;
+            for (int32_t r : Q[col])
+                if (claim[k][r >> 6] >> (r & 63) & 1ull) {
+                    ok = false;
+                    break;
+                }
+            if (ok) chosen = k;
+        }
+        if (chosen < 0) {
+            chosen = ncol++;
+            claim.emplace_back((nco + 63) / 64, 0ull);
+        }
+        color[col] = chosen;
+        for (int32_t r : Q[col]) claim[chosen][r >> 6] |= 1ull << (r & 63);
+    }
+    c->ncolors = ncol;
+    c->color_off.assign(ncol + 1, 0);
+    c->color_col_off.assign(ncol + 1, 0);
+    std::vector<std::vector<int32_t>> cols_of(ncol);
+    for (int col = 0; col < nco; ++col) cols_of[color[col]].push_back(col);
+    c->probe.clear();
+    c->color_cols.clear();
+    for (int k = 0; k < ncol; ++k) {
+        for (int32_t col : cols_of[k]) {
+            c->color_cols.push_back(col);
+            for (int32_t r : Q[col]) c->probe.push_back({r, col});
+        }
+        c->color_off[k + 1] = (int64_t)c->probe.size();
+        c->color_col_off[k + 1] = (int64_t)c->color_cols.size();
+    }
+    return GPLMM_OK;
+}
+
+}  // namespace gp

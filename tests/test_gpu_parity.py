@@ -1,0 +1,163 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances: stencils (residual, Newton J v, build matrix X v) are FP64 sums of
+at most 16 terms, compared to 1e-13 relative; the FP64 preconditioner adds a
+no-pivot LU, an explicitly inverted coarse operator (condition up to ~1e7) and
+different summation orders, so its application is compared to 1e-9 relative;
+the converged Newton solution in FP64 mode to 1e-10 relative (u and the
+mean-free p), in FP32-preconditioner mode to 1e-8 (flexible GMRES in FP64
+recovers the accuracy; the tolerance is the outer loop's).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import gplmm as G
+from oracle import newton
+from oracle.mac import build_matrix, origin_rhs, residual, jacobian
+from synth import channel
+from tests.helpers import oracle_case, record_index, rel, to_record, workload
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _setup(name, seed=0, re=None, precision="fp64", **kw):
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    w = workload(name, seed, re=re)
+    _say("case", name, seed, precision)
+    s = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"], precision=precision, **kw)
+    g, ops, dc, ph = oracle_case(w["mask"], w["labels"], w["rho"], w["mu"], w["body"])
+    rec = record_index(g, s.maps()["cell_voxel"])
+    return torch, s, g, ops, dc, ph, rec
+
+
+def _dev(torch, a):
+    return torch.tensor(a, dtype=torch.float64, device="cuda")
+
+
+CASES = [("disks2d_32", 0), ("disks2d_64", 1), ("spheres3d_24", 0)]
+
+
+@pytest.mark.parametrize("name,seed", CASES)
+def test_residual_and_jacobian_parity(name, seed):
+    torch, s, g, ops, dc, ph, rec = _setup(name, seed)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(g.N)
+    v = rng.standard_normal(g.N)
+    xr, vr = _dev(torch, to_record(x, rec, s.N)), _dev(torch, to_record(v, rec, s.N))
+    r = s.residual(xr).cpu().numpy()
+    ro = residual(ops, x, ph)
+    assert rel(r[rec], ro) <= 1e-13
+    others = np.setdiff1d(np.arange(s.N), rec)
+    assert np.all(r[others] == 0.0)
+    y = s.matvec(xr, vr).cpu().numpy()
+    yo = jacobian(ops, x, ph) @ v
+    assert rel(y[rec], yo) <= 1e-13
+
+
+def test_transient_residual_parity():
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    from oracle.mac import Phys
+    w = workload("spheres3d_24", 1)
+    s = Solver(w["mask"], w["labels"], body=(0.7, 0.1, -0.2), dt=0.25)
+    g, ops, dc, ph = oracle_case(w["mask"], w["labels"], body=(0.7, 0.1, -0.2), dt=0.25)
+    rec = record_index(g, s.maps()["cell_voxel"])
+    rng = np.random.default_rng(4)
+    x, xo = rng.standard_normal(g.N), rng.standard_normal(g.N)
+    r = s.residual(_dev(torch, to_record(x, rec, s.N)), _dev(torch, to_record(xo, rec, s.N))).cpu().numpy()
+    assert rel(r[rec], residual(ops, x, ph, x_old=xo)) <= 1e-13
+
+
+@pytest.mark.parametrize("name,seed", CASES)
+def test_build_matrix_and_preconditioner_parity_fp64(name, seed):
+    torch, s, g, ops, dc, ph, rec = _setup(name, seed)
+    rng = np.random.default_rng(10 + seed)
+    wind = rng.standard_normal(g.N)
+    s.build(_dev(torch, to_record(wind, rec, s.N)))
+    X = build_matrix(ops, ph, wind=wind, tags=dc.tags)
+    v = rng.standard_normal(g.N)
+    vr = _dev(torch, to_record(v, rec, s.N))
+    y = s.build_matvec(vr).cpu().numpy()
+    assert rel(y[rec], X @ v) <= 1e-13
+    M = G.build(X, dc, origin_rhs(ops, ph))
+    z = s.precond_apply(vr).cpu().numpy()
+    zo = G.apply(M, v)
+    err = rel(z[rec], zo)
+    _say("precond apply rel err", err)
+    assert err <= 1e-9
+    # coarse part alone through a right-hand side in the coarse range: b_B
+    bB = origin_rhs(ops, ph)
+    zb = s.precond_apply(_dev(torch, to_record(bB, rec, s.N))).cpu().numpy()
+    assert rel(zb[rec], G.apply(M, bB)) <= 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+@pytest.mark.parametrize("name,seed,re", [("disks2d_64", 0, 1.0), ("disks2d_32", 2, 10.0), ("spheres3d_24", 0, 1.0)])
+def test_newton_solution_parity(name, seed, re, precision, tol):
+    torch, s, g, ops, dc, ph, rec = _setup(name, seed, re=re, precision=precision,
+                                           newton_tol=1e-13, lin_tol=1e-14)
+    x, st = s.newton_solve()
+    _say("gpu newton", st["newton_its"], st["lin_its"], st["res_hist"][-1])
+    assert st["converged"]
+    xo, sto = newton.solve(ops, dc, ph, tol=1e-14, precond="exact")
+    xg = x.cpu().numpy()[rec]
+    u = slice(0, g.nu)
+    p = g.p_slice
+    assert rel(xg[u], xo[u]) <= tol
+    pg, po = xg[p] - xg[p].mean(), xo[p] - xo[p].mean()
+    assert rel(pg, po) <= tol
+
+
+def test_poiseuille_channel_closed_form():
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    from tests.test_oracle_mac import poiseuille_profile
+    nz, ny, nx = 4, 9, 12
+    m = channel(nx, ny, nz)
+    lab = np.zeros_like(m, dtype=np.int32)
+    for k in range(3):
+        lab[:, :, 4 * k:4 * (k + 1)] = k + 1
+    s = Solver(m, lab, rho=1.0, mu=0.8, body=(0.6, 0, 0), periodic=(1, 0, 1), newton_tol=1e-13, lin_tol=1e-14)
+    x, st = s.newton_solve()
+    assert st["converged"] and st["newton_its"] == 1 and st["lin_its"][0] == 1
+    xr = x.cpu().numpy().reshape(-1, 4)
+    u = xr[:, 0].reshape(nz, ny, nx)
+    ref = np.tile(poiseuille_profile(ny, 1.0, 0.6, 0.8, 1.0)[None, :, None], (nz, 1, nx))
+    assert np.max(np.abs(u - ref)) <= 1e-12 * ref.max()
+    assert np.max(np.abs(xr[:, 1:])) <= 1e-12 * ref.max()
+
+
+def test_single_pore_is_exact_inverse():
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    m = np.ones((5, 7, 8), np.uint8)
+    m[1:3, 3, 3:5] = 0
+    lab = np.ones_like(m, dtype=np.int32)
+    s = Solver(m, lab, body=(1.0, 0.0, 0.0))
+    assert s.info()["Nc"] == 0
+    s.build()
+    v = torch.randn(s.N, dtype=torch.float64, device="cuda")
+    vh = v.cpu().numpy().reshape(-1, 4)
+    # keep void slots at zero
+    g, ops, dc, ph = oracle_case(m, lab)
+    rec = record_index(g, s.maps()["cell_voxel"])
+    vv = np.zeros(s.N)
+    vv[rec] = v.cpu().numpy()[rec]
+    vd = _dev(torch, vv)
+    z = s.precond_apply(vd)
+    back = s.build_matvec(z).cpu().numpy()
+    assert rel(back, vv) <= 1e-12

@@ -1,0 +1,82 @@
+"""CPU tests of the C ABI: the library loads, exports every declared entry
+point, and its host-side decomposition (carving, admissibility merge, interface
+merge, ownership, tags, dual grids, pin) is bit-exact against the oracle's
+independent implementation.  No device call is made (host-only contexts)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from tests.helpers import oracle_case, record_index, workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    from paper_2510_22077_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libgplmm.so not built")
+    return binding
+
+
+def test_library_exports_every_declared_symbol():
+    binding = _lib_or_skip()
+    lib = binding.load()
+    hdr = open(os.path.join(ROOT, "include", "gplmm.h")).read()
+    declared = set(re.findall(r"\b(gplmm_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(binding.EXPORTS)
+
+
+@pytest.mark.parametrize("name,seed", [("disks2d_64", 0), ("disks2d_64", 3), ("disks2d_32", 1),
+                                       ("spheres3d_24", 0), ("spheres3d_24", 2), ("spheres3d_48", 0)])
+def test_host_decomposition_bit_exact(name, seed):
+    binding = _lib_or_skip()
+    w = workload(name, seed)
+    s = binding.Solver(w["mask"], w["labels"], body=w["body"], host_only=True)
+    g, ops, dc, ph = oracle_case(w["mask"], w["labels"], body=w["body"])
+    info = s.info()
+    m = s.maps()
+    assert info["ncell"] == g.nc and info["nface_active"] == g.nu
+    assert info["Np"] == dc.Np and info["Nc"] == dc.Nc and info["pin"] == dc.pin
+    assert np.array_equal(m["cell_voxel"], np.flatnonzero(g.fluid))
+    assert np.array_equal(m["cell_iface"], dc.iface)
+    assert np.array_equal(m["cell_prim"], dc.prim)
+    rec = record_index(g, m["cell_voxel"])
+    # face ownership and tags on every velocity unknown
+    assert np.array_equal(m["face_owner"][rec[:g.nu]], dc.owner)
+    tags = np.concatenate([t for t in dc.tags]).astype(np.int8)
+    assert np.array_equal(m["face_tag"][rec[:g.nu]], tags)
+    # every other slot is a void slot or a pressure
+    other = np.setdiff1d(np.arange(info["N"]), rec[:g.nu])
+    assert np.all(np.isin(m["face_owner"][other], [-2, -3]))
+    du = s.duals()
+    assert len(du) == dc.Nc
+    for a, b in zip(du, dc.dual_cells):
+        assert np.array_equal(a, b)
+    s.close()
+
+
+def test_host_only_context_refuses_compute_calls():
+    binding = _lib_or_skip()
+    w = workload("disks2d_32", 0)
+    s = binding.Solver(w["mask"], w["labels"], body=w["body"], host_only=True)
+    lib = s.lib
+    rc = lib.gplmm_build(s.ctx, None)
+    assert rc == -5
+    assert b"host-only" in lib.gplmm_last_error(s.ctx)
+    s.close()
+
+
+def test_setup_rejects_bad_labels_and_sizes():
+    binding = _lib_or_skip()
+    w = workload("disks2d_32", 0)
+    lab = w["labels"].copy()
+    lab[w["mask"] == 1] = 0
+    with pytest.raises(binding.GplmmError):
+        binding.Solver(w["mask"], lab, host_only=True)
+    with pytest.raises(binding.GplmmError):
+        binding.Solver(np.zeros((1, 8, 8), np.uint8), np.zeros((1, 8, 8), np.int32), host_only=True)
