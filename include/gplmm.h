@@ -191,10 +191,11 @@ int gplmm_newton_solve(gplmm_ctx* ctx, const double* x_prev_dev, double* x_dev, 
  * stencil and the Arnoldi step (on = 1) or stop recording (on = 0). */
 int gplmm_set_timing(gplmm_ctx* ctx, int on);
 
-/* Average device time (ms) of the last k launches of a named kernel group,
- * recorded with HIP events on the context's stream; used for roofline
- * reporting.  name: "precond_apply", "trsv", "jv", "xv", "arnoldi".
- * Returns the number of samples. */
+/* Average device time (ms) and average algorithmic bytes of the timed
+ * launches of a named kernel group since the last reset, recorded with HIP
+ * events on the context's stream (see gplmm_set_timing); used for roofline
+ * reporting.  name: "precond_apply", "trsv", "jv", "arnoldi".  Returns the
+ * number of samples. */
 int gplmm_kernel_time(gplmm_ctx* ctx, const char* name, double* avg_ms, double* bytes);
 
 /* Reset the kernel timers. */

@@ -21,14 +21,13 @@ paper asks only for a thinnest separating set, which it does not construct):
   own label); interfaces are numbered by sorting the pairs; a primary is the
   set of its label's cells that are not interface cells (empty ones are
   dropped), numbered in label order;
-* admissibility: the closure of a primary replaces every coupling to an
-  f-face or another primary by a zero normal gradient, so a group of the
+* wall-free face groups: the closure of a primary replaces every coupling to
+  an f-face or another primary by a zero normal gradient, so a group of the
   primary's same-axis faces that are linked to each other through the viscous
   stencil, and none of which touches a grain (or the image edge), would leave
-  a uniform velocity on that group undetermined.  Each such primary's label is
-  merged into the face-adjacent label it shares the most faces with (lowest
-  label on ties; all offending labels in one pass, chains followed) and the
-  carving is redone, until every primary is admissible;
+  a uniform velocity on that group undetermined (a singular closure matrix).
+  The faces of such a group are marked ``free`` and keep their plain rows in
+  the closure matrix (no column sums), which keeps it nonsingular;
 * an interface with no face to any primary cell is merged into the interface
   it shares the most faces with (lowest id on ties), lowest id first, until
   none is left; ids are then compacted keeping their order;
@@ -135,6 +134,7 @@ class Decomp:
     dual_cells: List[np.ndarray]
     icells: List[np.ndarray]    # global unknowns of each interface's cells
     f_faces: np.ndarray
+    free: np.ndarray            # per velocity unknown: in a wall-free face group of its primary
 
 
 def unknowns_of_cells(g, fc, cells):
@@ -167,20 +167,15 @@ def carve(L, nbr):
     return is_if, minlow
 
 
-def _bad_labels(g, L, is_if, fc, walled):
-    """Labels of primaries that own a viscous-connected group of same-axis
-    faces with no walled face."""
+def free_faces(g, owner, walled):
+    """Velocity unknowns whose primary's viscous-connected group of same-axis
+    faces contains no walled face."""
     from scipy.sparse import csr_matrix
     from scipy.sparse.csgraph import connected_components
-    bad = set()
-    cell_lab = np.where(is_if, 0, L)
+    out = np.zeros(g.nu, dtype=bool)
     for c in g.comps:
         nc = g.ncomp[c]
-        lab_face = np.zeros(nc, dtype=np.int64)
-        for t in (0, 1):
-            f = fc[:, 2 * c + t]
-            ok = (f >= 0) & (cell_lab > 0)
-            lab_face[f[ok] - g.off[c]] = cell_lab[ok]
+        own = owner[g.comp_slice(c)]
         act = g.act[c]
         me = g.fid[c][act] - g.off[c]
         rr, cc = [], []
@@ -188,47 +183,17 @@ def _bad_labels(g, L, is_if, fc, walled):
             nb = g.shift(g.fid[c], d, +1, -1)[act]
             ok = nb >= 0
             a, b = me[ok], nb[ok] - g.off[c]
-            same = (lab_face[a] > 0) & (lab_face[a] == lab_face[b])
+            same = (own[a] >= 0) & (own[a] == own[b])
             rr.append(a[same])
             cc.append(b[same])
         rr, cc = np.concatenate(rr), np.concatenate(cc)
         A = csr_matrix((np.ones(rr.size), (rr, cc)), shape=(nc, nc))
         _, grp = connected_components(A, directed=False)
-        owned = lab_face > 0
+        owned = own >= 0
         has_wall = np.zeros(grp.max() + 1 if grp.size else 0, dtype=bool)
         has_wall[grp[owned & walled[c]]] = True
-        free = owned & ~has_wall[grp]
-        bad.update(np.unique(lab_face[free]).tolist())
-    return sorted(bad)
-
-
-def _merge_labels(L, nbr, bad):
-    """Map each bad label to the adjacent label sharing the most faces."""
-    Lmax = int(L.max())
-    a = L[:, None].repeat(nbr.shape[1], 1)
-    b = np.where(nbr >= 0, L[np.maximum(nbr, 0)], 0)
-    sel = (b > 0) & (a != b)
-    pa, pb = a[sel], b[sel]
-    target = np.arange(Lmax + 1)
-    for l in bad:
-        m = pa == l
-        if not np.any(m):
-            continue
-        cnt = np.bincount(pb[m], minlength=Lmax + 1)
-        target[l] = int(np.argmax(cnt))
-    # follow chains; a cycle collapses to its smallest label
-    final = target.copy()
-    for l in bad:
-        seen = [l]
-        cur = target[l]
-        while cur != target[cur] and cur not in seen:
-            seen.append(cur)
-            cur = target[cur]
-        if cur in seen:
-            cyc = seen[seen.index(cur):]
-            cur = min(cyc)
-        final[l] = cur
-    return final[L]
+        out[g.comp_slice(c)] = owned & ~has_wall[grp]
+    return out
 
 
 def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
@@ -244,14 +209,8 @@ def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
     nbr = cell_neighbours(g)
     fc = cell_faces(g)
     nc = g.nc
-    walled = walled_faces(g)
-    # --- carving, repeated until every primary is admissible
-    while True:
-        is_if, minlow = carve(L, nbr)
-        bad = _bad_labels(g, L, is_if, fc, walled)
-        if not bad:
-            break
-        L = _merge_labels(L, nbr, bad)
+    # --- carving
+    is_if, minlow = carve(L, nbr)
     pr = np.stack([minlow[is_if], L[is_if]], 1)
     upairs, inv = np.unique(pr, axis=0, return_inverse=True)
     iface = np.full(nc, -1, dtype=np.int64)
@@ -303,6 +262,7 @@ def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
                 raise AssertionError("a face lies between two different primaries")
             owner[f[ok]] = prim[ok]
     f_faces = np.flatnonzero(owner < 0)
+    free = free_faces(g, owner, walled_faces(g))
     # --- C^{p_i}: interfaces sharing a face with primary i (D4)
     a_pr = prim[:, None].repeat(nbr.shape[1], 1)
     nb_if = np.where(nbr >= 0, iface[np.maximum(nbr, 0)], -1)
@@ -337,4 +297,4 @@ def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
         D.append(unknowns_of_cells(g, fc, cur))
     return Decomp(g=g, label=L, iface=iface, prim=prim, Nc=Nc, Np=Np, pairs=upairs,
                   pin=pin, owner=owner, Cp=Cp, tags=tags, S=S, D=D,
-                  dual_cells=dual_cells, icells=icells, f_faces=f_faces)
+                  dual_cells=dual_cells, icells=icells, f_faces=f_faces, free=free)

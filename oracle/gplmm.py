@@ -7,7 +7,8 @@ Paper:
   the base smoother M_l = M_dp (Section 3.1);
 * reduction: the f-face columns and the other primaries' columns of each
   primary row are summed onto its diagonal (Section 3.2.2, the two reduction
-  equations), which gives the closure matrices Abar_i;
+  equations), which gives the closure matrices Abar_i; rows of faces in a
+  wall-free group (see ``decomp``) are left unsummed so Abar_i stays regular;
 * shape vectors  phi_ij = -Abar_i^-1 (A restricted to the rows of primary i
   and summed over the cells of interface j), correction vectors
   chi_i = Abar_i^-1 b_B (Section 3.2.2, prolongation), with b_B the residual
@@ -49,12 +50,15 @@ class GPLMM:
     Abar: list
 
 
-def closure_matrix(X, S, cols_summed):
-    """X[S,S] + diag(row sums of X[S, cols_summed])."""
+def closure_matrix(X, S, cols_summed, exempt=None):
+    """X[S,S] + diag(row sums of X[S, cols_summed]); rows flagged in ``exempt``
+    (faces of wall-free groups) keep their plain row."""
     XS = X[S][:, S].tocsr()
     if cols_summed.size == 0:
         return XS.tocsc()
     extra = np.asarray(X[S][:, cols_summed].sum(axis=1)).ravel()
+    if exempt is not None:
+        extra = np.where(exempt, 0.0, extra)
     return (XS + sp.diags(extra)).tocsc()
 
 
@@ -77,7 +81,10 @@ def build(X, dc: Decomp, bB):
         nz_cols = np.unique(XS.indices)
         oc = owner_all[nz_cols]
         summed = nz_cols[((oc == -1) | (oc >= 0)) & (oc != i)]
-        Ab = closure_matrix(X, S, summed)
+        exempt = np.zeros(S.size, dtype=bool)
+        vel = S < g.nu
+        exempt[vel] = dc.free[S[vel]]
+        Ab = closure_matrix(X, S, summed, exempt)
         lu = spla.splu(Ab)
         Abar.append(Ab)
         cols = []

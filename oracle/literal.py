@@ -11,6 +11,9 @@ dense matrix exactly as the paper writes it,
   dropped;
 * reduction 2: Abar^{p_i}_{p_i} = A~^{p_i}_{p_i} + diag(sum_{j != i}
   csum(A~^{p_i}_{p_j})), off-diagonal primary blocks dropped;
+* both column sums skip the rows of faces in wall-free groups (this
+  project's reading, see ``decomp``), which keeps every Abar^{p_i}_{p_i}
+  regular;
 * the reduction matrix Q = blkdiag(I, Q^o) and A_M = Q^T Abar Q;
 * prolongation P = [B C; I O] with shape vectors
   -(Abar^{p_i}_{p_i})^-1 R^{p_i}_p Abar^p_c e^{c_j} and correction vectors
@@ -48,9 +51,14 @@ def literal_preconditioner(Ahat, dc, bB):
     npf = sum(b.size for b in p_blocks)
     ncf = sum(b.size for b in c_blocks)
     P_, C_, F_ = slice(0, npf), slice(npf, npf + ncf), slice(npf + ncf, N)
+    # rows of faces in wall-free groups take no column sums (see decomp)
+    perm_free = np.zeros(N, dtype=bool)
+    vel = order < g.nu
+    perm_free[vel] = dc.free[order[vel]]
+    keep = (~perm_free).astype(float)
     # --- reduction 1
     Atil = A[:npf + ncf, :npf + ncf].copy()
-    Atil[P_, P_] += np.diag(csum(A[P_, F_]))
+    Atil[P_, P_] += np.diag(keep[P_] * csum(A[P_, F_]))
     Atil[C_, C_] += np.diag(csum(A[C_, F_]))
     # --- reduction 2: block-diagonalise the primary block
     offs = np.cumsum([0] + [b.size for b in p_blocks])
@@ -64,7 +72,7 @@ def literal_preconditioner(Ahat, dc, bB):
             rj = slice(offs[j], offs[j + 1])
             extra += csum(Atil[ri, rj])
             Abar[ri, rj] = 0.0
-        Abar[ri, ri] += np.diag(extra)
+        Abar[ri, ri] += np.diag(keep[ri] * extra)
     # --- reduction matrix Q
     Nc = dc.Nc
     Qo = np.zeros((ncf, Nc))

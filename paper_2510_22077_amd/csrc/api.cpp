@@ -33,7 +33,7 @@ void timer_end(gplmm_ctx* c, const char* name, double bytes) {
     hipEventCreate(&e);
     hipEventRecord(e, c->stream);
     t.ev1.push_back(e);
-    t.bytes = bytes;
+    t.bytes.push_back(bytes);
 }
 }  // namespace gp
 
@@ -111,6 +111,7 @@ int upload_all(gplmm_ctx* c) {
     GP_TRY(upload(c, &c->d_sorted_slot, sorted_slot));
     GP_TRY(upload(c, &c->d_sorted_loc, sorted_loc));
     GP_TRY(upload(c, &c->d_slot_class, slot_class));
+    GP_TRY(upload(c, &c->d_noclose, c->noclose));
     GP_TRY(upload(c, &c->d_local_off, local_off));
     GP_TRY(upload(c, &c->d_sub_ids, sub_ids));
     GP_TRY(upload(c, &c->d_tfc, c->env_tfc));
@@ -555,14 +556,15 @@ int gplmm_kernel_time(gplmm_ctx* c, const char* name, double* avg_ms, double* by
     hipStreamSynchronize(c->stream);
     Timer& t = it->second;
     size_t n = std::min(t.ev0.size(), t.ev1.size());
-    double sum = 0.0;
+    double sum = 0.0, bsum = 0.0;
     for (size_t k = 0; k < n; ++k) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, t.ev0[k], t.ev1[k]);
         sum += ms;
+        bsum += t.bytes[k];
     }
     if (avg_ms) *avg_ms = n ? sum / n : 0.0;
-    if (bytes) *bytes = t.bytes;
+    if (bytes) *bytes = n ? bsum / n : 0.0;
     return (int)n;
 }
 
@@ -588,7 +590,8 @@ void gplmm_destroy(gplmm_ctx* c) {
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_wind_f, c->d_r, c->d_tmp,
                     c->d_dx, c->d_zero, c->d_V, c->d_Z, c->d_red, c->d_pv, c->d_local, c->d_cv, c->d_row_sub,
-                    c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids};
+                    c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids,
+                    c->d_noclose};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_red) hipHostFree(c->h_red);

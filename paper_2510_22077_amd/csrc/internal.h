@@ -49,7 +49,7 @@ struct ProbeEntry {
 
 struct Timer {
     std::vector<hipEvent_t> ev0, ev1;
-    double bytes = 0.0;      // algorithmic bytes per launch
+    std::vector<double> bytes;   // algorithmic bytes of each timed launch
 };
 
 }  // namespace gp
@@ -70,6 +70,7 @@ struct gplmm_ctx {
     std::vector<int32_t> iface, prim; // per cell
     std::vector<int32_t> owner;       // per slot (see gplmm_get_maps)
     std::vector<int8_t> tagslot;      // per slot
+    std::vector<uint8_t> noclose;     // per slot: face of a wall-free group (no closure sums)
     std::vector<uint8_t> tagcell;     // per cell bits
     int Np = 0, Nc = 0, Ny = 0;
     int64_t pin = 0;
@@ -116,6 +117,7 @@ struct gplmm_ctx {
     int32_t* d_sorted_slot = nullptr;    // per sub: its slots ascending ...
     int32_t* d_sorted_loc = nullptr;     // ... and their local indices
     int32_t* d_slot_class = nullptr;     // per slot: owner primary, -1 f-face, -2 void, -4 interface cell
+    uint8_t* d_noclose = nullptr;        // per slot: 1 = keep the plain row in the closure matrix
     int64_t* d_local_off = nullptr;      // per sub: offset of its padded local vector
     int32_t* d_sub_ids = nullptr;        // 0 .. Np+Nc-1
     gp::Sub* d_subs = nullptr;

@@ -47,8 +47,8 @@ template <typename T, typename W>
 __global__ void assemble_kernel(DevGeo g, Phys ph, const W* __restrict__ wind, Env e, T* __restrict__ F,
                                 const int32_t* __restrict__ row_sub, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ sorted_slot, const int32_t* __restrict__ sorted_loc,
-                                const int32_t* __restrict__ slot_class, int64_t nrows, int first_sub, int nsub,
-                                int closure) {
+                                const int32_t* __restrict__ slot_class, const uint8_t* __restrict__ noclose,
+                                int64_t nrows, int first_sub, int nsub, int closure) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nrows) return;
     const int s = row_sub[t];
@@ -63,6 +63,7 @@ __global__ void assemble_kernel(DevGeo g, Phys ph, const W* __restrict__ wind, E
     int64_t cols[kMaxRow];
     double vals[kMaxRow];
     const int cnt = x_row(g, ph, nb, c, comp, wind, cols, vals);
+    if (noclose[gs]) closure = 0;
     double diag_extra = 0.0;
     const int32_t* ss = sorted_slot + sb.slot_off;
     const int32_t* sl = sorted_loc + sb.slot_off;
@@ -292,11 +293,12 @@ int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure) {
     if (c->opt.precision == GPLMM_FP32 && c->d_wind_f)
         assemble_kernel<T, float><<<nb, 256, 0, c->stream>>>(c->geo, c->phys, c->d_wind_f, e, F, c->d_row_sub,
                                                              c->d_sub_slots, c->d_sorted_slot, c->d_sorted_loc,
-                                                             c->d_slot_class, nrows, first_sub, nsub, closure ? 1 : 0);
+                                                             c->d_slot_class, c->d_noclose, nrows, first_sub, nsub, closure ? 1 : 0);
     else
         assemble_kernel<T, double><<<nb, 256, 0, c->stream>>>(c->geo, c->phys, c->d_wind, e, F, c->d_row_sub,
                                                               c->d_sub_slots, c->d_sorted_slot, c->d_sorted_loc,
-                                                              c->d_slot_class, nrows, first_sub, nsub, closure ? 1 : 0);
+                                                              c->d_slot_class, c->d_noclose, nrows, first_sub, nsub,
+                                                              closure ? 1 : 0);
     if (nsub > 0) pad_kernel<T><<<nsub, 64, 0, c->stream>>>(e, F, first_sub, nsub);
     return GPLMM_OK;
 }
@@ -321,8 +323,19 @@ template <typename T>
 void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vin, T* out_local) {
     if (nsub <= 0) return;
     Env e = make_env(c);
+    // algorithmic bytes: every factor tile of these subdomains once, the gathered
+    // right-hand side (value + slot index) and the written solution
+    const bool duals = sub_ids_dev != c->d_sub_ids;
+    const int s0 = duals ? c->Np : 0, s1 = duals ? c->Np + c->Nc : c->Np;
+    const int64_t e0 = c->subs[s0].diag_off;
+    const int64_t e1 = s1 < (int)c->subs.size() ? c->subs[s1].diag_off : c->factor_elems;
+    const int64_t rows = (s1 < (int)c->subs.size() ? c->subs[s1].slot_off : (int64_t)c->sub_slots.size()) -
+                         c->subs[s0].slot_off;
+    const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)rows * (2.0 * sizeof(T) + 4.0);
+    timer_begin(c, "trsv");
     trsv_kernel<T><<<dim3(nsub, 1), 256, 0, c->stream>>>(e, (const T*)c->d_factor, sub_ids_dev, c->d_sub_slots, vin,
                                                         out_local, c->d_local_off, nullptr, 0);
+    timer_end(c, "trsv", bytes);
 }
 
 template <typename T>

@@ -4,7 +4,7 @@
 // permutation paragraph of Section 3.2.2 (a face with a flanking cell in a
 // primary belongs to it; a face flanked by neither belongs to the interface).
 // The rules that turn pore labels into interfaces (carving on the higher-label
-// side, the admissibility merge, the merge of interfaces that touch no
+// side, the closure exemption of wall-free face groups, the merge of interfaces that touch no
 // primary, the pin, tags and dual growth) are this library's reading of the
 // paper, stated where each step is implemented.
 #include <algorithm>
@@ -129,81 +129,7 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
     };
     // an a-face "at" cell q is its lower a-face; active iff the lower neighbour is fluid
     auto face_active = [&](int64_t q, int a) { return q >= 0 && NB(q, a, 0) >= 0; };
-    // ---- carving repeated until every primary is admissible: every group of a primary's
-    // same-axis faces linked through the viscous stencil must reach a non-active face position
-    for (int round = 0;; ++round) {
-        carve();
-        std::vector<int64_t> bad;
-        for (int a = 0; a < nd; ++a) {
-            std::vector<int64_t> lab(nc, 0);
-            for (int64_t q = 0; q < nc; ++q) {
-                if (!face_active(q, a)) continue;
-                int64_t lq = is_if[q] ? 0 : L[q];
-                int64_t l0 = NB(q, a, 0);
-                int64_t ll = is_if[l0] ? 0 : L[l0];
-                lab[q] = lq > 0 ? lq : ll;
-            }
-            UF uf(nc);
-            std::vector<uint8_t> walled(nc, 0);
-            for (int64_t q = 0; q < nc; ++q) {
-                if (!face_active(q, a)) continue;
-                for (int d = 0; d < nd; ++d)
-                    for (int t = 0; t < 2; ++t) {
-                        int64_t p = NB(q, d, t);     // the cell at the neighbour face position
-                        bool act = face_active(p, a);
-                        if (!act) walled[q] = 1;
-                        if (t == 1 && act && lab[q] > 0 && lab[q] == lab[p]) uf.unite(q, p);
-                    }
-            }
-            std::vector<uint8_t> root_wall(nc, 0);
-            for (int64_t q = 0; q < nc; ++q)
-                if (lab[q] > 0 && walled[q]) root_wall[uf.find(q)] = 1;
-            for (int64_t q = 0; q < nc; ++q)
-                if (lab[q] > 0 && !root_wall[uf.find(q)]) bad.push_back(lab[q]);
-        }
-        if (bad.empty()) break;
-        std::sort(bad.begin(), bad.end());
-        bad.erase(std::unique(bad.begin(), bad.end()), bad.end());
-        if (round > 1000) return fail(c, GPLMM_E_GEOMETRY, "label merging did not settle");
-        // each offending label goes to the neighbour label it shares the most faces with
-        int64_t Lmax = *std::max_element(L.begin(), L.end());
-        std::vector<int64_t> target(Lmax + 1);
-        std::iota(target.begin(), target.end(), 0);
-        std::vector<uint8_t> isbad(Lmax + 1, 0);
-        for (int64_t l : bad) isbad[l] = 1;
-        std::map<int64_t, std::map<int64_t, int64_t>> cnt;
-        for (int64_t q = 0; q < nc; ++q) {
-            if (!isbad[L[q]]) continue;
-            for (int e = 0; e < 2 * nd; ++e) {
-                int64_t w = c->nbr[q * 6 + e];
-                if (w >= 0 && L[w] > 0 && L[w] != L[q]) cnt[L[q]][L[w]]++;
-            }
-        }
-        for (int64_t l : bad) {
-            auto it = cnt.find(l);
-            if (it == cnt.end()) continue;
-            int64_t best = -1, bc = -1;
-            for (auto& kv : it->second)
-                if (kv.second > bc) {   // map order: lowest label wins ties
-                    bc = kv.second;
-                    best = kv.first;
-                }
-            target[l] = best;
-        }
-        std::vector<int64_t> fin = target;
-        for (int64_t l : bad) {
-            std::vector<int64_t> seen{l};
-            int64_t cur = target[l];
-            while (cur != target[cur] && std::find(seen.begin(), seen.end(), cur) == seen.end()) {
-                seen.push_back(cur);
-                cur = target[cur];
-            }
-            auto f = std::find(seen.begin(), seen.end(), cur);
-            if (f != seen.end()) cur = *std::min_element(f, seen.end());
-            fin[l] = cur;
-        }
-        for (int64_t q = 0; q < nc; ++q) L[q] = fin[L[q]];
-    }
+    carve();
     // ---- interfaces: sorted (lower label, own label) pairs
     std::vector<std::pair<int64_t, int64_t>> pairs;
     for (int64_t q = 0; q < nc; ++q)
@@ -284,6 +210,30 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
                 return fail(c, GPLMM_E_GEOMETRY, "a face lies between two different primaries");
             c->owner[s] = pq >= 0 ? pq : (pl >= 0 ? pl : -1);
         }
+    // ---- wall-free face groups: a primary's same-axis faces linked through the viscous
+    // stencil, none of which reaches a non-active face position, keep their plain rows in
+    // the closure matrix (the column sums would leave their common velocity undetermined)
+    c->noclose.assign(c->N, 0);
+    for (int a = 0; a < nd; ++a) {
+        UF uf(nc);
+        std::vector<uint8_t> walled(nc, 0);
+        auto own = [&](int64_t q) -> int32_t { return face_active(q, a) ? c->owner[slot(c, q, a)] : -9; };
+        for (int64_t q = 0; q < nc; ++q) {
+            if (!face_active(q, a)) continue;
+            for (int d = 0; d < nd; ++d)
+                for (int t = 0; t < 2; ++t) {
+                    int64_t p = NB(q, d, t);
+                    bool act = face_active(p, a);
+                    if (!act) walled[q] = 1;
+                    if (t == 1 && act && own(q) >= 0 && own(q) == own(p)) uf.unite(q, p);
+                }
+        }
+        std::vector<uint8_t> root_wall(nc, 0);
+        for (int64_t q = 0; q < nc; ++q)
+            if (own(q) >= 0 && walled[q]) root_wall[uf.find(q)] = 1;
+        for (int64_t q = 0; q < nc; ++q)
+            if (own(q) >= 0 && !root_wall[uf.find(q)]) c->noclose[slot(c, q, a)] = 1;
+    }
     // ---- interfaces adjacent to each primary
     c->Cp.assign(c->Np, {});
     for (int64_t q = 0; q < nc; ++q) {
