@@ -89,7 +89,7 @@ typedef struct {
                                 no inertia in X (default 1) */
     int dual_dilations;      /* face-neighbour growths of each interface into its dual grid;
                                 -1 = default (2 in 2D, 0 in 3D) */
-    int restart;             /* FGMRES restart length (default 30, at most 64) */
+    int restart;             /* FGMRES restart length (default 30, at most 256) */
     double newton_tol;       /* stop when ||r(x)|| <= newton_tol * ||r(0)|| (default 1e-8) */
     double lin_tol;          /* FGMRES stops when ||J d + r|| <= lin_tol * ||r(0)|| (default 1e-9) */
     int newton_maxit;        /* default 30 */
@@ -148,7 +148,9 @@ int gplmm_layout_info(const gplmm_ctx* ctx, gplmm_layout* out);
  * cell_prim[ncell]    primary grid of each cell, -1 for interface cells;
  * face_owner[N]       for velocity slots: owning primary, -1 for f-faces (both cells
  *                     in interfaces), -2 for void slots; for pressure slots: -3;
- * face_tag[N]         1 where the velocity slot carries no inertia in X, else 0.
+ * face_tag[N]         bit 0: the velocity slot carries no inertia in X (tagged face);
+ *                     bit 1: the face belongs to a wall-free group of its primary and keeps
+ *                     its plain row in the closure matrix.
  * Any pointer may be NULL to skip that map. */
 int gplmm_get_maps(const gplmm_ctx* ctx, int32_t* cell_voxel, int32_t* cell_iface,
                    int32_t* cell_prim, int32_t* face_owner, int8_t* face_tag);
@@ -175,6 +177,12 @@ int gplmm_build_matvec(gplmm_ctx* ctx, const double* v_dev, double* y_dev);
  * vectors (Section 3.2.2, prolongation), assemble and invert the coarse operator
  * Rhat X Phat (Remark 1).  Errors: GPLMM_E_BREAKDOWN, GPLMM_E_HIP. */
 int gplmm_build(gplmm_ctx* ctx, const double* wind_dev);
+
+/* Host copy of the coarse operator Rhat X Phat assembled by the last gplmm_build
+ * (row-major, nco x nco with nco = Nc + Ny; rows and columns: interfaces 0..Nc-1,
+ * then the correction unknowns of the primaries that carry one, in primary order).
+ * ao_host must hold nco*nco doubles; nco_out (may be NULL) receives nco. */
+int gplmm_get_coarse(gplmm_ctx* ctx, double* ao_host, int* nco_out);
 
 /* z = M^-1 v (Section 3.1 with Section 3.2.3: coarse correction, then the dual
  * and the primary additive-Schwarz smoothers).  Requires gplmm_build.  v_dev and

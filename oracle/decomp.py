@@ -28,9 +28,14 @@ paper asks only for a thinnest separating set, which it does not construct):
   a uniform velocity on that group undetermined (a singular closure matrix).
   The faces of such a group are marked ``free`` and keep their plain rows in
   the closure matrix (no column sums), which keeps it nonsingular;
-* an interface with no face to any primary cell is merged into the interface
-  it shares the most faces with (lowest id on ties), lowest id first, until
-  none is left; ids are then compacted keeping their order;
+* an interface is degenerate when no primary cell touches it, or when every
+  primary touching it touches no other interface (a dead-end pocket that
+  reaches the rest of the void only through faces between interface cells,
+  which the coarse space leaves at zero, so its coarse pressure would be
+  undetermined); the lowest-id degenerate interface that shares a face with
+  another interface is merged into the one it shares the most faces with
+  (lowest id on ties), until none is left; ids are then compacted keeping
+  their order;
 * the pin c* is the first fluid cell in raster order that is not an interface
   cell;
 * tags: a face is tagged iff one of its two cells lies within Chebyshev
@@ -215,25 +220,37 @@ def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
     upairs, inv = np.unique(pr, axis=0, return_inverse=True)
     iface = np.full(nc, -1, dtype=np.int64)
     iface[is_if] = inv.ravel()
-    # --- merge interfaces that touch no primary cell
+    # --- merge degenerate interfaces
     while True:
         nif = upairs.shape[0]
         prim_cell = iface < 0
         a_if = iface[:, None].repeat(nbr.shape[1], 1)
         valid = (nbr >= 0) & (a_if >= 0)
         nb_prim = valid & prim_cell[np.maximum(nbr, 0)]
-        touches = np.zeros(nif, dtype=bool)
-        touches[a_if[nb_prim]] = True
-        bad = np.nonzero(~touches)[0]
-        if bad.size == 0:
+        # (interface, label of the touching primary cell) pairs
+        ip = np.unique(np.stack([a_if[nb_prim], L[np.maximum(nbr, 0)][nb_prim]], 1), axis=0)
+        # interfaces touched by each primary label
+        lab_ifs = {}
+        for j, l in ip:
+            lab_ifs.setdefault(int(l), set()).add(int(j))
+        touching = {}
+        for j, l in ip:
+            touching.setdefault(int(j), []).append(int(l))
+        nb_if = np.where(valid, iface[np.maximum(nbr, 0)], -1)
+        shares = np.zeros(nif, dtype=bool)
+        sel = valid & (nb_if >= 0) & (nb_if != a_if)
+        shares[a_if[sel]] = True
+        bad = []
+        for j in range(nif):
+            labs = touching.get(j, [])
+            dead = all(lab_ifs[l] == {j} for l in labs)
+            if dead and shares[j]:
+                bad.append(j)
+        if not bad:
             break
         j = bad[0]
-        nb_if = np.where(valid, iface[np.maximum(nbr, 0)], -1)
         sel = (a_if == j) & (nb_if >= 0) & (nb_if != j)
-        cand = nb_if[sel]
-        if cand.size == 0:
-            raise ValueError("interface %d touches neither a primary nor another interface" % j)
-        cnt = np.bincount(cand, minlength=nif)
+        cnt = np.bincount(nb_if[sel], minlength=nif)
         k = int(np.argmax(cnt))          # argmax returns the lowest id on ties
         iface[iface == j] = k
         keep = np.ones(nif, dtype=bool)

@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",
            "gplmm_get_duals", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
-           "gplmm_precond_apply", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
+           "gplmm_precond_apply", "gplmm_get_coarse", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
            "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy"]
 
 _lib = None
@@ -89,6 +89,8 @@ def load():
     lib.gplmm_build_matvec.restype = I
     lib.gplmm_build.argtypes = [P, P]
     lib.gplmm_build.restype = I
+    lib.gplmm_get_coarse.argtypes = [P, P, P]
+    lib.gplmm_get_coarse.restype = I
     lib.gplmm_precond_apply.argtypes = [P, P, P]
     lib.gplmm_precond_apply.restype = I
     lib.gplmm_newton_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
@@ -245,6 +247,14 @@ class Solver:
 
     def build(self, wind=None):
         self._check(self.lib.gplmm_build(self.ctx, _ptr(self._vec(wind))), "build")
+
+    def coarse_operator(self):
+        """Host copy of the assembled coarse operator Rhat X Phat (after build)."""
+        n = ctypes.c_int()
+        self.lib.gplmm_get_coarse(self.ctx, None, ctypes.byref(n))
+        A = np.zeros((n.value, n.value))
+        self._check(self.lib.gplmm_get_coarse(self.ctx, A.ctypes.data, None), "get_coarse")
+        return A
 
     def precond_apply(self, v, out=None):
         out = self.zeros() if out is None else out

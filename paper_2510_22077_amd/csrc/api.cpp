@@ -122,6 +122,14 @@ int upload_all(gplmm_ctx* c) {
         GP_TRY(upload(c, &c->d_step_pairs[set], c->lu_step_pairs[set]));
         GP_TRY(upload(c, &c->d_sub_list[set], c->lu_sub_list[set]));
     }
+    // triangular solves: each set's subdomains, largest first (they bound the launch)
+    for (int set = 0; set < 2; ++set) {
+        int s0 = set == 0 ? 0 : c->Np, s1 = set == 0 ? c->Np : nsub;
+        std::vector<int32_t> ord;
+        for (int sidx = s0; sidx < s1; ++sidx) ord.push_back(sidx);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return c->subs[a].nT > c->subs[b].nT; });
+        GP_TRY(upload(c, &c->d_sub_order[set], ord));
+    }
     c->prim_factor_elems = c->Nc > 0 ? c->subs[c->Np].diag_off : c->factor_elems;
     c->prim_rows = c->Nc > 0 ? c->subs[c->Np].slot_off : (int64_t)c->sub_slots.size();
     GP_TRY(alloc(c, &c->d_factor, real_size(c) * c->factor_elems));
@@ -210,7 +218,8 @@ int upload_all(gplmm_ctx* c) {
     const int nco = c->nco;
     GP_TRY(alloc(c, (void**)&c->d_Ao, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
     GP_TRY(alloc(c, (void**)&c->d_Aowork, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
-    GP_TRY(alloc(c, (void**)&c->d_piv, sizeof(int32_t) * std::max(nco, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_Aoasm, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_piv, sizeof(int32_t) * 2 * std::max(nco, 1)));
     GP_TRY(alloc(c, (void**)&c->d_cv, sizeof(double) * 2 * std::max(nco, 1)));
     GP_TRY(alloc(c, (void**)&c->d_flag, sizeof(int) * 4));
     // vectors
@@ -358,7 +367,7 @@ int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double m
         *out = c;
         return GPLMM_E_ARG;
     };
-    if (c->opt.restart > kMaxRestart) return bad("restart must be <= 64");
+    if (c->opt.restart > kMaxRestart) return bad("restart must be <= 256");
     if (c->opt.tile != 32) return bad("only tile = 32 is supported");
     if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return bad("image dimensions must be positive");
     if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024) return bad("image dimensions must be <= 1024");
@@ -422,7 +431,8 @@ int gplmm_get_maps(const gplmm_ctx* c, int32_t* cell_voxel, int32_t* cell_iface,
     if (cell_iface) std::copy(c->iface.begin(), c->iface.end(), cell_iface);
     if (cell_prim) std::copy(c->prim.begin(), c->prim.end(), cell_prim);
     if (face_owner) std::copy(c->owner.begin(), c->owner.end(), face_owner);
-    if (face_tag) std::copy(c->tagslot.begin(), c->tagslot.end(), face_tag);
+    if (face_tag)
+        for (int64_t k = 0; k < c->N; ++k) face_tag[k] = (int8_t)(c->tagslot[k] | (c->noclose[k] << 1));
     return GPLMM_OK;
 }
 
@@ -471,6 +481,18 @@ int gplmm_build(gplmm_ctx* c, const double* wind) {
     int rc = do_build(c);
     if (rc == GPLMM_OK) GP_HIP(c, hipGetLastError());
     return rc;
+}
+
+int gplmm_get_coarse(gplmm_ctx* c, double* ao, int* nco_out) {
+    if (!c) return GPLMM_E_ARG;
+    if (nco_out) *nco_out = c->nco;
+    if (!ao) return GPLMM_OK;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!c->built) return fail(c, GPLMM_E_STATE, "gplmm_build must precede gplmm_get_coarse");
+    GP_HIP(c, hipMemcpyAsync(ao, c->d_Aoasm, sizeof(double) * (int64_t)c->nco * c->nco, hipMemcpyDeviceToHost,
+                             c->stream));
+    GP_HIP(c, hipStreamSynchronize(c->stream));
+    return GPLMM_OK;
 }
 
 int gplmm_precond_apply(gplmm_ctx* c, const double* v, double* z) {
@@ -591,7 +613,7 @@ void gplmm_destroy(gplmm_ctx* c) {
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_wind_f, c->d_r, c->d_tmp,
                     c->d_dx, c->d_zero, c->d_V, c->d_Z, c->d_red, c->d_pv, c->d_local, c->d_cv, c->d_row_sub,
                     c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids,
-                    c->d_noclose};
+                    c->d_noclose, c->d_Aoasm, c->d_sub_order[0], c->d_sub_order[1]};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_red) hipHostFree(c->h_red);

@@ -9,11 +9,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gplmm.h"
+#include "gplmm.h"
 
 namespace gp {
 
-constexpr int kMaxRestart = 64;
+constexpr int kMaxRestart = 256;
 
 // Geometry as the device kernels see it.
 struct DevGeo {
@@ -143,10 +143,13 @@ struct gplmm_ctx {
     int64_t* d_dinv = nullptr;
     double* d_Ao = nullptr;              // coarse operator, then its inverse (nco x nco, row-major)
     double* d_Aowork = nullptr;
+    double* d_Aoasm = nullptr;           // the assembled coarse operator (kept for inspection)
     int32_t* d_piv = nullptr;
     gp::ProbeEntry* d_probe = nullptr;
     int32_t* d_color_cols = nullptr;
     int* d_flag = nullptr;               // breakdown flags
+    // triangular solves: subdomains of each set (0 primaries, 1 duals), largest first
+    int32_t* d_sub_order[2] = {nullptr, nullptr};
 
     // work vectors (FP64 unless noted)
     double* d_wind = nullptr;            // N

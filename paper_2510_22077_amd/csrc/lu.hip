@@ -280,6 +280,87 @@ __global__ void __launch_bounds__(256) trsv_kernel(Env e, const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------
+// Single-right-hand-side solves for the preconditioner application: one block of 1024
+// threads per subdomain (largest first), no communication between blocks.  Thread
+// (r, c) = (tid / 32, tid % 32) owns element (r, c) of every tile it touches, so the
+// tiles of a tile row (L, stored row by row) or of a tile column (U, stored column by
+// column) stream through the block as one contiguous, coalesced range with independent
+// loads; partial sums are reduced over the 32 lanes of a row.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T sum32(T v) {
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restrict__ F,
+                                                        const int32_t* __restrict__ order,
+                                                        const int32_t* __restrict__ slots, const T* __restrict__ vin,
+                                                        T* __restrict__ out, const int64_t* __restrict__ off) {
+    __shared__ T part[kT];
+    __shared__ T xs[kT];
+    const int s = order[blockIdx.x];
+    const Sub sb = e.subs[s];
+    T* x = out + off[s];
+    const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
+    const int32_t* tfc = e.tfc + sb.env_off;
+    const int32_t* tfr = e.tfr + sb.env_off;
+    const int32_t* sl = slots + sb.slot_off;
+    // forward: L y = b, y overwrites x
+    for (int I = 0; I < sb.nT; ++I) {
+        const int j0 = tfc[I], nt = I - j0;
+        const T* Lr = F + e.lrow[sb.env_off + I] + tid;
+        const T* y = x + j0 * kT + c;
+        T acc = 0;
+#pragma unroll 4
+        for (int t = 0; t < nt; ++t) acc += Lr[(int64_t)t * kTT] * y[t * kT];
+        acc = sum32(acc);
+        if (c == 0) {
+            const int gr = I * kT + r;
+            part[r] = (gr < sb.n ? vin[sl[gr]] : (T)0) - acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const T* dt = F + sb.diag_off + (int64_t)I * kTT;
+            T v = tid < kT ? part[tid] : (T)0;
+            for (int k = 0; k < kT; ++k) {
+                T yk = __shfl(v, k, 64);
+                if (tid > k && tid < kT) v -= dt[tid * kT + k] * yk;
+            }
+            if (tid < kT) x[I * kT + tid] = v;
+        }
+        __syncthreads();
+    }
+    // backward: U x = y, column-oriented (push) over U's tile columns
+    for (int J = sb.nT - 1; J >= 0; --J) {
+        if (tid < 64) {
+            const T* dt = F + sb.diag_off + (int64_t)J * kTT;
+            T v = tid < kT ? x[J * kT + tid] : (T)0;
+            for (int k = kT - 1; k >= 0; --k) {
+                T xk = __shfl(v, k, 64) / dt[k * kT + k];
+                if (tid == k) v = xk;
+                if (tid < k) v -= dt[tid * kT + k] * xk;
+            }
+            if (tid < kT) {
+                x[J * kT + tid] = v;
+                xs[tid] = v;
+            }
+        }
+        __syncthreads();
+        const int i0 = tfr[J], nt = J - i0;
+        const T* Uc = F + e.ucol[sb.env_off + J] + tid;
+        const T xc = xs[c];
+#pragma unroll 4
+        for (int t = 0; t < nt; ++t) {
+            T v = sum32(Uc[(int64_t)t * kTT] * xc);
+            if (c == 0) x[(i0 + t) * kT + r] -= v;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------------------
 static Env make_env(gplmm_ctx* c) { return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow, c->d_ucol}; }
@@ -323,18 +404,19 @@ template <typename T>
 void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vin, T* out_local) {
     if (nsub <= 0) return;
     Env e = make_env(c);
-    // algorithmic bytes: every factor tile of these subdomains once, the gathered
-    // right-hand side (value + slot index) and the written solution
     const bool duals = sub_ids_dev != c->d_sub_ids;
+    const int set = duals ? 1 : 0;
+    // algorithmic bytes: every factor tile of these subdomains once, the gathered
+    // right-hand side (value + slot index) and the solution written and re-read
     const int s0 = duals ? c->Np : 0, s1 = duals ? c->Np + c->Nc : c->Np;
     const int64_t e0 = c->subs[s0].diag_off;
     const int64_t e1 = s1 < (int)c->subs.size() ? c->subs[s1].diag_off : c->factor_elems;
     const int64_t rows = (s1 < (int)c->subs.size() ? c->subs[s1].slot_off : (int64_t)c->sub_slots.size()) -
                          c->subs[s0].slot_off;
-    const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)rows * (2.0 * sizeof(T) + 4.0);
+    const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)rows * (3.0 * sizeof(T) + 4.0);
     timer_begin(c, "trsv");
-    trsv_kernel<T><<<dim3(nsub, 1), 256, 0, c->stream>>>(e, (const T*)c->d_factor, sub_ids_dev, c->d_sub_slots, vin,
-                                                        out_local, c->d_local_off, nullptr, 0);
+    trsv_sub_kernel<T><<<nsub, 1024, 0, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set], c->d_sub_slots,
+                                                     vin, out_local, c->d_local_off);
     timer_end(c, "trsv", bytes);
 }
 

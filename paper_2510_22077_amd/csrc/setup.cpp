@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <map>
 #include <queue>
 
 #include "internal.h"
@@ -141,23 +142,46 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
         if (is_if[q])
             c->iface[q] = (int32_t)(std::lower_bound(pairs.begin(), pairs.end(),
                                                      std::make_pair(minlow[q], L[q])) - pairs.begin());
-    // ---- an interface with no face to a primary cell joins the interface it shares most faces with
+    // ---- degenerate interfaces: touched by no primary cell, or only by primaries that touch no
+    // other interface (a dead-end pocket seen by the rest of the void only through faces between
+    // interface cells, which the coarse space leaves at zero).  The lowest-id one that shares a
+    // face with another interface joins the interface it shares the most faces with.
     for (;;) {
         int nif = (int)pairs.size();
-        std::vector<uint8_t> touches(nif, 0);
+        std::vector<std::vector<int64_t>> if_labs(nif);                 // primary labels touching j
+        std::map<int64_t, std::vector<int32_t>> lab_ifs;                 // interfaces touched by a label
+        std::vector<uint8_t> shares(nif, 0);
         for (int64_t q = 0; q < nc; ++q) {
-            if (c->iface[q] < 0) continue;
+            int j = c->iface[q];
+            if (j < 0) continue;
             for (int e = 0; e < 2 * nd; ++e) {
                 int64_t w = c->nbr[q * 6 + e];
-                if (w >= 0 && c->iface[w] < 0) touches[c->iface[q]] = 1;
+                if (w < 0) continue;
+                if (c->iface[w] < 0) {
+                    if_labs[j].push_back(L[w]);
+                    lab_ifs[L[w]].push_back(j);
+                } else if (c->iface[w] != j) {
+                    shares[j] = 1;
+                }
             }
         }
+        for (auto& kv : lab_ifs) {
+            std::sort(kv.second.begin(), kv.second.end());
+            kv.second.erase(std::unique(kv.second.begin(), kv.second.end()), kv.second.end());
+        }
         int j = -1;
-        for (int t = 0; t < nif; ++t)
-            if (!touches[t]) {
-                j = t;
-                break;
+        for (int t = 0; t < nif && j < 0; ++t) {
+            if (!shares[t]) continue;
+            bool dead = true;
+            for (int64_t l : if_labs[t]) {
+                const auto& v = lab_ifs[l];
+                if (!(v.size() == 1 && v[0] == t)) {
+                    dead = false;
+                    break;
+                }
             }
+            if (dead) j = t;
+        }
         if (j < 0) break;
         std::vector<int64_t> cnt(nif, 0);
         for (int64_t q = 0; q < nc; ++q) {
@@ -168,7 +192,6 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
             }
         }
         int k = (int)(std::max_element(cnt.begin(), cnt.end()) - cnt.begin());
-        if (cnt[k] == 0) return fail(c, GPLMM_E_GEOMETRY, "an interface touches neither a primary nor another interface");
         for (int64_t q = 0; q < nc; ++q) {
             if (c->iface[q] == j) c->iface[q] = k;
             if (c->iface[q] > j) c->iface[q] -= 1;

@@ -161,3 +161,54 @@ def test_single_pore_is_exact_inverse():
     z = s.precond_apply(vd)
     back = s.build_matvec(z).cpu().numpy()
     assert rel(back, vv) <= 1e-12
+
+
+def test_preconditioner_parity_on_a_crop_of_the_benchmark_packing():
+    """The 48^3 corner of the 128^3 benchmark packing (about 110 pores, 400
+    interfaces): every multi-block triangular solve path and the probing of
+    the coarse operator at a few hundred colours-worth of columns."""
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    w = workload("spheres3d_128", 0)
+    m = w["mask"][:48, :48, :48].copy()
+    lab = w["labels"][:48, :48, :48].copy()
+    _say("case spheres3d_128 crop 48")
+    s = Solver(m, lab, body=w["body"])
+    g, ops, dc, ph = oracle_case(m, lab, body=w["body"])
+    rec = record_index(g, s.maps()["cell_voxel"])
+    rng = np.random.default_rng(7)
+    wind = 0.05 * rng.standard_normal(g.N)
+    s.build(_dev(torch, to_record(wind, rec, s.N)))
+    X = build_matrix(ops, ph, wind=wind, tags=dc.tags)
+    M = G.build(X, dc, origin_rhs(ops, ph))
+    Ao = s.coarse_operator()
+    _say("coarse operator rel err", rel(Ao, M.Ao), "shape", Ao.shape, M.Ao.shape)
+    D = np.abs(Ao - M.Ao)
+    bad = np.argwhere(D > 1e-8 * np.abs(M.Ao).max())
+    _say("bad entries", bad.shape[0], bad[:10].tolist())
+    assert rel(Ao, M.Ao) <= 1e-11
+    for k in range(2):
+        v = rng.standard_normal(g.N)
+        z = s.precond_apply(_dev(torch, to_record(v, rec, s.N))).cpu().numpy()
+        zo = G.apply(M, v)
+        err = rel(z[rec], zo)
+        _say("crop precond apply rel err", err)
+        if err > 1e-9:
+            d = np.abs(z[rec] - zo)
+            co = g.unknown_coords()
+            top = np.argsort(-d)[:12]
+            for t in top:
+                kind = co[t][0]
+                cell = None
+                _say("  unk", t, "kind", kind, "kji", co[t][1:].tolist(), "err %.3e val %.3e" % (d[t], zo[t]),
+                     "owner", dc.owner[t] if t < g.nu else -9,
+                     "prim/iface", (dc.prim[t - g.nu], dc.iface[t - g.nu]) if t >= g.nu else "")
+            # error by class
+            cls = np.full(g.N, "p")
+            cls[:g.nu] = np.where(dc.owner >= 0, "prim_face", "f_face")
+            cc = np.where(dc.prim >= 0, "prim_cell", "iface_cell")
+            cls[g.nu:] = cc
+            for nm in ["prim_face", "f_face", "prim_cell", "iface_cell"]:
+                m_ = cls == nm
+                _say("  class", nm, m_.sum(), "err norm %.3e of %.3e" % (np.linalg.norm(d[m_]), np.linalg.norm(zo[m_])))
+        assert err <= 1e-9
