@@ -293,6 +293,8 @@ __device__ __forceinline__ T sum32(T v) {
     return v;
 }
 
+constexpr int kPF = 32;   // tiles of the next tile row prefetched into registers
+
 template <typename T>
 __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restrict__ F,
                                                         const int32_t* __restrict__ order,
@@ -300,47 +302,77 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
                                                         T* __restrict__ out, const int64_t* __restrict__ off) {
     __shared__ T part[kT];
     __shared__ T xs[kT];
+    __shared__ T Dt[kT][kT + 1];
     const int s = order[blockIdx.x];
     const Sub sb = e.subs[s];
     T* x = out + off[s];
     const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
     const int32_t* tfc = e.tfc + sb.env_off;
     const int32_t* tfr = e.tfr + sb.env_off;
+    const int64_t* lrow = e.lrow + sb.env_off;
+    const int64_t* ucol = e.ucol + sb.env_off;
     const int32_t* sl = slots + sb.slot_off;
-    // forward: L y = b, y overwrites x
-    for (int I = 0; I < sb.nT; ++I) {
+    const int nT = sb.nT;
+    if (nT == 0) return;
+    T pre[kPF];
+    // ---- forward: L y = b (y overwrites x); row I+1's tiles load while row I is solved
+    int ntp = 0;   // tiles held in pre[] for the current row
+#pragma unroll
+    for (int t = 0; t < kPF; ++t) pre[t] = 0;
+    for (int I = 0; I < nT; ++I) {
         const int j0 = tfc[I], nt = I - j0;
-        const T* Lr = F + e.lrow[sb.env_off + I] + tid;
+        const T dval = F[sb.diag_off + (int64_t)I * kTT + tid];
+        const T b = (c == 0 && I * kT + r < sb.n) ? vin[sl[I * kT + r]] : (T)0;
         const T* y = x + j0 * kT + c;
         T acc = 0;
-#pragma unroll 4
-        for (int t = 0; t < nt; ++t) acc += Lr[(int64_t)t * kTT] * y[t * kT];
-        acc = sum32(acc);
-        if (c == 0) {
-            const int gr = I * kT + r;
-            part[r] = (gr < sb.n ? vin[sl[gr]] : (T)0) - acc;
+#pragma unroll
+        for (int t = 0; t < kPF; ++t)
+            if (t < ntp) acc += pre[t] * y[t * kT];
+        const T* Lr = F + lrow[I] + tid;
+        for (int t = kPF; t < nt; ++t) acc += Lr[(int64_t)t * kTT] * y[t * kT];
+        if (I + 1 < nT) {   // prefetch the next tile row
+            const int ntn = I + 1 - tfc[I + 1];
+            const T* Ln = F + lrow[I + 1] + tid;
+#pragma unroll
+            for (int t = 0; t < kPF; ++t)
+                if (t < ntn) pre[t] = Ln[(int64_t)t * kTT];
+            ntp = min(ntn, kPF);
         }
+        acc = sum32(acc);
+        Dt[r][c] = dval;
+        if (c == 0) part[r] = b - acc;
         __syncthreads();
         if (tid < 64) {
-            const T* dt = F + sb.diag_off + (int64_t)I * kTT;
             T v = tid < kT ? part[tid] : (T)0;
+            const int rr = tid < kT ? tid : 0;
             for (int k = 0; k < kT; ++k) {
                 T yk = __shfl(v, k, 64);
-                if (tid > k && tid < kT) v -= dt[tid * kT + k] * yk;
+                if (tid > k && tid < kT) v -= Dt[rr][k] * yk;
             }
             if (tid < kT) x[I * kT + tid] = v;
         }
         __syncthreads();
     }
-    // backward: U x = y, column-oriented (push) over U's tile columns
-    for (int J = sb.nT - 1; J >= 0; --J) {
+    // ---- backward: U x = y, column-oriented (push) over U's contiguous tile columns
+    {
+        const int J = nT - 1;
+        const int ntn = J - tfr[J];
+        const T* Un = F + ucol[J] + tid;
+#pragma unroll
+        for (int t = 0; t < kPF; ++t)
+            if (t < ntn) pre[t] = Un[(int64_t)t * kTT];
+        ntp = min(ntn, kPF);
+    }
+    for (int J = nT - 1; J >= 0; --J) {
+        Dt[r][c] = F[sb.diag_off + (int64_t)J * kTT + tid];
+        __syncthreads();
         if (tid < 64) {
-            const T* dt = F + sb.diag_off + (int64_t)J * kTT;
             T v = tid < kT ? x[J * kT + tid] : (T)0;
+            const int rr = tid < kT ? tid : 0;
             for (int k = kT - 1; k >= 0; --k) {
-                T xk = __shfl(v, k, 64) / dt[k * kT + k];
+                T xk = __shfl(v, k, 64) / Dt[k][k];
                 if (tid == k) v = xk;
-                if (tid < k) v -= dt[tid * kT + k] * xk;
+                if (tid < k) v -= Dt[rr][k] * xk;
             }
             if (tid < kT) {
                 x[J * kT + tid] = v;
@@ -349,10 +381,28 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         }
         __syncthreads();
         const int i0 = tfr[J], nt = J - i0;
-        const T* Uc = F + e.ucol[sb.env_off + J] + tid;
         const T xc = xs[c];
-#pragma unroll 4
-        for (int t = 0; t < nt; ++t) {
+        T cur[kPF];
+#pragma unroll
+        for (int t = 0; t < kPF; ++t) cur[t] = pre[t];
+        const int ntc = ntp;
+        if (J > 0) {   // prefetch the next tile column
+            const int ntn = J - 1 - tfr[J - 1];
+            const T* Un = F + ucol[J - 1] + tid;
+#pragma unroll
+            for (int t = 0; t < kPF; ++t)
+                if (t < ntn) pre[t] = Un[(int64_t)t * kTT];
+            ntp = min(ntn, kPF);
+        }
+#pragma unroll
+        for (int t = 0; t < kPF; ++t) {
+            if (t < ntc) {
+                T v = sum32(cur[t] * xc);
+                if (c == 0) x[(i0 + t) * kT + r] -= v;
+            }
+        }
+        const T* Uc = F + ucol[J] + tid;
+        for (int t = kPF; t < nt; ++t) {
             T v = sum32(Uc[(int64_t)t * kTT] * xc);
             if (c == 0) x[(i0 + t) * kT + r] -= v;
         }
