@@ -159,6 +159,12 @@ int gplmm_get_maps(const gplmm_ctx* ctx, int32_t* cell_voxel, int32_t* cell_ifac
  * grid, ascending).  Call with dual_cells = NULL to get dual_ptr only. */
 int gplmm_get_duals(const gplmm_ctx* ctx, int64_t* dual_ptr, int32_t* dual_cells);
 
+/* Sizes of the local problems of Section 3.2.3 (primaries first, in primary order, then
+ * the dual grids in interface order; Np + Nc entries each): n[s] local unknowns and
+ * factor_elems[s] stored factor elements (diagonal tiles, L tile rows, U tile columns).
+ * Host arrays owned by the caller; either may be NULL. */
+int gplmm_get_subdomains(const gplmm_ctx* ctx, int32_t* n, int64_t* factor_elems);
+
 /* r = r(x): the MAC residual of the momentum and mass equations (Section 1;
  * backward Euler against x_prev when dt > 0, x_prev may be NULL = 0; the pinned
  * cell's mass row is p = 0).  All pointers are device vectors of N doubles. */

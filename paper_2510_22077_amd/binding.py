@@ -54,7 +54,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",
-           "gplmm_get_duals", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
+           "gplmm_get_duals", "gplmm_get_subdomains", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
            "gplmm_precond_apply", "gplmm_get_coarse", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
            "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy"]
 
@@ -82,6 +82,8 @@ def load():
     lib.gplmm_get_maps.restype = I
     lib.gplmm_get_duals.argtypes = [P, P, P]
     lib.gplmm_get_duals.restype = I
+    lib.gplmm_get_subdomains.argtypes = [P, P, P]
+    lib.gplmm_get_subdomains.restype = I
     for f in ("gplmm_residual", "gplmm_matvec"):
         getattr(lib, f).argtypes = [P, P, P, P]
         getattr(lib, f).restype = I
@@ -215,6 +217,14 @@ class Solver:
         cells = np.zeros(max(int(ptr[-1]), 1), np.int32)
         self.lib.gplmm_get_duals(self.ctx, ptr.ctypes.data, cells.ctypes.data)
         return [cells[ptr[j]:ptr[j + 1]].copy() for j in range(self.layout.Nc)]
+
+    def subdomains(self):
+        """(n, factor_elems) of every local problem: primaries, then dual grids."""
+        k = self.layout.Np + self.layout.Nc
+        n = np.zeros(max(k, 1), np.int32)
+        fe = np.zeros(max(k, 1), np.int64)
+        self._check(self.lib.gplmm_get_subdomains(self.ctx, n.ctypes.data, fe.ctypes.data), "get_subdomains")
+        return n[:k], fe[:k]
 
     # ---- device vectors
     def zeros(self):

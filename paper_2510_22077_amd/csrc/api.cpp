@@ -117,7 +117,8 @@ int upload_all(gplmm_ctx* c) {
     GP_TRY(upload(c, &c->d_tfc, c->env_tfc));
     GP_TRY(upload(c, &c->d_tfr, c->env_tfr));
     GP_TRY(upload(c, &c->d_lrow, c->env_lrow));
-    GP_TRY(upload(c, &c->d_ucol, c->env_ucol));
+    GP_TRY(upload(c, &c->d_urow, c->env_urow));
+    GP_TRY(upload(c, &c->d_tlc, c->env_tlc));
     for (int set = 0; set < 2; ++set) {
         GP_TRY(upload(c, &c->d_step_pairs[set], c->lu_step_pairs[set]));
         GP_TRY(upload(c, &c->d_sub_list[set], c->lu_sub_list[set]));
@@ -446,6 +447,17 @@ int gplmm_get_duals(const gplmm_ctx* c, int64_t* ptr, int32_t* cells) {
     return GPLMM_OK;
 }
 
+int gplmm_get_subdomains(const gplmm_ctx* c, int32_t* n, int64_t* factor_elems) {
+    if (!c) return GPLMM_E_ARG;
+    const int nsub = (int)c->subs.size();
+    for (int s = 0; s < nsub; ++s) {
+        if (n) n[s] = c->subs[s].n;
+        if (factor_elems)
+            factor_elems[s] = (s + 1 < nsub ? c->subs[s + 1].diag_off : c->factor_elems) - c->subs[s].diag_off;
+    }
+    return GPLMM_OK;
+}
+
 int gplmm_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r) {
     if (!c) return GPLMM_E_ARG;
     if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
@@ -607,7 +619,7 @@ void gplmm_destroy(gplmm_ctx* c) {
     else hipDeviceSynchronize();
     gplmm_reset_timers(c);
     void* ptrs[] = {c->d_cidx, c->d_coord, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
-                    c->d_ucol, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
+                    c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_wind_f, c->d_r, c->d_tmp,

@@ -38,7 +38,7 @@ struct Sub {
     int n;                   // local unknowns
     int nT;                  // tiles per side
     int64_t slot_off;        // into sub_slots
-    int64_t env_off;         // into env arrays (tfc, tfr, lrow, ucol), nT entries each
+    int64_t env_off;         // into env arrays (tfc, tfr, tlc, lrow, urow), nT entries each
     int64_t diag_off;        // element offset of the first diagonal tile in the factor buffer
 };
 
@@ -84,7 +84,8 @@ struct gplmm_ctx {
     std::vector<gp::Sub> subs;        // [0, Np): primaries, [Np, Np + Nc): duals
     std::vector<int32_t> sub_slots;   // global slot of each local unknown, local order
     std::vector<int32_t> env_tfc, env_tfr;   // per tile row/col: first tile col/row of L/U
-    std::vector<int64_t> env_lrow, env_ucol; // element offsets of L tile-row / U tile-col starts
+    std::vector<int32_t> env_tlc;            // per tile row: last tile column of U (inclusive)
+    std::vector<int64_t> env_lrow, env_urow; // element offsets of the L and U tile rows
     int64_t factor_elems = 0;
     int maxT = 0;
     // LU schedule: per step K, (sub, I) pairs for the row-update kernel
@@ -124,7 +125,8 @@ struct gplmm_ctx {
     int32_t* d_tfc = nullptr;
     int32_t* d_tfr = nullptr;
     int64_t* d_lrow = nullptr;
-    int64_t* d_ucol = nullptr;
+    int64_t* d_urow = nullptr;
+    int32_t* d_tlc = nullptr;
     int32_t* d_step_pairs[2] = {nullptr, nullptr};
     int32_t* d_sub_list[2] = {nullptr, nullptr};
     void* d_factor = nullptr;            // real (float or double) tiles

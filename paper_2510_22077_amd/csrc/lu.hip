@@ -8,10 +8,12 @@
 //
 // Layout: each local matrix (n x n, unknowns in the pressure-after-faces
 // raster order) is cut into T x T tiles.  Lower tiles (I, J), J < I, exist for
-// J >= tfc[I] and are stored tile-row by tile-row; upper tiles (I, J), I < J,
-// exist for I >= tfr[J] and are stored tile-column by tile-column; tfc and tfr
-// are non-decreasing, so fill-in of an LU without pivoting stays inside (the
-// envelope property).  Tiles are row-major.  Pivoting is not needed in this
+// J >= tfc[I]; upper tiles (I, J), I < J, exist for I >= tfr[J], i.e. for
+// J <= tlc[I]; both are stored tile-row by tile-row (L row I: columns tfc[I]..
+// I-1, U row I: columns I+1..tlc[I]), so a substitution streams each factor
+// as one contiguous range.  tfc and tfr are non-decreasing, so fill-in of an
+// LU without pivoting stays inside (the envelope property).  Tiles are
+// row-major.  Pivoting is not needed in this
 // order: every pressure follows all of its faces, so each leading block is a
 // saddle-point matrix with a positive-real velocity block and a full-rank
 // divergence block.
@@ -27,15 +29,16 @@ struct Env {
     const Sub* subs;
     const int32_t* tfc;
     const int32_t* tfr;
+    const int32_t* tlc;
     const int64_t* lrow;
-    const int64_t* ucol;
+    const int64_t* urow;
 };
 
 template <typename T>
 __device__ __forceinline__ T* tile_ptr(T* F, const Env& e, const Sub& sb, int I, int J) {
     if (I == J) return F + sb.diag_off + (int64_t)I * kTT;
     if (J < I) return F + e.lrow[sb.env_off + I] + (int64_t)(J - e.tfc[sb.env_off + I]) * kTT;
-    return F + e.ucol[sb.env_off + J] + (int64_t)(I - e.tfr[sb.env_off + J]) * kTT;
+    return F + e.urow[sb.env_off + I] + (int64_t)(J - I - 1) * kTT;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -240,33 +243,34 @@ __global__ void __launch_bounds__(256) trsv_kernel(Env e, const T* __restrict__ 
             part[r] = b - acc;
         }
         __syncthreads();
-        if (tid < 64) {   // one wave: forward substitution inside the diagonal tile
-            const T* dt = F + sb.diag_off + (int64_t)I * kTT;
-            T v = tid < kT ? part[tid] : (T)0;
-            for (int k = 0; k < kT; ++k) {
-                T yk = __shfl(v, k, 64);
-                if (tid > k && tid < kT) v -= dt[tid * kT + k] * yk;
+        {   // y_I = inv(L_II) part: strictly lower part of the inverted tile, unit diagonal
+            const T* dt = F + sb.diag_off + (int64_t)I * kTT + r * kT + q * 4;
+            T v = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int k = q * 4 + m;
+                v += (k < r ? dt[m] : (k == r ? (T)1 : (T)0)) * part[k];
             }
-            if (tid < kT) x[I * kT + tid] = v;
+            v = wave_sum8(v);
+            if (q == 0) x[I * kT + r] = v;
         }
         __syncthreads();
     }
     // backward: U x = y, U stored by tile columns
     for (int J = sb.nT - 1; J >= 0; --J) {
-        if (tid < 64) {
-            const T* dt = F + sb.diag_off + (int64_t)J * kTT;
-            T v = tid < kT ? x[J * kT + tid] : (T)0;
-            for (int k = kT - 1; k >= 0; --k) {
-                T xk = __shfl(v, k, 64) / dt[k * kT + k];
-                if (tid == k) v = xk;
-                if (tid < k) v -= dt[tid * kT + k] * xk;
+        {   // x_J = inv(U_JJ) x_J: upper part (with diagonal) of the inverted tile
+            const T* dt = F + sb.diag_off + (int64_t)J * kTT + r * kT + q * 4;
+            T v = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int k = q * 4 + m;
+                if (k >= r) v += dt[m] * x[J * kT + k];
             }
-            if (tid < kT) {
-                x[J * kT + tid] = v;
-                yt[tid] = v;
-            }
+            v = wave_sum8(v);
+            if (q == 0) yt[r] = v;
         }
         __syncthreads();
+        if (tid < kT) x[J * kT + tid] = yt[tid];
         for (int I = tfr[J]; I < J; ++I) {
             const T* ut = tile_ptr(const_cast<T*>(F), e, sb, I, J);
             T acc = 0;
@@ -293,127 +297,182 @@ __device__ __forceinline__ T sum32(T v) {
     return v;
 }
 
-constexpr int kPF = 32;   // tiles of the next tile row prefetched into registers
-
+constexpr size_t kTrsvLdsMax = 64 * 1024;   // dynamic LDS bound for the in-LDS solve
+// tiles of a tile row (column) held per register buffer: 32 FP32 or 16 FP64 values per thread
 template <typename T>
+constexpr int pf_tiles() { return sizeof(T) == 4 ? 32 : 16; }
+
+template <typename T, int kPF>
+__device__ __forceinline__ void load_tiles(T (&buf)[kPF], const T* __restrict__ src, int n) {
+#pragma unroll
+    for (int t = 0; t < kPF; ++t)
+        if (t < n) buf[t] = src[(int64_t)t * kTT];
+}
+
+// kLds: the subdomain's solution vector lives in LDS (dynamic, nT * T entries) during
+// the solve and is written out once at the end; otherwise it is updated in place in
+// `out`.  Diagonal tiles hold inv(L_II) (strictly lower, unit diagonal implied) and
+// inv(U_II) (upper with diagonal), so each diagonal block is one 32 x 32 product.
+// Both substitutions are row-oriented (one 32-lane reduction per tile row); the tiles
+// of tile row I + 2 (I - 2 going backward) are loaded into registers while rows I and
+// I + 1 are processed (two register buffers), which keeps two rows of factor loads in
+// flight behind the dependency chain of the substitution.
+template <typename T, bool kLds>
 __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restrict__ F,
                                                         const int32_t* __restrict__ order,
                                                         const int32_t* __restrict__ slots, const T* __restrict__ vin,
                                                         T* __restrict__ out, const int64_t* __restrict__ off) {
+    constexpr int kPF = pf_tiles<T>();
+    extern __shared__ unsigned char dyn_lds[];
     __shared__ T part[kT];
-    __shared__ T xs[kT];
-    __shared__ T Dt[kT][kT + 1];
     const int s = order[blockIdx.x];
     const Sub sb = e.subs[s];
-    T* x = out + off[s];
-    const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
-    const int32_t* tfc = e.tfc + sb.env_off;
-    const int32_t* tfr = e.tfr + sb.env_off;
-    const int64_t* lrow = e.lrow + sb.env_off;
-    const int64_t* ucol = e.ucol + sb.env_off;
-    const int32_t* sl = slots + sb.slot_off;
     const int nT = sb.nT;
     if (nT == 0) return;
-    T pre[kPF];
-    // ---- forward: L y = b (y overwrites x); row I+1's tiles load while row I is solved
-    int ntp = 0;   // tiles held in pre[] for the current row
-#pragma unroll
-    for (int t = 0; t < kPF; ++t) pre[t] = 0;
-    for (int I = 0; I < nT; ++I) {
+    T* xo = out + off[s];
+    T* x = kLds ? reinterpret_cast<T*>(dyn_lds) : xo;
+    const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
+    const int32_t* tfc = e.tfc + sb.env_off;
+    const int32_t* tlc = e.tlc + sb.env_off;
+    const int64_t* lrow = e.lrow + sb.env_off;
+    const int64_t* urow = e.urow + sb.env_off;
+    const int32_t* sl = slots + sb.slot_off;
+    const T* D = F + sb.diag_off + tid;
+    const int len = nT * kT;
+    for (int i = tid; i < len; i += 1024) x[i] = i < sb.n ? vin[sl[i]] : (T)0;
+    T bufA[kPF], bufB[kPF];
+    int nA = 0, nB = 0;
+    T dA = D[0], dB = 0;
+    if (nT > 1) {
+        nB = min(1 - tfc[1], kPF);
+        load_tiles(bufB, F + lrow[1] + tid, nB);
+        dB = D[kTT];
+    }
+    __syncthreads();
+    // ---- forward: L y = b, row-oriented over L's contiguous tile rows
+    auto fwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
         const int j0 = tfc[I], nt = I - j0;
-        const T dval = F[sb.diag_off + (int64_t)I * kTT + tid];
-        const T b = (c == 0 && I * kT + r < sb.n) ? vin[sl[I * kT + r]] : (T)0;
         const T* y = x + j0 * kT + c;
+        const T dv = db;
         T acc = 0;
 #pragma unroll
         for (int t = 0; t < kPF; ++t)
-            if (t < ntp) acc += pre[t] * y[t * kT];
+            if (t < nb) acc += buf[t] * y[t * kT];
         const T* Lr = F + lrow[I] + tid;
         for (int t = kPF; t < nt; ++t) acc += Lr[(int64_t)t * kTT] * y[t * kT];
-        if (I + 1 < nT) {   // prefetch the next tile row
-            const int ntn = I + 1 - tfc[I + 1];
-            const T* Ln = F + lrow[I + 1] + tid;
-#pragma unroll
-            for (int t = 0; t < kPF; ++t)
-                if (t < ntn) pre[t] = Ln[(int64_t)t * kTT];
-            ntp = min(ntn, kPF);
+        if (I + 2 < nT) {
+            nb = min(I + 2 - tfc[I + 2], kPF);
+            load_tiles(buf, F + lrow[I + 2] + tid, nb);
+            db = D[(int64_t)(I + 2) * kTT];
         }
         acc = sum32(acc);
-        Dt[r][c] = dval;
-        if (c == 0) part[r] = b - acc;
+        if (c == 0) part[r] = x[I * kT + r] - acc;
         __syncthreads();
-        if (tid < 64) {
-            T v = tid < kT ? part[tid] : (T)0;
-            const int rr = tid < kT ? tid : 0;
-            for (int k = 0; k < kT; ++k) {
-                T yk = __shfl(v, k, 64);
-                if (tid > k && tid < kT) v -= Dt[rr][k] * yk;
-            }
-            if (tid < kT) x[I * kT + tid] = v;
-        }
+        const T v = sum32((c < r ? dv : (c == r ? (T)1 : (T)0)) * part[c]);
+        if (c == 0) x[I * kT + r] = v;
         __syncthreads();
+    };
+    for (int I = 0; I < nT; I += 2) {
+        fwd_row(I, bufA, nA, dA);
+        if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
     }
-    // ---- backward: U x = y, column-oriented (push) over U's contiguous tile columns
-    {
-        const int J = nT - 1;
-        const int ntn = J - tfr[J];
-        const T* Un = F + ucol[J] + tid;
+    // ---- backward: U x = y, row-oriented over U's contiguous tile rows (descending)
+    auto bwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
+        const int nt = tlc[I] - I;
+        const T* y = x + (I + 1) * kT + c;
+        const T dv = db;
+        T acc = 0;
 #pragma unroll
         for (int t = 0; t < kPF; ++t)
-            if (t < ntn) pre[t] = Un[(int64_t)t * kTT];
-        ntp = min(ntn, kPF);
+            if (t < nb) acc += buf[t] * y[t * kT];
+        const T* Ur = F + urow[I] + tid;
+        for (int t = kPF; t < nt; ++t) acc += Ur[(int64_t)t * kTT] * y[t * kT];
+        if (I >= 2) {
+            nb = min(tlc[I - 2] - (I - 2), kPF);
+            load_tiles(buf, F + urow[I - 2] + tid, nb);
+            db = D[(int64_t)(I - 2) * kTT];
+        }
+        acc = sum32(acc);
+        if (c == 0) part[r] = x[I * kT + r] - acc;
+        __syncthreads();
+        const T v = sum32((c >= r ? dv : (T)0) * part[c]);
+        if (c == 0) x[I * kT + r] = v;
+        __syncthreads();
+    };
+    {
+        const int I = nT - 1;
+        nA = min(tlc[I] - I, kPF);
+        load_tiles(bufA, F + urow[I] + tid, nA);
+        dA = D[(int64_t)I * kTT];
+        if (I >= 1) {
+            nB = min(tlc[I - 1] - (I - 1), kPF);
+            load_tiles(bufB, F + urow[I - 1] + tid, nB);
+            dB = D[(int64_t)(I - 1) * kTT];
+        }
     }
-    for (int J = nT - 1; J >= 0; --J) {
-        Dt[r][c] = F[sb.diag_off + (int64_t)J * kTT + tid];
+    for (int I = nT - 1; I >= 0; I -= 2) {
+        bwd_row(I, bufA, nA, dA);
+        if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+    }
+    if (kLds)
+        for (int i = tid; i < len; i += 1024) xo[i] = x[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// After a set is factorised: replace every diagonal tile (packed unit-lower L and upper U)
+// by its packed inverses, inv(L) strictly below the diagonal and inv(U) on and above it.
+// Columns are computed in FP64 by substitution (thread c: column c of inv(L); thread
+// 32 + c: column c of inv(U)).  One 64-thread block per (subdomain, tile stride).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) invert_diag_kernel(Env e, T* __restrict__ F, int first_sub) {
+    __shared__ double A[kT][kT + 1];
+    __shared__ double X[kT][kT + 1];
+    const Sub sb = e.subs[first_sub + blockIdx.x];
+    const int tid = threadIdx.x, c = tid & 31;
+    const bool up = tid >= kT;
+    for (int I = blockIdx.y; I < sb.nT; I += gridDim.y) {
+        T* dp = F + sb.diag_off + (int64_t)I * kTT;
         __syncthreads();
-        if (tid < 64) {
-            T v = tid < kT ? x[J * kT + tid] : (T)0;
-            const int rr = tid < kT ? tid : 0;
-            for (int k = kT - 1; k >= 0; --k) {
-                T xk = __shfl(v, k, 64) / Dt[k][k];
-                if (tid == k) v = xk;
-                if (tid < k) v -= Dt[rr][k] * xk;
+        for (int x = tid; x < kTT; x += 64) A[x / kT][x % kT] = (double)dp[x];
+        __syncthreads();
+        double col[kT];
+        if (!up) {   // inv(L) e_c, L unit lower
+#pragma unroll
+            for (int i = 0; i < kT; ++i) {
+                double v = i == c ? 1.0 : 0.0;
+                if (i > c) {
+#pragma unroll
+                    for (int k = 0; k < i; ++k)
+                        if (k >= c) v -= A[i][k] * col[k];
+                }
+                col[i] = i < c ? 0.0 : v;
             }
-            if (tid < kT) {
-                x[J * kT + tid] = v;
-                xs[tid] = v;
+        } else {      // inv(U) e_c, U upper
+#pragma unroll
+            for (int i = kT - 1; i >= 0; --i) {
+                double v = i == c ? 1.0 : 0.0;
+                if (i <= c) {
+#pragma unroll
+                    for (int k = i + 1; k < kT; ++k)
+                        if (k <= c) v -= A[i][k] * col[k];
+                }
+                col[i] = i > c ? 0.0 : v / A[i][i];
             }
         }
         __syncthreads();
-        const int i0 = tfr[J], nt = J - i0;
-        const T xc = xs[c];
-        T cur[kPF];
 #pragma unroll
-        for (int t = 0; t < kPF; ++t) cur[t] = pre[t];
-        const int ntc = ntp;
-        if (J > 0) {   // prefetch the next tile column
-            const int ntn = J - 1 - tfr[J - 1];
-            const T* Un = F + ucol[J - 1] + tid;
-#pragma unroll
-            for (int t = 0; t < kPF; ++t)
-                if (t < ntn) pre[t] = Un[(int64_t)t * kTT];
-            ntp = min(ntn, kPF);
-        }
-#pragma unroll
-        for (int t = 0; t < kPF; ++t) {
-            if (t < ntc) {
-                T v = sum32(cur[t] * xc);
-                if (c == 0) x[(i0 + t) * kT + r] -= v;
-            }
-        }
-        const T* Uc = F + ucol[J] + tid;
-        for (int t = kPF; t < nt; ++t) {
-            T v = sum32(Uc[(int64_t)t * kTT] * xc);
-            if (c == 0) x[(i0 + t) * kT + r] -= v;
-        }
+        for (int i = 0; i < kT; ++i)
+            if (up ? (i <= c) : (i > c)) X[i][c] = col[i];
         __syncthreads();
+        for (int x = tid; x < kTT; x += 64) dp[x] = (T)X[x / kT][x % kT];
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------------------
-static Env make_env(gplmm_ctx* c) { return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow, c->d_ucol}; }
+static Env make_env(gplmm_ctx* c) { return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_tlc, c->d_lrow, c->d_urow}; }
 
 template <typename T>
 int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure) {
@@ -447,6 +506,9 @@ int factor_set(gplmm_ctx* c, int set) {
         int np = (int)(poff[K + 1] - poff[K]);
         if (np > 0) lu_row_kernel<T><<<np, 256, 0, c->stream>>>(e, F, c->d_step_pairs[set] + 2 * poff[K], K);
     }
+    const int nsub = set == 0 ? c->Np : c->Np + c->Nc;
+    if (nsub > 0)
+        invert_diag_kernel<T><<<dim3(nsub, (unsigned)std::min(c->maxT, 16)), 64, 0, c->stream>>>(e, F, 0);
     return GPLMM_OK;
 }
 
@@ -465,8 +527,13 @@ void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vi
                          c->subs[s0].slot_off;
     const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)rows * (3.0 * sizeof(T) + 4.0);
     timer_begin(c, "trsv");
-    trsv_sub_kernel<T><<<nsub, 1024, 0, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set], c->d_sub_slots,
-                                                     vin, out_local, c->d_local_off);
+    const size_t lds = (size_t)c->maxT * kT * sizeof(T);
+    if (lds <= kTrsvLdsMax)
+        trsv_sub_kernel<T, true><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
+                                                                c->d_sub_slots, vin, out_local, c->d_local_off);
+    else
+        trsv_sub_kernel<T, false><<<nsub, 1024, 0, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
+                                                               c->d_sub_slots, vin, out_local, c->d_local_off);
     timer_end(c, "trsv", bytes);
 }
 

@@ -399,7 +399,8 @@ int build_local_problems(gplmm_ctx* c) {
     c->env_tfc.clear();
     c->env_tfr.clear();
     c->env_lrow.clear();
-    c->env_ucol.clear();
+    c->env_urow.clear();
+    c->env_tlc.clear();
     std::vector<std::vector<int32_t>> prim_cells(c->Np);
     for (int64_t q = 0; q < c->ncell; ++q)
         if (c->prim[q] >= 0) prim_cells[c->prim[q]].push_back((int32_t)q);
@@ -466,9 +467,13 @@ int build_local_problems(gplmm_ctx* c) {
             c->env_lrow.push_back(elems);
             elems += (int64_t)(I - tfc[I]) * T * T;
         }
-        for (int J = 0; J < sb.nT; ++J) {
-            c->env_ucol.push_back(elems);
-            elems += (int64_t)(J - tfr[J]) * T * T;
+        // U by tile rows: row I holds columns I+1 .. tlc[I], tlc[I] = last J with tfr[J] <= I
+        for (int I = 0, J = 0; I < sb.nT; ++I) {
+            while (J + 1 < sb.nT && tfr[J + 1] <= I) ++J;
+            const int last = std::max(J, I);
+            c->env_tlc.push_back(last);
+            c->env_urow.push_back(elems);
+            elems += (int64_t)(last - I) * T * T;
         }
     }
     c->factor_elems = elems;
