@@ -67,18 +67,10 @@ int upload_all(gplmm_ctx* c) {
     const int64_t nc = c->ncell, N = c->N;
     const int T = c->tile;
     // geometry
-    std::vector<uint32_t> coord(nc);
-    for (int64_t q = 0; q < nc; ++q) {
-        int64_t v = c->cell_voxel[q];
-        uint32_t i = (uint32_t)(v % c->nx), j = (uint32_t)((v / c->nx) % c->ny),
-                 k = (uint32_t)(v / ((int64_t)c->nx * c->ny));
-        coord[q] = i | (j << 10) | (k << 20);
-    }
-    GP_TRY(upload(c, &c->d_cidx, c->cidx));
-    GP_TRY(upload(c, &c->d_coord, coord));
+    GP_TRY(upload(c, &c->d_nb6, c->nbr));
     GP_TRY(upload(c, &c->d_tag, c->tagcell));
     c->geo = DevGeo{c->nx, c->ny, c->nz, c->ndim, c->nrec, {c->opt.periodic[0], c->opt.periodic[1], c->opt.periodic[2]},
-                    nc, (int)c->pin, c->opt.h, c->d_cidx, c->d_coord, c->d_tag};
+                    nc, (int)c->pin, c->opt.h, c->d_nb6, c->d_tag};
     // local problems
     const int nsub = c->Np + c->Nc;
     std::vector<int32_t> row_sub(c->sub_slots.size()), sorted_slot(c->sub_slots.size()), sorted_loc(c->sub_slots.size());
@@ -226,7 +218,9 @@ int upload_all(gplmm_ctx* c) {
     // vectors
     const int m = c->opt.restart;
     GP_TRY(alloc(c, (void**)&c->d_wind, sizeof(double) * N));
-    if (c->opt.precision == GPLMM_FP32) GP_TRY(alloc(c, (void**)&c->d_wind_f, sizeof(float) * N));
+    const int64_t ncoef = (int64_t)(1 + 2 * c->ndim) * c->ndim * nc;
+    GP_TRY(alloc(c, (void**)&c->d_xcoef, sizeof(double) * ncoef));
+    if (c->opt.precision == GPLMM_FP32) GP_TRY(alloc(c, (void**)&c->d_xcoef_f, sizeof(float) * ncoef));
     GP_TRY(alloc(c, (void**)&c->d_r, sizeof(double) * N));
     GP_TRY(alloc(c, (void**)&c->d_tmp, sizeof(double) * N));
     GP_TRY(alloc(c, (void**)&c->d_dx, sizeof(double) * N));
@@ -242,8 +236,8 @@ int upload_all(gplmm_ctx* c) {
 int do_build(gplmm_ctx* c) {
     auto t0 = std::chrono::steady_clock::now();
     int rc;
+    launch_xcoef(c, c->stream);
     if (c->opt.precision == GPLMM_FP32) {
-        convert<double, float>(c, c->d_wind, c->d_wind_f, c->N);
         rc = build_precond<float>(c);
     } else {
         rc = build_precond<double>(c);
@@ -386,6 +380,10 @@ int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double m
     if (rc == GPLMM_OK) rc = build_local_problems(c);
     if (rc == GPLMM_OK) rc = build_probing(c);
     if (rc == GPLMM_OK && !c->opt.host_only) rc = upload_all(c);
+    if (rc == GPLMM_OK && !c->opt.host_only) {   // X of the zero wind until the first build
+        launch_xcoef(c, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) rc = gp::fail(c, GPLMM_E_HIP, "coefficient table");
+    }
     if (rc == GPLMM_OK && !c->opt.host_only) {
         // algorithmic bytes of one preconditioner application (for roofline reporting):
         // every local factor read once, the shape vectors once, the coarse inverse once,
@@ -393,7 +391,7 @@ int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double m
         const double rs = (double)real_size(c);
         c->apply_bytes = rs * (double)c->factor_elems + rs * (double)c->phi_elems +
                          8.0 * (double)c->nco * c->nco + 16.0 * rs * (double)c->N;
-        c->jv_bytes = 8.0 * 3.0 * (double)c->N + 4.0 * (double)c->nvox;
+        c->jv_bytes = 8.0 * 3.0 * (double)c->N + 24.0 * (double)c->ncell;
         c->ready = true;
     }
     *out = c;
@@ -618,11 +616,11 @@ void gplmm_destroy(gplmm_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     gplmm_reset_timers(c);
-    void* ptrs[] = {c->d_cidx, c->d_coord, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
+    void* ptrs[] = {c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
-                    c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_wind_f, c->d_r, c->d_tmp,
+                    c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_r, c->d_tmp,
                     c->d_dx, c->d_zero, c->d_V, c->d_Z, c->d_red, c->d_pv, c->d_local, c->d_cv, c->d_row_sub,
                     c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids,
                     c->d_noclose, c->d_Aoasm, c->d_sub_order[0], c->d_sub_order[1]};

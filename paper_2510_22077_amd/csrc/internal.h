@@ -22,8 +22,7 @@ struct DevGeo {
     int64_t ncell;
     int pin;                 // pinned cell
     double h;
-    const int32_t* cidx;     // voxel -> cell or -1 (nx*ny*nz)
-    const uint32_t* coord;   // cell -> i | j << 10 | k << 20
+    const int32_t* nb6;      // cell * 6 + 2 d + t -> cell -/+ e_d (periodic wrap) or -1
     const uint8_t* tag;      // cell -> bit a: lower a-face carries no inertia in X
 };
 
@@ -110,8 +109,9 @@ struct gplmm_ctx {
 
     // ---- device buffers
     gp::DevGeo geo{};
-    int32_t* d_cidx = nullptr;
-    uint32_t* d_coord = nullptr;
+    int32_t* d_nb6 = nullptr;
+    double* d_xcoef = nullptr;           // tabulated momentum rows of X, FP64
+    float* d_xcoef_f = nullptr;          // the same in FP32 (FP32 preconditioner)
     uint8_t* d_tag = nullptr;
     int32_t* d_sub_slots = nullptr;      // local order, concatenated over subs
     int32_t* d_row_sub = nullptr;        // sub of each concatenated row
@@ -155,7 +155,6 @@ struct gplmm_ctx {
 
     // work vectors (FP64 unless noted)
     double* d_wind = nullptr;            // N
-    float* d_wind_f = nullptr;           // N (FP32 builds)
     double* d_r = nullptr;
     double* d_tmp = nullptr;
     double* d_dx = nullptr;
@@ -197,6 +196,7 @@ void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double*
 void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s);
 template <typename T>
 void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s);
+void launch_xcoef(gplmm_ctx* c, hipStream_t s);
 void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s);
 
 // krylov.hip

@@ -42,48 +42,73 @@ __device__ __forceinline__ T* tile_ptr(T* F, const Env& e, const Sub& sb, int I,
 }
 
 // ---------------------------------------------------------------------------------------
-// Assembly: one thread per local row; rows of X = J~_w gathered through the slot lists.
-// closure != 0 (primaries only): entries in columns of f-faces or of other primaries'
-// unknowns are added to the diagonal (Section 3.2.2, both reduction steps).
+// Assembly: one thread per local row; the row of X = J~_w comes from the tabulated
+// momentum coefficients (or the mass / pin row), its columns are located in the
+// subdomain through the sorted slot list.  closure != 0 (primaries only): entries in
+// columns of f-faces or of other primaries' unknowns are added to the diagonal
+// (Section 3.2.2, both reduction steps), except on rows of wall-free faces.
 // ---------------------------------------------------------------------------------------
-template <typename T, typename W>
-__global__ void assemble_kernel(DevGeo g, Phys ph, const W* __restrict__ wind, Env e, T* __restrict__ F,
+template <int ND, typename T>
+__global__ void assemble_kernel(DevGeo g, const double* __restrict__ coef, Env e, T* __restrict__ F,
                                 const int32_t* __restrict__ row_sub, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ sorted_slot, const int32_t* __restrict__ sorted_loc,
                                 const int32_t* __restrict__ slot_class, const uint8_t* __restrict__ noclose,
                                 int64_t nrows, int first_sub, int nsub, int closure) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nrows) return;
     const int s = row_sub[t];
     if (s < first_sub || s >= first_sub + nsub) return;
+    constexpr int nr = ND + 1;
     const Sub sb = e.subs[s];
     const int r = (int)(t - sb.slot_off);
     const int64_t gs = slots[t];
-    const int64_t c = gs / g.nrec;
-    const int comp = (int)(gs % g.nrec);
-    Nbhd nb;
-    load_nbhd(g, c, nb);
-    int64_t cols[kMaxRow];
-    double vals[kMaxRow];
-    const int cnt = x_row(g, ph, nb, c, comp, wind, cols, vals);
+    const int64_t c = gs / nr;
+    const int comp = (int)(gs % nr);
     if (noclose[gs]) closure = 0;
     double diag_extra = 0.0;
     const int32_t* ss = sorted_slot + sb.slot_off;
     const int32_t* sl = sorted_loc + sb.slot_off;
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t col = (int32_t)cols[k];
-        int lo = 0, hi = sb.n;  // binary search in the sub's sorted slots
+    auto emit = [&](int64_t col64, double val) {
+        const int32_t col = (int32_t)col64;
+        int lo = 0, hi = sb.n;   // binary search in the subdomain's sorted slots
         while (lo < hi) {
-            int mid = (lo + hi) >> 1;
+            const int mid = (lo + hi) >> 1;
             if (ss[mid] < col) lo = mid + 1; else hi = mid;
         }
         if (lo < sb.n && ss[lo] == col) {
             const int lc = sl[lo];
             T* tp = tile_ptr(F, e, sb, r / kT, lc / kT);
-            tp[(r % kT) * kT + (lc % kT)] += (T)vals[k];
+            tp[(r % kT) * kT + (lc % kT)] += (T)val;
         } else if (closure) {
             const int32_t cls = slot_class[col];
-            if (cls == -1 || (cls >= 0 && cls != sb.id)) diag_extra += vals[k];
+            if (cls == -1 || (cls >= 0 && cls != sb.id)) diag_extra += val;
+        }
+    };
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const double ih = 1.0 / g.h;
+    const int64_t nce = g.ncell;
+    if (comp < ND) {
+        const int a = comp;
+        const int32_t L = nc.n[a][0];
+        if (L >= 0) {
+            const Nb<ND> nl = load_nb<ND>(g, L);
+            const FaceNb<ND> f = face_nb(nc, nl, a);
+            emit(gs, coef[a * nce + c]);
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (f.kind[d][q] == kActive) emit((int64_t)nr * f.P[d][q] + a, coef[((1 + 2 * d + q) * ND + a) * nce + c]);
+            emit(nr * c + ND, ih);
+            emit((int64_t)nr * L + ND, -ih);
+        }
+    } else if (c == g.pin) {
+        emit(gs, 1.0);
+    } else {
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            if (nc.n[a][0] >= 0) emit(nr * c + a, ih);
+            if (nc.n[a][1] >= 0) emit((int64_t)nr * nc.n[a][1] + a, -ih);
         }
     }
     if (diag_extra != 0.0) {
@@ -480,15 +505,14 @@ int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure) {
     T* F = (T*)c->d_factor;
     const int64_t nrows = (int64_t)c->sub_slots.size();
     const unsigned nb = (unsigned)((nrows + 255) / 256);
-    if (c->opt.precision == GPLMM_FP32 && c->d_wind_f)
-        assemble_kernel<T, float><<<nb, 256, 0, c->stream>>>(c->geo, c->phys, c->d_wind_f, e, F, c->d_row_sub,
-                                                             c->d_sub_slots, c->d_sorted_slot, c->d_sorted_loc,
-                                                             c->d_slot_class, c->d_noclose, nrows, first_sub, nsub, closure ? 1 : 0);
+    if (c->ndim == 3)
+        assemble_kernel<3, T><<<nb, 256, 0, c->stream>>>(c->geo, c->d_xcoef, e, F, c->d_row_sub, c->d_sub_slots,
+                                                         c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class,
+                                                         c->d_noclose, nrows, first_sub, nsub, closure ? 1 : 0);
     else
-        assemble_kernel<T, double><<<nb, 256, 0, c->stream>>>(c->geo, c->phys, c->d_wind, e, F, c->d_row_sub,
-                                                              c->d_sub_slots, c->d_sorted_slot, c->d_sorted_loc,
-                                                              c->d_slot_class, c->d_noclose, nrows, first_sub, nsub,
-                                                              closure ? 1 : 0);
+        assemble_kernel<2, T><<<nb, 256, 0, c->stream>>>(c->geo, c->d_xcoef, e, F, c->d_row_sub, c->d_sub_slots,
+                                                         c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class,
+                                                         c->d_noclose, nrows, first_sub, nsub, closure ? 1 : 0);
     if (nsub > 0) pad_kernel<T><<<nsub, 64, 0, c->stream>>>(e, F, first_sub, nsub);
     return GPLMM_OK;
 }

@@ -13,6 +13,11 @@
 // rho * sum_d a_d D_d u with a_x = u_F and transverse a_d the mean of the four
 // d-faces of the face's two cells; gradient (p_R - p_L)/h; mass row -div u;
 // the pinned cell's mass row is p = 0.
+//
+// X is fixed between builds, so its momentum rows are tabulated once per build
+// (kNC coefficients per face, structure of arrays over cells); X v is then a
+// gather over the face's stencil with no classification work.  The Newton
+// Jacobian changes with every Newton iterate and is applied matrix-free.
 #include "internal.h"
 #include "stencil_dev.h"
 
@@ -23,29 +28,34 @@ namespace {
 constexpr int kBlock = 256;
 
 // r(x): momentum and mass residual.
-__global__ void residual_kernel(DevGeo g, Phys ph, const double* __restrict__ x,
-                                const double* __restrict__ xold, double* __restrict__ r) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int ND>
+__global__ void __launch_bounds__(kBlock) residual_kernel(DevGeo g, Phys ph, const double* __restrict__ x,
+                                                          const double* __restrict__ xold, double* __restrict__ r) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
-    Nbhd nb;
-    load_nbhd(g, c, nb);
-    const int nd = g.ndim, nr = g.nrec;
-    const double h = g.h, ih = 1.0 / h, vis = ph.mu / (h * h);
-    for (int a = 0; a < nd; ++a) {
+    constexpr int nr = ND + 1;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const double ih = 1.0 / g.h, vis = ph.mu * ih * ih;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
         double out = 0.0;
-        if (nb.L[a] >= 0) {
+        const int32_t L = nc.n[a][0];
+        if (L >= 0) {
+            const Nb<ND> nl = load_nb<ND>(g, L);
+            const FaceNb<ND> f = face_nb(nc, nl, a);
             const double uF = x[nr * c + a];
-            FaceKinds fk;
-            classify(g, nb, a, fk);
             double visc = 0.0;
-            for (int d = 0; d < nd; ++d)
-                for (int t = 0; t < 2; ++t) visc += uF - nbval(fk, d, t, x, nr, a, uF);
-            out = vis * visc + (x[nr * c + nd] - x[nr * (int64_t)nb.L[a] + nd]) * ih - ph.rho * ph.body[a];
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) visc += uF - nb_value(f, d, t, x, nr, a, uF);
+            out = vis * visc + (x[nr * c + ND] - x[(int64_t)nr * L + ND]) * ih - ph.rho * ph.body[a];
             if (ph.dt > 0.0) out += ph.rho * (uF - (xold ? xold[nr * c + a] : 0.0)) / ph.dt;
             double conv = 0.0;
-            for (int d = 0; d < nd; ++d) {
-                double ad = advecting(g, nb, a, d, x, c);
-                double gm = nbval(fk, d, 0, x, nr, a, uF), gp_ = nbval(fk, d, 1, x, nr, a, uF);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const double ad = advecting(nc, nl, c, L, a, d, x, nr);
+                const double gm = nb_value(f, d, 0, x, nr, a, uF), gp_ = nb_value(f, d, 1, x, nr, a, uF);
                 conv += ad * (ad >= 0.0 ? (uF - gm) : (gp_ - uF)) * ih;
             }
             out += ph.rho * conv;
@@ -54,45 +64,52 @@ __global__ void residual_kernel(DevGeo g, Phys ph, const double* __restrict__ x,
     }
     double m;
     if (c == g.pin) {
-        m = x[nr * c + nd];
+        m = x[nr * c + ND];
     } else {
         m = 0.0;
-        for (int a = 0; a < nd; ++a) {
-            double up = nb.n[a][1] >= 0 ? x[nr * (int64_t)nb.n[a][1] + a] : 0.0;
-            double lo = nb.L[a] >= 0 ? x[nr * c + a] : 0.0;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            const double up = nc.n[a][1] >= 0 ? x[(int64_t)nr * nc.n[a][1] + a] : 0.0;
+            const double lo = nc.n[a][0] >= 0 ? x[nr * c + a] : 0.0;
             m -= (up - lo) * ih;
         }
     }
-    r[nr * c + nd] = m;
+    r[nr * c + ND] = m;
 }
 
-// y = J(xk) v with upwind branches frozen at xk.
-__global__ void jv_kernel(DevGeo g, Phys ph, const double* __restrict__ xk, const double* __restrict__ v,
-                          double* __restrict__ y) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// y = J(xk) v with the upwind branches frozen at xk.
+template <int ND>
+__global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph, const double* __restrict__ xk,
+                                                    const double* __restrict__ v, double* __restrict__ y) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
-    Nbhd nb;
-    load_nbhd(g, c, nb);
-    const int nd = g.ndim, nr = g.nrec;
-    const double h = g.h, ih = 1.0 / h, vis = ph.mu / (h * h);
-    for (int a = 0; a < nd; ++a) {
+    constexpr int nr = ND + 1;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const double ih = 1.0 / g.h, vis = ph.mu * ih * ih;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
         double out = 0.0;
-        if (nb.L[a] >= 0) {
+        const int32_t L = nc.n[a][0];
+        if (L >= 0) {
+            const Nb<ND> nl = load_nb<ND>(g, L);
+            const FaceNb<ND> f = face_nb(nc, nl, a);
             const double uF = xk[nr * c + a], vF = v[nr * c + a];
-            FaceKinds fk;
-            classify(g, nb, a, fk);
             double visc = 0.0;
-            for (int d = 0; d < nd; ++d)
-                for (int t = 0; t < 2; ++t) visc += vF - nbval(fk, d, t, v, nr, a, vF);
-            out = vis * visc + (v[nr * c + nd] - v[nr * (int64_t)nb.L[a] + nd]) * ih;
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) visc += vF - nb_value(f, d, t, v, nr, a, vF);
+            out = vis * visc + (v[nr * c + ND] - v[(int64_t)nr * L + ND]) * ih;
             if (ph.dt > 0.0) out += ph.rho * vF / ph.dt;
             double conv = 0.0;
-            for (int d = 0; d < nd; ++d) {
-                double ad = advecting(g, nb, a, d, xk, c);
-                double adv = advecting(g, nb, a, d, v, c);
-                bool bw = ad >= 0.0;
-                double Du = bw ? (uF - nbval(fk, d, 0, xk, nr, a, uF)) : (nbval(fk, d, 1, xk, nr, a, uF) - uF);
-                double Dv = bw ? (vF - nbval(fk, d, 0, v, nr, a, vF)) : (nbval(fk, d, 1, v, nr, a, vF) - vF);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const double ad = advecting(nc, nl, c, L, a, d, xk, nr);
+                const double adv = advecting(nc, nl, c, L, a, d, v, nr);
+                const int t = ad >= 0.0 ? 0 : 1;
+                const double gu = nb_value(f, d, t, xk, nr, a, uF), gv = nb_value(f, d, t, v, nr, a, vF);
+                const double Du = t == 0 ? uF - gu : gu - uF;
+                const double Dv = t == 0 ? vF - gv : gv - vF;
                 conv += (ad * Dv + adv * Du) * ih;
             }
             out += ph.rho * conv;
@@ -101,46 +118,103 @@ __global__ void jv_kernel(DevGeo g, Phys ph, const double* __restrict__ xk, cons
     }
     double m;
     if (c == g.pin) {
-        m = v[nr * c + nd];
+        m = v[nr * c + ND];
     } else {
         m = 0.0;
-        for (int a = 0; a < nd; ++a) {
-            double up = nb.n[a][1] >= 0 ? v[nr * (int64_t)nb.n[a][1] + a] : 0.0;
-            double lo = nb.L[a] >= 0 ? v[nr * c + a] : 0.0;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            const double up = nc.n[a][1] >= 0 ? v[(int64_t)nr * nc.n[a][1] + a] : 0.0;
+            const double lo = nc.n[a][0] >= 0 ? v[nr * c + a] : 0.0;
             m -= (up - lo) * ih;
         }
     }
-    y[nr * c + nd] = m;
+    y[nr * c + ND] = m;
 }
 
-// y = a - X b  (a == nullptr: y = X b), X = J~_w with tags; T = float or double.
-template <typename T, typename W>
-__global__ void xv_kernel(DevGeo g, Phys ph, const W* __restrict__ wind, const T* __restrict__ a,
-                          const T* __restrict__ b, T* __restrict__ y) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Momentum rows of X = J~_w: coef[(k * ND + a) * ncell + c], k = 0 diagonal, k = 1 + 2 d + t
+// neighbour face (d, t); all zero for an inactive face.  FP64 and, if cf32 != nullptr, FP32.
+template <int ND>
+__global__ void __launch_bounds__(kBlock) xcoef_kernel(DevGeo g, Phys ph, const double* __restrict__ wind,
+                                                       double* __restrict__ cf64, float* __restrict__ cf32) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
-    Nbhd nb;
-    load_nbhd(g, c, nb);
-    const int nr = g.nrec;
-    for (int comp = 0; comp < nr; ++comp) {
-        int64_t cols[kMaxRow];
-        double vals[kMaxRow];
-        int cnt = x_row(g, ph, nb, c, comp, wind, cols, vals);
-        T acc = 0;
-        for (int k = 0; k < cnt; ++k) acc += (T)vals[k] * b[cols[k]];
-        int64_t s = (int64_t)nr * c + comp;
-        y[s] = a ? (T)(a[s] - acc) : acc;
+    constexpr int nr = ND + 1;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const int64_t nce = g.ncell;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        double co[kNC];
+#pragma unroll
+        for (int k = 0; k < kNC; ++k) co[k] = 0.0;
+        const int32_t L = nc.n[a][0];
+        if (L >= 0) {
+            const Nb<ND> nl = load_nb<ND>(g, L);
+            const FaceNb<ND> f = face_nb(nc, nl, a);
+            const bool tagged = (g.tag[c] >> a) & 1u;
+            x_face_coefs(ph, g.h, nc, nl, f, c, a, tagged ? (const double*)nullptr : wind, nr, co);
+        }
+#pragma unroll
+        for (int k = 0; k < 1 + 2 * ND; ++k) {
+            cf64[(k * ND + a) * nce + c] = co[k];
+            if (cf32) cf32[(k * ND + a) * nce + c] = (float)co[k];
+        }
     }
 }
 
-// b_B = -r(u = 0, p = 0) of the steady equations: rho * body on every active face.
-__global__ void bB_kernel(DevGeo g, Phys ph, double* __restrict__ out) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// y = a - X b  (a == nullptr: y = X b) from the tabulated rows.
+template <int ND, typename T>
+__global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restrict__ coef, const T* __restrict__ a,
+                                                    const T* __restrict__ b, T* __restrict__ y) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
-    Nbhd nb;
-    load_nbhd(g, c, nb);
-    for (int a = 0; a < g.ndim; ++a) out[g.nrec * c + a] = nb.L[a] >= 0 ? ph.rho * ph.body[a] : 0.0;
-    out[g.nrec * c + g.ndim] = 0.0;
+    constexpr int nr = ND + 1;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const int64_t nce = g.ncell;
+    const T ih = (T)(1.0 / g.h);
+    const T pc = b[nr * c + ND];
+#pragma unroll
+    for (int ax = 0; ax < ND; ++ax) {
+        const int64_t s = nr * c + ax;
+        T acc = 0;
+        const int32_t L = nc.n[ax][0];
+        if (L >= 0) {
+            acc = coef[ax * nce + c] * b[s] + ih * (pc - b[(int64_t)nr * L + ND]);
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const T w = coef[((1 + 2 * d + t) * ND + ax) * nce + c];
+                    const int32_t P = nc.n[d][t];   // (ax, t = 0) -> L itself
+                    if (w != (T)0 && P >= 0) acc += w * b[(int64_t)nr * P + ax];
+                }
+        }
+        y[s] = a ? (T)(a[s] - acc) : acc;
+    }
+    T m;
+    if (c == g.pin) {
+        m = pc;
+    } else {
+        m = 0;
+#pragma unroll
+        for (int ax = 0; ax < ND; ++ax) {
+            if (nc.n[ax][0] >= 0) m += ih * b[nr * c + ax];
+            if (nc.n[ax][1] >= 0) m -= ih * b[(int64_t)nr * nc.n[ax][1] + ax];
+        }
+    }
+    const int64_t s = nr * c + ND;
+    y[s] = a ? (T)(a[s] - m) : m;
+}
+
+// b_B = -r(u = 0, p = 0) of the steady equations: rho * body on every active face.
+template <int ND>
+__global__ void bB_kernel(DevGeo g, Phys ph, double* __restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    constexpr int nr = ND + 1;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+#pragma unroll
+    for (int a = 0; a < ND; ++a) out[nr * c + a] = nc.n[a][0] >= 0 ? ph.rho * ph.body[a] : 0.0;
+    out[nr * c + ND] = 0.0;
 }
 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
@@ -148,20 +222,39 @@ inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlo
 }  // namespace
 
 void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s) {
-    residual_kernel<<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, x, xprev, r);
+    if (c->ndim == 3) residual_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, x, xprev, r);
+    else residual_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, x, xprev, r);
 }
 
 void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s) {
-    jv_kernel<<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, xk, v, y);
+    if (c->ndim == 3) jv_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, xk, v, y);
+    else jv_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, xk, v, y);
+}
+
+void launch_xcoef(gplmm_ctx* c, hipStream_t s) {
+    if (c->ndim == 3)
+        xcoef_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+    else
+        xcoef_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
 }
 
 template <typename T>
+static const T* xcoef_table(gplmm_ctx* c);
+template <>
+const double* xcoef_table<double>(gplmm_ctx* c) { return c->d_xcoef; }
+template <>
+const float* xcoef_table<float>(gplmm_ctx* c) { return c->d_xcoef_f; }
+
+template <typename T>
 void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s) {
-    xv_kernel<T, double><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, c->d_wind, sub_from, v, y);
+    const T* cf = xcoef_table<T>(c);
+    if (c->ndim == 3) xv_kernel<3, T><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, cf, sub_from, v, y);
+    else xv_kernel<2, T><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, cf, sub_from, v, y);
 }
 
 void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s) {
-    bB_kernel<<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, bB);
+    if (c->ndim == 3) bB_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, bB);
+    else bB_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, bB);
 }
 
 template void launch_xv<float>(gplmm_ctx*, const float*, float*, const float*, hipStream_t);
