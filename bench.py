@@ -143,6 +143,8 @@ def main():
         "newton_its": st["newton_its"],
         "fgmres_its": st["lin_its"],
         "fgmres_its_total": st["lin_its_total"],
+        "gs_reorth_steps": st["gs_reorth"],
+        "newton_res_hist": st["res_hist"],
         "final_rel_residual": st["res_hist"][-1],
         "t_build_ms": st["t_build_ms"],
         "t_solve_ms": st["t_solve_ms"],

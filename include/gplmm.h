@@ -123,6 +123,7 @@ typedef struct {
     double t_total_ms;
     int builds;
     int converged;
+    int gs_reorth;           /* Arnoldi steps that needed a second Gram-Schmidt projection */
 } gplmm_stats;
 
 /* Fill *opt with the defaults listed above. */

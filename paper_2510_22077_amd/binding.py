@@ -42,7 +42,7 @@ class Stats(ctypes.Structure):
                 ("lin_its", ctypes.c_int * 64), ("res_hist", ctypes.c_double * 65),
                 ("r0_norm", ctypes.c_double), ("t_build_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
-                ("builds", ctypes.c_int), ("converged", ctypes.c_int)]
+                ("builds", ctypes.c_int), ("converged", ctypes.c_int), ("gs_reorth", ctypes.c_int)]
 
     def as_dict(self):
         n = self.newton_its
@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
                     lin_its=[self.lin_its[k] for k in range(n)],
                     res_hist=[self.res_hist[k] for k in range(n + 1)],
                     r0_norm=self.r0_norm, t_build_ms=self.t_build_ms, t_solve_ms=self.t_solve_ms,
-                    t_total_ms=self.t_total_ms, builds=self.builds, converged=bool(self.converged))
+                    t_total_ms=self.t_total_ms, builds=self.builds, converged=bool(self.converged),
+                    gs_reorth=self.gs_reorth)
 
 
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",

@@ -524,6 +524,7 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
     std::memset(S, 0, sizeof(*S));
     auto T0 = std::chrono::steady_clock::now();
     const int64_t N = c->N;
+    const int64_t reorth0 = c->gs_reorth;
     // ||r(0)||: the residual at the origin (previous time level also zero)
     launch_residual(c, c->d_zero, c->d_zero, c->d_r, c->stream);
     const double r0 = nrm2(c, c->d_r, N);
@@ -569,6 +570,7 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
     }
     if (rn <= c->opt.newton_tol * r0) rcode = 0;
     S->converged = rcode == 0;
+    S->gs_reorth = (int)(c->gs_reorth - reorth0);
     GP_HIP(c, hipStreamSynchronize(c->stream));
     GP_HIP(c, hipGetLastError());
     S->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();

@@ -169,6 +169,7 @@ struct gplmm_ctx {
     bool ready = false;
     bool built = false;
     int builds = 0;
+    int64_t gs_passes = 0, gs_reorth = 0;   // Gram-Schmidt steps, and those reorthogonalised
     double last_build_ms = 0.0;
     bool timing = false;
     double apply_bytes = 0.0, jv_bytes = 0.0;

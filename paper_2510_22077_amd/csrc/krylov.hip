@@ -24,18 +24,44 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
-// partial[j * nblk + b] = sum over block b's rows of V_j . w
-__global__ void multidot_kernel(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ w,
-                                int64_t n, double* __restrict__ partial) {
-    __shared__ double sh[16];
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-    for (int j = 0; j < k; ++j) {
-        const double* v = V + (int64_t)j * ldv;
-        double acc = 0.0;
-        for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) acc += v[r] * w[r];
-        double s = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = s;
+// partial[j * nblk + b] = sum over block b's rows of V_j . w.  Vectors are taken eight at
+// a time (eight independent streams in flight per thread, w read once per group),
+// rows grid-strided, and the eight block sums reduced together.
+constexpr int kGroup = 8;
+
+__global__ void __launch_bounds__(kThreads) multidot_kernel(const double* __restrict__ V, int64_t ldv, int k,
+                                                            const double* __restrict__ w, int64_t n,
+                                                            double* __restrict__ partial) {
+    __shared__ double sh[kThreads / 64][kGroup];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < k; j0 += kGroup) {
+        const int kk = min(kGroup, k - j0);
+        const double* Vg = V + (int64_t)j0 * ldv;
+        double acc[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) acc[q] = 0.0;
+        for (int64_t r = r0; r < n; r += stride) {
+            const double wr = w[r];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q)
+                if (q < kk) acc[q] += Vg[(int64_t)q * ldv + r] * wr;
+        }
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            double v = acc[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) sh[wv][q] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < kk) {
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < kThreads / 64; ++u) t += sh[u][threadIdx.x];
+            partial[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -49,16 +75,28 @@ __global__ void reduce_kernel(const double* __restrict__ partial, int nblk, doub
     if (threadIdx.x == 0) out[j] = s;
 }
 
-// w -= sum_j V_j h_j ; optionally partial sums of w_new^2
-__global__ void update_kernel(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ hcoef,
-                              double* __restrict__ w, int64_t n, double* __restrict__ partial_nrm) {
+// w -= sum_j V_j h_j ; optionally partial sums of w_new^2.  The coefficients sit in LDS;
+// the k column reads of a row are independent loads, eight in flight at a time.
+__global__ void __launch_bounds__(kThreads) update_kernel(const double* __restrict__ V, int64_t ldv, int k,
+                                                          const double* __restrict__ hcoef, double* __restrict__ w,
+                                                          int64_t n, double* __restrict__ partial_nrm) {
     __shared__ double sh[16];
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    __shared__ double hs[kMaxRestart + 2];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = hcoef[j];
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     double acc = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
         double x = w[r];
-        for (int j = 0; j < k; ++j) x -= V[(int64_t)j * ldv + r] * hcoef[j];
+        int j = 0;
+        for (; j + kGroup <= k; j += kGroup) {
+            double t[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) t[q] = V[(int64_t)(j + q) * ldv + r];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) x -= t[q] * hs[j + q];
+        }
+        for (; j < k; ++j) x -= V[(int64_t)j * ldv + r] * hs[j];
         w[r] = x;
         acc += x * x;
     }
@@ -127,22 +165,44 @@ static void multi_dot_dev(gplmm_ctx* c, const double* V, int64_t ldv, int k, con
     reduce_kernel<<<k, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, out_dev);
 }
 
-// One CGS2 step: w <- w - V h1 - V h2 with h1 = V^T w, h2 = V^T (w - V h1); returns
-// h = h1 + h2 (k values) and ||w_new|| in hout[k] (host).
+// Classical Gram-Schmidt with the Daniel-Gragg-Kaufman-Stewart reorthogonalisation
+// test: h = V^T w and ||w||^2 in one pass over V (w must be the column after V's k
+// columns, so the k + 1 dots include w.w), w <- w - V h with ||w||^2 fused; if the new
+// norm dropped below 1/sqrt(2) of the old one (cancellation), a second projection
+// h2 = V^T w, w <- w - V h2 follows and h += h2.  Returns h (k values) and ||w|| in
+// hout[k] (host).  Passes over V: two, four when the test fires.
 void cgs2(gplmm_ctx* c, const double* V, int64_t ldv, int k, double* w, int64_t n, double* hout) {
     double* r = results(c);
     double* h1 = r;
     double* h2 = r + (kMaxRestart + 2);
     double* nr = r + 2 * (kMaxRestart + 2);
-    multi_dot_dev(c, V, ldv, k, w, n, h1);
-    update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h1, w, n, nullptr);
-    multi_dot_dev(c, V, ldv, k, w, n, h2);
-    update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h2, w, n, partials(c));
+    const bool fused = w == V + (int64_t)k * ldv;
+    multi_dot_dev(c, V, ldv, fused ? k + 1 : k, w, n, h1);
+    if (!fused) {
+        multidot_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(w, 0, 1, w, n, partials(c));
+        reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, h1 + k);
+    }
+    update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h1, w, n, partials(c));
     reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, nr);
-    hipMemcpyAsync(c->h_red, r, sizeof(double) * 3 * (kMaxRestart + 2), hipMemcpyDeviceToHost, c->stream);
+    hipMemcpyAsync(c->h_red, h1, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, c->stream);
+    hipMemcpyAsync(c->h_red + (kMaxRestart + 2), nr, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
-    for (int j = 0; j < k; ++j) hout[j] = c->h_red[j] + c->h_red[(kMaxRestart + 2) + j];
-    hout[k] = std::sqrt(std::max(0.0, c->h_red[2 * (kMaxRestart + 2)]));
+    for (int j = 0; j < k; ++j) hout[j] = c->h_red[j];
+    const double before = c->h_red[k];
+    double after = c->h_red[kMaxRestart + 2];
+    c->gs_passes++;
+    if (!(after > 0.5 * before)) {
+        multi_dot_dev(c, V, ldv, k, w, n, h2);
+        update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h2, w, n, partials(c));
+        reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, nr);
+        hipMemcpyAsync(c->h_red, h2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream);
+        hipMemcpyAsync(c->h_red + (kMaxRestart + 2), nr, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        hipStreamSynchronize(c->stream);
+        for (int j = 0; j < k; ++j) hout[j] += c->h_red[j];
+        after = c->h_red[kMaxRestart + 2];
+        c->gs_reorth++;
+    }
+    hout[k] = std::sqrt(std::max(0.0, after));
 }
 
 void lincomb(gplmm_ctx* c, const double* Z, int64_t ldz, int k, const double* y_host, double* x, int64_t n) {

@@ -46,27 +46,30 @@ __global__ void restrict_kernel(const V* __restrict__ v, const int64_t* __restri
     if (threadIdx.x == 0) out[g] = s;
 }
 
-// z on the primaries' slots: sum_k phi_k coef[col_k]; one block per primary.
+// z on the primaries' slots: sum_k phi_k coef[col_k]; one thread per primary row
+// (flat over all primaries, so large pores do not serialise the launch).
 template <typename T, typename O>
 __global__ void prolong_prim_kernel(const T* __restrict__ phi, const int64_t* __restrict__ phi_off,
                                     const int64_t* __restrict__ pcol_off, const int32_t* __restrict__ pcols,
-                                    const Sub* __restrict__ subs, const int32_t* __restrict__ slots,
-                                    const double* __restrict__ coef, O* __restrict__ z, int kT) {
-    const int i = blockIdx.x;
+                                    const Sub* __restrict__ subs, const int32_t* __restrict__ row_sub,
+                                    const int32_t* __restrict__ slots, const double* __restrict__ coef,
+                                    O* __restrict__ z, int64_t nrows, int kT) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows) return;
+    const int i = row_sub[t];
     const Sub sb = subs[i];
-    const int ld = sb.nT * kT;
+    const int r = (int)(t - sb.slot_off);
+    const int64_t ld = (int64_t)sb.nT * kT;
     const int64_t c0 = pcol_off[i], c1 = pcol_off[i + 1];
-    const T* ph = phi + phi_off[i];
-    for (int r = threadIdx.x; r < sb.n; r += blockDim.x) {
-        double acc = 0.0;
-        for (int64_t k = c0; k < c1; ++k) {
-            int32_t col = pcols[k];
-            if (col < 0) continue;
-            double a = coef[col];
-            if (a != 0.0) acc += a * (double)ph[(k - c0) * ld + r];
-        }
-        z[slots[sb.slot_off + r]] = (O)acc;
+    const T* ph = phi + phi_off[i] + r;
+    double acc = 0.0;
+    for (int64_t k = c0; k < c1; ++k) {
+        const int32_t col = pcols[k];
+        if (col < 0) continue;
+        const double a = coef[col];
+        if (a != 0.0) acc += a * (double)ph[(k - c0) * ld];
     }
+    z[slots[t]] = (O)acc;
 }
 
 // z on interface cells' pressures: the coarse pressure of their interface.
@@ -157,9 +160,9 @@ template <typename T, typename O>
 static void prolong(gplmm_ctx* c, const double* coef, O* z) {
     hipMemsetAsync(z, 0, sizeof(O) * c->N, c->stream);
     if (c->Np > 0)
-        prolong_prim_kernel<T, O><<<c->Np, kB, 0, c->stream>>>((const T*)c->d_phi, c->d_phi_off, c->d_phi_cols_off,
-                                                              c->d_phi_cols, c->d_subs, c->d_sub_slots, coef, z,
-                                                              c->tile);
+        prolong_prim_kernel<T, O><<<nb(c->prim_rows), kB, 0, c->stream>>>(
+            (const T*)c->d_phi, c->d_phi_off, c->d_phi_cols_off, c->d_phi_cols, c->d_subs, c->d_row_sub,
+            c->d_sub_slots, coef, z, c->prim_rows, c->tile);
     if (c->Nc > 0)
         prolong_iface_kernel<O><<<c->Nc, 64, 0, c->stream>>>(c->d_grp_ptr, c->d_grp_slot, c->Nc, coef, z);
 }
