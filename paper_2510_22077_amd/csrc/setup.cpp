@@ -14,6 +14,7 @@
 #include <queue>
 
 #include "internal.h"
+#include <array>
 
 namespace gp {
 
@@ -349,17 +350,84 @@ std::vector<int64_t> unknowns_of(const gplmm_ctx* c, const std::vector<int32_t>&
     return u;
 }
 
-// Sort key: faces at their record cell's raster position (axis order within it);
-// a pressure right after the last face of its cell, i.e. after the upper face
-// along the slowest axis (position unwrapped), so that each pressure follows all
-// of its faces and the velocity-first leading blocks stay nonsingular.
-int64_t order_key(const gplmm_ctx* c, int64_t s) {
-    int64_t q = s / c->nrec;
-    int comp = (int)(s % c->nrec);
-    int64_t v = c->cell_voxel[q];
-    if (comp < c->ndim) return v * 8 + comp;
-    int64_t stride = c->ndim == 3 ? (int64_t)c->nx * c->ny : (int64_t)c->nx;
-    return (v + stride) * 8 + 7;
+// Local order of a subdomain's unknowns: a raster order over the set's own bounding
+// box (periodic axes cut at their longest empty run, so a set that wraps is
+// contiguous), with the longest extent as the slowest axis, which keeps the
+// envelope (the slab of unknowns between a row and its furthest lower neighbour)
+// small.  A face sits at its record cell's raster position (axis order within it;
+// for a face whose record cell is outside the set, that cell's unwrapped position);
+// a pressure sits after the upper face of its cell along the slowest axis, so every
+// pressure follows all of its faces and the velocity-first leading blocks of the
+// saddle-point matrix stay nonsingular without pivoting.
+std::vector<int64_t> local_keys(const gplmm_ctx* c, const std::vector<int32_t>& cells, const std::vector<int64_t>& u) {
+    const int nd = c->ndim;
+    const int n = (int)cells.size();
+    const int dims[3] = {c->nx, c->ny, c->nz};
+    std::vector<std::array<int, 3>> co(n);
+    for (int t = 0; t < n; ++t) {
+        int64_t v = c->cell_voxel[cells[t]];
+        co[t] = {(int)(v % c->nx), (int)((v / c->nx) % c->ny), (int)(v / ((int64_t)c->nx * c->ny))};
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (!c->opt.periodic[a] || dims[a] < 2) continue;
+        std::vector<char> occ(dims[a], 0);
+        for (int t = 0; t < n; ++t) occ[co[t][a]] = 1;
+        int best = -1, bestlen = 0;
+        for (int x0 = 0; x0 < dims[a]; ++x0) {
+            if (occ[x0] || !occ[(x0 + dims[a] - 1) % dims[a]]) continue;   // an empty run starts at x0
+            int len = 0;
+            while (len < dims[a] && !occ[(x0 + len) % dims[a]]) ++len;
+            if (len > bestlen) {
+                bestlen = len;
+                best = x0;
+            }
+        }
+        if (best < 0) continue;   // occupies the whole ring: keep the image coordinates
+        const int start = (best + bestlen) % dims[a];
+        for (int t = 0; t < n; ++t) co[t][a] = (co[t][a] - start + dims[a]) % dims[a];
+    }
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (int t = 0; t < n; ++t)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], co[t][a]);
+            hi[a] = std::max(hi[a], co[t][a]);
+        }
+    int ax[3] = {0, 1, 2};   // fastest .. slowest; ties keep x fastest
+    std::stable_sort(ax, ax + nd, [&](int a, int b) { return hi[a] - lo[a] < hi[b] - lo[b]; });
+    int64_t stride[3] = {0, 0, 0}, st = 1;
+    for (int q = 0; q < nd; ++q) {
+        stride[ax[q]] = st;
+        st *= (int64_t)(hi[ax[q]] - lo[ax[q]] + 2);   // +1 for the upper faces of the top layer
+    }
+    const int slow = ax[nd - 1];
+    auto lin = [&](const std::array<int, 3>& p) {
+        int64_t l = 0;
+        for (int a = 0; a < nd; ++a) l += (int64_t)(p[a] - lo[a]) * stride[a];
+        return l;
+    };
+    auto idx = [&](int64_t q) -> int {
+        auto it = std::lower_bound(cells.begin(), cells.end(), (int32_t)q);
+        return (it != cells.end() && *it == q) ? (int)(it - cells.begin()) : -1;
+    };
+    std::vector<int64_t> keys(u.size());
+    for (size_t t = 0; t < u.size(); ++t) {
+        const int64_t q = u[t] / c->nrec;
+        const int comp = (int)(u[t] % c->nrec);
+        int k = idx(q);
+        if (comp < nd) {
+            std::array<int, 3> p;
+            if (k >= 0) {
+                p = co[k];
+            } else {   // record cell outside the set: one step above its lower neighbour
+                p = co[idx(c->nbr[q * 6 + 2 * comp])];
+                p[comp] += 1;
+            }
+            keys[t] = lin(p) * 8 + comp;
+        } else {
+            keys[t] = (lin(co[k]) + stride[slow]) * 8 + 7;
+        }
+    }
+    return keys;
 }
 
 // Structural columns of row s of X (viscous/convective neighbours, gradient, divergence).
@@ -414,7 +482,8 @@ int build_local_problems(gplmm_ctx* c) {
         const std::vector<int32_t>& cells = sb.kind == 0 ? prim_cells[sb.id] : c->dual_cells[sb.id];
         std::vector<int64_t> u = unknowns_of(c, cells);
         std::vector<std::pair<int64_t, int64_t>> keyed(u.size());
-        for (size_t t = 0; t < u.size(); ++t) keyed[t] = {order_key(c, u[t]), u[t]};
+        std::vector<int64_t> keys = local_keys(c, cells, u);
+        for (size_t t = 0; t < u.size(); ++t) keyed[t] = {keys[t], u[t]};
         std::sort(keyed.begin(), keyed.end());
         const int n = (int)u.size();
         sb.n = n;
