@@ -317,21 +317,91 @@ __global__ void __launch_bounds__(256) trsv_kernel(Env e, const T* __restrict__ 
 // loads; partial sums are reduced over the 32 lanes of a row.
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T sum32(T v) {
-    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
-    return v;
+__device__ __forceinline__ T sum32(T v);
+
+// Lane permutations inside a wave: DPP within 16-lane rows, a swizzle across the two
+// rows of a 32-lane group (bit mode: and 0x1f, xor 0x10).
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, 0xf, 0xf, true));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), kCtrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float swz16_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401f));
+}
+__device__ __forceinline__ double swz16_d(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), 0x401f);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401f);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 32 lanes of a half-wave, result in every lane: quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror, row_mirror (a 16-lane sum), then the other row.
+template <>
+__device__ __forceinline__ float sum32<float>(float v) {
+    v += dpp_f<0xb1>(v);
+    v += dpp_f<0x4e>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return v + swz16_f(v);
+}
+template <>
+__device__ __forceinline__ double sum32<double>(double v) {
+    v += dpp_d<0xb1>(v);
+    v += dpp_d<0x4e>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return v + swz16_d(v);
 }
 
 constexpr size_t kTrsvLdsMax = 64 * 1024;   // dynamic LDS bound for the in-LDS solve
 // tiles of a tile row (column) held per register buffer: 32 FP32 or 16 FP64 values per thread
 template <typename T>
-constexpr int pf_tiles() { return sizeof(T) == 4 ? 32 : 16; }
+constexpr int pf_tiles() { return sizeof(T) == 4 ? 30 : 16; }
 
+// Tiles t0..nt-1 of a long tile row (past the register buffer), eight loads in flight.
+template <typename T>
+__device__ __forceinline__ T tail_dot(const T* __restrict__ src, const T* y, int t0, int nt) {
+    T acc = 0;
+    int t = t0;
+    for (; t + 8 <= nt; t += 8) {
+        T v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = src[(int64_t)(t + q) * kTT];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q] * y[(t + q) * kT];
+    }
+    for (; t < nt; ++t) acc += src[(int64_t)t * kTT] * y[t * kT];
+    return acc;
+}
+
+// buf[t] = tile t of a tile row for t < n (entries past the row keep stale values,
+// which buf_dot drops)
 template <typename T, int kPF>
-__device__ __forceinline__ void load_tiles(T (&buf)[kPF], const T* __restrict__ src, int n) {
+__device__ __forceinline__ void load_row(T (&buf)[kPF], const T* __restrict__ src, int n) {
 #pragma unroll
     for (int t = 0; t < kPF; ++t)
         if (t < n) buf[t] = src[(int64_t)t * kTT];
+}
+
+// sum_{t < n} buf[t] y[t kT]: entries past the row read the (always valid) ysafe and
+// are dropped after the product, so nothing outside the row reaches the sum
+template <typename T, int kPF>
+__device__ __forceinline__ T buf_dot(const T (&buf)[kPF], const T* y, int n, const T* ysafe) {
+    T acc = 0;
+#pragma unroll
+    for (int t = 0; t < kPF; ++t) {
+        const T p = buf[t] * *(t < n ? y + t * kT : ysafe);
+        acc += t < n ? p : (T)0;
+    }
+    return acc;
 }
 
 // kLds: the subdomain's solution vector lives in LDS (dynamic, nT * T entries) during
@@ -366,35 +436,42 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     const int len = nT * kT;
     for (int i = tid; i < len; i += 1024) x[i] = i < sb.n ? vin[sl[i]] : (T)0;
     T bufA[kPF], bufB[kPF];
+#pragma unroll
+    for (int t = 0; t < kPF; ++t) bufA[t] = bufB[t] = 0;
     int nA = 0, nB = 0;
-    T dA = D[0], dB = 0;
-    if (nT > 1) {
-        nB = min(1 - tfc[1], kPF);
-        load_tiles(bufB, F + lrow[1] + tid, nB);
-        dB = D[kTT];
-    }
+    T dA, dB;
+    // rows I and I + 1 are in flight while row I - 2 is solved; loads of rows past the
+    // end are clamped to the last row (and never used)
+    // (the diagonal value of a row is fetched only after the row's diagonal product has
+    // consumed the previous one, so that it reuses its register without a copy)
+    auto fetch_l = [&](int I, T(&buf)[kPF], int& nb) {
+        const int Ic = min(I, nT - 1);
+        nb = min(Ic - tfc[Ic], kPF);
+        load_row(buf, F + lrow[Ic] + tid, nb);
+    };
+    auto fetch_u = [&](int I, T(&buf)[kPF], int& nb) {
+        const int Ic = max(I, 0);
+        nb = min(tlc[Ic] - Ic, kPF);
+        load_row(buf, F + urow[Ic] + tid, nb);
+    };
+    fetch_l(0, bufA, nA);
+    fetch_l(1, bufB, nB);
+    dA = D[0];
+    dB = D[(int64_t)min(1, nT - 1) * kTT];
     __syncthreads();
     // ---- forward: L y = b, row-oriented over L's contiguous tile rows
     auto fwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
         const int j0 = tfc[I], nt = I - j0;
         const T* y = x + j0 * kT + c;
-        const T dv = db;
-        T acc = 0;
-#pragma unroll
-        for (int t = 0; t < kPF; ++t)
-            if (t < nb) acc += buf[t] * y[t * kT];
-        const T* Lr = F + lrow[I] + tid;
-        for (int t = kPF; t < nt; ++t) acc += Lr[(int64_t)t * kTT] * y[t * kT];
-        if (I + 2 < nT) {
-            nb = min(I + 2 - tfc[I + 2], kPF);
-            load_tiles(buf, F + lrow[I + 2] + tid, nb);
-            db = D[(int64_t)(I + 2) * kTT];
-        }
+        T acc = buf_dot(buf, y, nb, x + c);
+        if (nt > kPF) acc += tail_dot<T>(F + lrow[I] + tid, y, kPF, nt);
+        fetch_l(I + 2, buf, nb);
         acc = sum32(acc);
         if (c == 0) part[r] = x[I * kT + r] - acc;
         __syncthreads();
-        const T v = sum32((c < r ? dv : (c == r ? (T)1 : (T)0)) * part[c]);
+        const T v = sum32((c < r ? db : (c == r ? (T)1 : (T)0)) * part[c]);
         if (c == 0) x[I * kT + r] = v;
+        db = D[(int64_t)min(I + 2, nT - 1) * kTT];
         __syncthreads();
     };
     for (int I = 0; I < nT; I += 2) {
@@ -405,36 +482,21 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     auto bwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
         const int nt = tlc[I] - I;
         const T* y = x + (I + 1) * kT + c;
-        const T dv = db;
-        T acc = 0;
-#pragma unroll
-        for (int t = 0; t < kPF; ++t)
-            if (t < nb) acc += buf[t] * y[t * kT];
-        const T* Ur = F + urow[I] + tid;
-        for (int t = kPF; t < nt; ++t) acc += Ur[(int64_t)t * kTT] * y[t * kT];
-        if (I >= 2) {
-            nb = min(tlc[I - 2] - (I - 2), kPF);
-            load_tiles(buf, F + urow[I - 2] + tid, nb);
-            db = D[(int64_t)(I - 2) * kTT];
-        }
+        T acc = buf_dot(buf, y, nb, x + c);
+        if (nt > kPF) acc += tail_dot<T>(F + urow[I] + tid, y, kPF, nt);
+        fetch_u(I - 2, buf, nb);
         acc = sum32(acc);
         if (c == 0) part[r] = x[I * kT + r] - acc;
         __syncthreads();
-        const T v = sum32((c >= r ? dv : (T)0) * part[c]);
+        const T v = sum32((c >= r ? db : (T)0) * part[c]);
         if (c == 0) x[I * kT + r] = v;
+        db = D[(int64_t)max(I - 2, 0) * kTT];
         __syncthreads();
     };
-    {
-        const int I = nT - 1;
-        nA = min(tlc[I] - I, kPF);
-        load_tiles(bufA, F + urow[I] + tid, nA);
-        dA = D[(int64_t)I * kTT];
-        if (I >= 1) {
-            nB = min(tlc[I - 1] - (I - 1), kPF);
-            load_tiles(bufB, F + urow[I - 1] + tid, nB);
-            dB = D[(int64_t)(I - 1) * kTT];
-        }
-    }
+    fetch_u(nT - 1, bufA, nA);
+    fetch_u(nT - 2, bufB, nB);
+    dA = D[(int64_t)(nT - 1) * kTT];
+    dB = D[(int64_t)max(nT - 2, 0) * kTT];
     for (int I = nT - 1; I >= 0; I -= 2) {
         bwd_row(I, bufA, nA, dA);
         if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
