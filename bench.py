@@ -50,6 +50,26 @@ def _cpu_baseline(workload, crop):
                 converged=bool(st.converged))
 
 
+def _measured_traffic(workload, precision):
+    """HBM bytes per launch of the skyline-solve kernel from the committed PMC summary, if
+    it was taken on this workload and precision with the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "trsv_sub_kernel_traffic_%s_%s.txt" % (workload, precision))
+    src = os.path.join(ROOT, "paper_2510_22077_amd", "csrc", "lu.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,7 +81,20 @@ def main():
     ap.add_argument("--restart", type=int, default=128)
     ap.add_argument("--cpu-crop", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES, five times (the reference "
+                         "point for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.copy_cal:
+        import torch
+        n = args.copy_cal // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -154,7 +187,8 @@ def main():
         "precond_apply_GBps": apply_gbs,
         "roofline": {"bound": "hbm", "kernel": "trsv_sub_kernel (batched skyline triangular solves)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _measured_traffic(args.workload, args.precision),
                      "avg_launch_ms": tr["avg_ms"], "algorithmic_bytes_per_launch": tr["bytes"],
                      "launches": tr["samples"]},
         "kernel_times": kt,

@@ -98,6 +98,10 @@ typedef struct {
     int host_only;           /* 1: build the decomposition and index maps on the host only
                                 (no device memory; compute calls return GPLMM_E_STATE) */
     void* stream;            /* hipStream_t, NULL = default stream */
+    int line_search;         /* 1 (default): backtracking on ||r||: the Newton update is
+                                lambda * delta with lambda = 1, 1/2, ... >= 1/64, the first
+                                lambda with ||r(x + lambda delta)|| <= (1 - 1e-4 lambda) ||r(x)||
+                                (the smallest if none); 0: full steps */
 } gplmm_options;
 
 typedef struct {
@@ -124,6 +128,7 @@ typedef struct {
     int builds;
     int converged;
     int gs_reorth;           /* Arnoldi steps that needed a second Gram-Schmidt projection */
+    double step_length[64];  /* Newton step length lambda of each Newton step */
 } gplmm_stats;
 
 /* Fill *opt with the defaults listed above. */

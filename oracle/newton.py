@@ -8,9 +8,9 @@ measured against ||r(u=0, p=0)|| (Section 7).  gPLMM is built from the
 modified Jacobian J~_w once and reused for every Newton iteration (Section 4);
 with no nearby solution the Stokes velocity serves as the wind.
 
-Readings taken where the paper is silent: full Newton steps with no line
-search; stop when ||r(x_k)|| <= tol * ||r(0)||; the first step uses w = 0 (the
-Stokes matrix); with ``wind="stokes"`` the preconditioner is rebuilt once with
+Readings taken where the paper is silent: Newton steps globalised by
+backtracking on the residual norm (see ``solve``); stop when
+||r(x_k)|| <= tol * ||r(0)||; the first step uses w = 0 (the Stokes matrix); with ``wind="stokes"`` the preconditioner is rebuilt once with
 w = the velocity after the first Newton step (the Stokes solution) and then
 kept.
 """
@@ -30,6 +30,7 @@ class NewtonStats:
     newton_its: int = 0
     lin_its: list = field(default_factory=list)
     res_hist: list = field(default_factory=list)
+    step_length: list = field(default_factory=list)
     t_mg: float = 0.0
     t_sol: float = 0.0
     converged: bool = False
@@ -43,8 +44,12 @@ def build_precond(ops, dc, phys, wind):
 
 def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
           maxit=30, restart=30, lin_maxit=600, wind="stokes", wind_vec=None,
-          precond="gplmm", stats=None):
-    """Newton-FGMRES with gPLMM.  ``precond``: "gplmm" or "exact" (spsolve)."""
+          precond="gplmm", stats=None, line_search=True):
+    """Newton-FGMRES with gPLMM.  ``precond``: "gplmm" or "exact" (spsolve).
+
+    ``line_search``: backtracking on ||r||, lambda = 1, 1/2, ... down to 1/64, the first
+    lambda with ||r(x + lambda d)|| <= (1 - 1e-4 lambda) ||r(x)|| (Armijo's sufficient
+    decrease), else the smallest; False takes full steps."""
     g = ops.g
     st = stats if stats is not None else NewtonStats()
     steady0 = Phys(phys.rho, phys.mu, phys.body, phys.dt, phys.pin)
@@ -78,9 +83,17 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
             d, its = spla.spsolve(J.tocsc(), -r), 1
         st.t_sol += time.perf_counter() - t
         st.lin_its.append(its)
-        x = x + d
         st.newton_its += 1
-        r = residual(ops, x, phys, x_old=x_old)
+        rn = np.linalg.norm(r)
+        lam = 1.0
+        while True:
+            xt = x + lam * d
+            rt = residual(ops, xt, phys, x_old=x_old)
+            if not line_search or np.linalg.norm(rt) <= (1.0 - 1e-4 * lam) * rn or lam <= 1.0 / 64.0:
+                break
+            lam *= 0.5
+        st.step_length.append(lam)
+        x, r = xt, rt
         st.res_hist.append(np.linalg.norm(r) / r0n)
     else:
         st.converged = np.linalg.norm(r) <= tol * r0n

@@ -26,7 +26,7 @@ class Options(ctypes.Structure):
                 ("restart", ctypes.c_int), ("newton_tol", ctypes.c_double),
                 ("lin_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int),
                 ("lin_maxit", ctypes.c_int), ("tile", ctypes.c_int), ("host_only", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("line_search", ctypes.c_int)]
 
 
 class Layout(ctypes.Structure):
@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("lin_its", ctypes.c_int * 64), ("res_hist", ctypes.c_double * 65),
                 ("r0_norm", ctypes.c_double), ("t_build_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
-                ("builds", ctypes.c_int), ("converged", ctypes.c_int), ("gs_reorth", ctypes.c_int)]
+                ("builds", ctypes.c_int), ("converged", ctypes.c_int), ("gs_reorth", ctypes.c_int),
+                ("step_length", ctypes.c_double * 64)]
 
     def as_dict(self):
         n = self.newton_its
@@ -51,7 +52,7 @@ class Stats(ctypes.Structure):
                     res_hist=[self.res_hist[k] for k in range(n + 1)],
                     r0_norm=self.r0_norm, t_build_ms=self.t_build_ms, t_solve_ms=self.t_solve_ms,
                     t_total_ms=self.t_total_ms, builds=self.builds, converged=bool(self.converged),
-                    gs_reorth=self.gs_reorth)
+                    gs_reorth=self.gs_reorth, step_length=[self.step_length[k] for k in range(n)])
 
 
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",
@@ -127,7 +128,7 @@ class Solver:
     def __init__(self, mask, labels, rho=1.0, mu=1.0, body=(1.0, 0.0, 0.0), dt=0.0, h=1.0,
                  periodic=(1, 0, 0), precision="fp64", wind="stokes", tag_layers=1,
                  dual_dilations=-1, restart=30, newton_tol=1e-8, lin_tol=1e-9,
-                 newton_maxit=30, lin_maxit=600, host_only=False, stream=None):
+                 newton_maxit=30, lin_maxit=600, host_only=False, stream=None, line_search=True):
         lib = load()
         self.lib = lib
         mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
@@ -154,6 +155,7 @@ class Solver:
         o.newton_maxit = newton_maxit
         o.lin_maxit = lin_maxit
         o.host_only = 1 if host_only else 0
+        o.line_search = 1 if line_search else 0
         self.torch = None
         if not host_only:
             import torch

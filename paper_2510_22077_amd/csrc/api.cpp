@@ -343,6 +343,7 @@ void gplmm_default_options(gplmm_options* o) {
     o->restart = 30;
     o->newton_tol = 1e-8;
     o->lin_tol = 1e-9;
+    o->line_search = 1;
     o->newton_maxit = 30;
     o->lin_maxit = 600;
     o->tile = 0;
@@ -562,10 +563,29 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
         S->t_solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
         S->lin_its[k] = its;
         S->lin_its_total += its;
-        axpy(c, 1.0, c->d_dx, x, N);
         S->newton_its = k + 1;
-        launch_residual(c, x, xprev, c->d_r, c->stream);
-        rn = nrm2(c, c->d_r, N);
+        if (c->opt.line_search) {
+            // backtracking on ||r||, trial points in d_tmp; d_r ends holding r(x_new)
+            double lam = 1.0;
+            for (;;) {
+                GP_HIP(c, hipMemcpyAsync(c->d_tmp, x, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+                axpy(c, lam, c->d_dx, c->d_tmp, N);
+                launch_residual(c, c->d_tmp, xprev, c->d_r, c->stream);
+                const double rt = nrm2(c, c->d_r, N);
+                if (rt <= (1.0 - 1e-4 * lam) * rn || lam <= 1.0 / 64.0) {
+                    GP_HIP(c, hipMemcpyAsync(x, c->d_tmp, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+                    rn = rt;
+                    break;
+                }
+                lam *= 0.5;
+            }
+            S->step_length[k] = lam;
+        } else {
+            axpy(c, 1.0, c->d_dx, x, N);
+            launch_residual(c, x, xprev, c->d_r, c->stream);
+            rn = nrm2(c, c->d_r, N);
+            S->step_length[k] = 1.0;
+        }
         S->res_hist[k + 1] = rn / r0;
     }
     if (rn <= c->opt.newton_tol * r0) rcode = 0;
