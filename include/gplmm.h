@@ -225,6 +225,50 @@ const char* gplmm_last_error(const gplmm_ctx* ctx);
 
 void gplmm_destroy(gplmm_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Learned coarse coefficients: a small MLP (hidden layers of equal width, GELU
+ * in its tanh form, linear output) trained by mean-squared error with Adam.
+ * The coarse operator it replaces is Rhat X Phat (Section 3.2.2, Remark 1);
+ * the exact operator stays the fallback.  Products run on BF16 matrix cores
+ * with FP32 accumulation; master weights are FP32.  All x / y / t pointers
+ * are device FP32 arrays, row-major [n x nin], [n x nout]; calls run on the
+ * stream given at creation (NULL = default stream).
+ * ------------------------------------------------------------------------- */
+typedef struct gplmm_mlp gplmm_mlp;
+
+/* nin inputs, nlayers hidden layers of nhidden units, nout outputs; max_batch rows
+ * per forward chunk and per gradient batch.  Weights start at zero.  Errors:
+ * GPLMM_E_ARG (sizes), GPLMM_E_HIP. */
+int gplmm_mlp_create(int nin, int nhidden, int nlayers, int nout, int max_batch, void* stream, gplmm_mlp** out);
+
+/* Parameter count of the packed host layout: for each layer (hidden layers first,
+ * then the output layer) W (fan_in x fan_out, row-major) then b (fan_out). */
+int64_t gplmm_mlp_num_params(const gplmm_mlp* mlp);
+
+/* Copy all parameters from / to a packed host FP32 array; setting them also resets
+ * the optimiser state. */
+int gplmm_mlp_set_params(gplmm_mlp* mlp, const float* host);
+int gplmm_mlp_get_params(gplmm_mlp* mlp, float* host);
+
+/* y = net(x) for n rows (any n, processed in chunks of max_batch). */
+int gplmm_mlp_forward(gplmm_mlp* mlp, const float* x_dev, int n, float* y_dev);
+
+/* Mean-squared loss over n <= max_batch rows and its gradient (kept on the device;
+ * also copied, packed, to grad_host when it is not NULL). */
+int gplmm_mlp_grad(gplmm_mlp* mlp, const float* x_dev, const float* t_dev, int n, double* loss, float* grad_host);
+
+/* One Adam step (Kingma & Ba) with the last gradient. */
+int gplmm_mlp_adam(gplmm_mlp* mlp, double lr, double beta1, double beta2, double eps);
+
+/* Minibatch Adam over the n rows in their given order, `epochs` passes; *loss_out
+ * receives the mean batch loss of the last pass. */
+int gplmm_mlp_train(gplmm_mlp* mlp, const float* x_dev, const float* t_dev, int n, int epochs, int batch,
+                    double lr, double* loss_out);
+
+const char* gplmm_mlp_last_error(const gplmm_mlp* mlp);
+
+void gplmm_mlp_destroy(gplmm_mlp* mlp);
+
 #ifdef __cplusplus
 }
 #endif

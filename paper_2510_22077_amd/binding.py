@@ -58,7 +58,10 @@ class Stats(ctypes.Structure):
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",
            "gplmm_get_duals", "gplmm_get_subdomains", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
            "gplmm_precond_apply", "gplmm_get_coarse", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
-           "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy"]
+           "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy",
+           "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
+           "gplmm_mlp_forward", "gplmm_mlp_grad", "gplmm_mlp_adam", "gplmm_mlp_train", "gplmm_mlp_last_error",
+           "gplmm_mlp_destroy"]
 
 _lib = None
 
@@ -110,6 +113,26 @@ def load():
     lib.gplmm_last_error.restype = ctypes.c_char_p
     lib.gplmm_destroy.argtypes = [P]
     lib.gplmm_destroy.restype = V
+    D = ctypes.c_double
+    lib.gplmm_mlp_create.argtypes = [I, I, I, I, I, P, ctypes.POINTER(P)]
+    lib.gplmm_mlp_create.restype = I
+    lib.gplmm_mlp_num_params.argtypes = [P]
+    lib.gplmm_mlp_num_params.restype = ctypes.c_int64
+    for f in ("gplmm_mlp_set_params", "gplmm_mlp_get_params"):
+        getattr(lib, f).argtypes = [P, P]
+        getattr(lib, f).restype = I
+    lib.gplmm_mlp_forward.argtypes = [P, P, I, P]
+    lib.gplmm_mlp_forward.restype = I
+    lib.gplmm_mlp_grad.argtypes = [P, P, P, I, ctypes.POINTER(D), P]
+    lib.gplmm_mlp_grad.restype = I
+    lib.gplmm_mlp_adam.argtypes = [P, D, D, D, D]
+    lib.gplmm_mlp_adam.restype = I
+    lib.gplmm_mlp_train.argtypes = [P, P, P, I, I, I, D, ctypes.POINTER(D)]
+    lib.gplmm_mlp_train.restype = I
+    lib.gplmm_mlp_last_error.argtypes = [P]
+    lib.gplmm_mlp_last_error.restype = ctypes.c_char_p
+    lib.gplmm_mlp_destroy.argtypes = [P]
+    lib.gplmm_mlp_destroy.restype = V
     _lib = lib
     return lib
 
@@ -294,3 +317,77 @@ class Solver:
 
     def reset_timers(self):
         self.lib.gplmm_reset_timers(self.ctx)
+
+
+class Mlp:
+    """The BF16 matrix-core MLP of the library (learned coarse coefficients).
+
+    Parameters are exchanged as a flat FP32 array in the packed layout of
+    ``gplmm_mlp_num_params``: per layer W (fan_in x fan_out, row-major), then b."""
+
+    def __init__(self, nin, nhidden=128, nlayers=3, nout=1, max_batch=4096):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.nin, self.nout = nin, nout
+        self.m = ctypes.c_void_p()
+        rc = self.lib.gplmm_mlp_create(nin, nhidden, nlayers, nout, max_batch, None, ctypes.byref(self.m))
+        if rc != 0:
+            raise GplmmError("gplmm_mlp_create failed (%d)" % rc)
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise GplmmError("%s: %s (%d)" % (what, self.lib.gplmm_mlp_last_error(self.m).decode(), rc))
+        return rc
+
+    def _f32(self, t):
+        t = self.torch.as_tensor(t, dtype=self.torch.float32, device="cuda")
+        return t.contiguous()
+
+    def num_params(self):
+        return int(self.lib.gplmm_mlp_num_params(self.m))
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.num_params()
+        self._check(self.lib.gplmm_mlp_set_params(self.m, a.ctypes.data), "mlp_set_params")
+
+    def get_params(self):
+        a = np.zeros(self.num_params(), np.float32)
+        self._check(self.lib.gplmm_mlp_get_params(self.m, a.ctypes.data), "mlp_get_params")
+        return a
+
+    def forward(self, x):
+        x = self._f32(x)
+        y = self.torch.empty((x.shape[0], self.nout), dtype=self.torch.float32, device="cuda")
+        self._check(self.lib.gplmm_mlp_forward(self.m, _ptr(x), x.shape[0], _ptr(y)), "mlp_forward")
+        return y
+
+    def grad(self, x, t):
+        x, t = self._f32(x), self._f32(t)
+        loss = ctypes.c_double()
+        g = np.zeros(self.num_params(), np.float32)
+        self._check(self.lib.gplmm_mlp_grad(self.m, _ptr(x), _ptr(t), x.shape[0], ctypes.byref(loss),
+                                            g.ctypes.data), "mlp_grad")
+        return loss.value, g
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self._check(self.lib.gplmm_mlp_adam(self.m, lr, b1, b2, eps), "mlp_adam")
+
+    def train(self, x, t, epochs=10, batch=1024, lr=1e-3):
+        x, t = self._f32(x), self._f32(t)
+        loss = ctypes.c_double()
+        self._check(self.lib.gplmm_mlp_train(self.m, _ptr(x), _ptr(t), x.shape[0], epochs, batch, lr,
+                                             ctypes.byref(loss)), "mlp_train")
+        return loss.value
+
+    def close(self):
+        if self.m:
+            self.lib.gplmm_mlp_destroy(self.m)
+            self.m = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
