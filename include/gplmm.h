@@ -129,6 +129,9 @@ typedef struct {
     int converged;
     int gs_reorth;           /* Arnoldi steps that needed a second Gram-Schmidt projection */
     double step_length[64];  /* Newton step length lambda of each Newton step */
+    double t_coarse_ms;      /* coarse-operator assembly (probing or learned inference), all builds */
+    int learned_builds;      /* builds whose coarse operator came from the learned model */
+    int coarse_fallbacks;    /* Newton steps redone with the exact coarse operator */
 } gplmm_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -266,6 +269,23 @@ int gplmm_mlp_train(gplmm_mlp* mlp, const float* x_dev, const float* t_dev, int 
                     double lr, double* loss_out);
 
 const char* gplmm_mlp_last_error(const gplmm_mlp* mlp);
+
+/* Use a trained model (kCoarse features in, one value out) for the coarse operator of
+ * every following build of ctx, NULL = the exact operator (probing of Rhat X Phat).
+ * The model predicts asinh(entry / scale) on the structural pattern of the coarse operator
+ * (see gplmm_coarse_entries); an operator that cannot be factorised falls back to the
+ * exact one, and gplmm_newton_solve redoes a Newton step with the exact operator when
+ * FGMRES misses its tolerance.  The model stays owned by the caller and must outlive
+ * its use. */
+int gplmm_set_coarse_model(gplmm_ctx* ctx, gplmm_mlp* model);
+
+/* The structural entries of the coarse operator (row, col: coarse ids, interfaces first,
+ * then the primaries' correction unknowns), their features (16 FP32 values per entry,
+ * from the geometry and the current wind) and scales, and, when exact != NULL, their
+ * values in the last build, which must have used the exact operator (training labels
+ * are asinh(exact / scale)).  Call with every array NULL to get *nent.  Host arrays. */
+int gplmm_coarse_entries(gplmm_ctx* ctx, int64_t* nent, int32_t* rows, int32_t* cols, float* feat, float* scale,
+                         double* exact);
 
 void gplmm_mlp_destroy(gplmm_mlp* mlp);
 

@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
                 ("r0_norm", ctypes.c_double), ("t_build_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("builds", ctypes.c_int), ("converged", ctypes.c_int), ("gs_reorth", ctypes.c_int),
-                ("step_length", ctypes.c_double * 64)]
+                ("step_length", ctypes.c_double * 64), ("t_coarse_ms", ctypes.c_double),
+                ("learned_builds", ctypes.c_int), ("coarse_fallbacks", ctypes.c_int)]
 
     def as_dict(self):
         n = self.newton_its
@@ -52,7 +53,9 @@ class Stats(ctypes.Structure):
                     res_hist=[self.res_hist[k] for k in range(n + 1)],
                     r0_norm=self.r0_norm, t_build_ms=self.t_build_ms, t_solve_ms=self.t_solve_ms,
                     t_total_ms=self.t_total_ms, builds=self.builds, converged=bool(self.converged),
-                    gs_reorth=self.gs_reorth, step_length=[self.step_length[k] for k in range(n)])
+                    gs_reorth=self.gs_reorth, step_length=[self.step_length[k] for k in range(n)],
+                    t_coarse_ms=self.t_coarse_ms, learned_builds=self.learned_builds,
+                    coarse_fallbacks=self.coarse_fallbacks)
 
 
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",
@@ -61,7 +64,7 @@ EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_g
            "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy",
            "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
            "gplmm_mlp_forward", "gplmm_mlp_grad", "gplmm_mlp_adam", "gplmm_mlp_train", "gplmm_mlp_last_error",
-           "gplmm_mlp_destroy"]
+           "gplmm_mlp_destroy", "gplmm_set_coarse_model", "gplmm_coarse_entries"]
 
 _lib = None
 
@@ -133,6 +136,10 @@ def load():
     lib.gplmm_mlp_last_error.restype = ctypes.c_char_p
     lib.gplmm_mlp_destroy.argtypes = [P]
     lib.gplmm_mlp_destroy.restype = V
+    lib.gplmm_set_coarse_model.argtypes = [P, P]
+    lib.gplmm_set_coarse_model.restype = I
+    lib.gplmm_coarse_entries.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P, P, P, P, P]
+    lib.gplmm_coarse_entries.restype = I
     _lib = lib
     return lib
 
@@ -291,6 +298,26 @@ class Solver:
         A = np.zeros((n.value, n.value))
         self._check(self.lib.gplmm_get_coarse(self.ctx, A.ctypes.data, None), "get_coarse")
         return A
+
+    def coarse_entries(self, exact=True):
+        """Pattern, features, scales (and exact values of the last exact build) of the
+        coarse operator's entries."""
+        n = ctypes.c_int64()
+        self._check(self.lib.gplmm_coarse_entries(self.ctx, ctypes.byref(n), None, None, None, None, None),
+                    "coarse_entries")
+        k = n.value
+        rows, cols = np.zeros(k, np.int32), np.zeros(k, np.int32)
+        feat, scale = np.zeros((k, 16), np.float32), np.zeros(k, np.float32)
+        ex = np.zeros(k) if exact else None
+        self._check(self.lib.gplmm_coarse_entries(self.ctx, ctypes.byref(n), rows.ctypes.data, cols.ctypes.data,
+                                                  feat.ctypes.data, scale.ctypes.data,
+                                                  ex.ctypes.data if exact else None), "coarse_entries")
+        return dict(rows=rows, cols=cols, feat=feat, scale=scale, exact=ex)
+
+    def set_coarse_model(self, mlp):
+        self._check(self.lib.gplmm_set_coarse_model(self.ctx, mlp.m if mlp is not None else None),
+                    "set_coarse_model")
+        self._coarse_model = mlp   # keep it alive while the context uses it
 
     def precond_apply(self, v, out=None):
         out = self.zeros() if out is None else out

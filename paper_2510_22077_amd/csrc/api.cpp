@@ -494,6 +494,41 @@ int gplmm_build(gplmm_ctx* c, const double* wind) {
     return rc;
 }
 
+int gplmm_set_coarse_model(gplmm_ctx* c, gplmm_mlp* model) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (model && (gp::mlp_width_in(model) != gp::kCoarseFeatures || gp::mlp_width_out(model) != 1))
+        return gp::fail(c, GPLMM_E_ARG, "the coarse model must map 16 features to one value");
+    c->coarse_model = model;
+    return GPLMM_OK;
+}
+
+int gplmm_coarse_entries(gplmm_ctx* c, int64_t* nent, int32_t* rows, int32_t* cols, float* feat, float* scale,
+                         double* exact) {
+    if (!c || !nent) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    std::vector<double> wh(c->N);
+    GP_HIP(c, hipMemcpyAsync(wh.data(), c->d_wind, sizeof(double) * c->N, hipMemcpyDeviceToHost, c->stream));
+    GP_HIP(c, hipStreamSynchronize(c->stream));
+    std::vector<float> f, s;
+    gp::coarse_features(c, wh.data(), f, s);
+    const int64_t ne = (int64_t)c->cl_row.size();
+    *nent = ne;
+    if (rows) std::copy(c->cl_row.begin(), c->cl_row.end(), rows);
+    if (cols) std::copy(c->cl_col.begin(), c->cl_col.end(), cols);
+    if (feat) std::copy(f.begin(), f.end(), feat);
+    if (scale) std::copy(s.begin(), s.end(), scale);
+    if (exact) {
+        if (!c->built || c->last_coarse_learned)
+            return gp::fail(c, GPLMM_E_STATE, "exact coarse values need a preceding build with the exact operator");
+        const int nco = c->nco;
+        std::vector<double> A((size_t)nco * nco);
+        GP_HIP(c, hipMemcpy(A.data(), c->d_Aoasm, sizeof(double) * A.size(), hipMemcpyDeviceToHost));
+        for (int64_t e = 0; e < ne; ++e) exact[e] = A[(size_t)c->cl_row[e] * nco + c->cl_col[e]];
+    }
+    return GPLMM_OK;
+}
+
 int gplmm_get_coarse(gplmm_ctx* c, double* ao, int* nco_out) {
     if (!c) return GPLMM_E_ARG;
     if (nco_out) *nco_out = c->nco;
@@ -537,6 +572,8 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
         int rc = do_build(c);
         S->t_build_ms += c->last_build_ms;
         S->builds++;
+        S->t_coarse_ms += c->last_coarse_ms;
+        S->learned_builds += c->last_coarse_learned ? 1 : 0;
         if (rc) return rc;
     }
     launch_residual(c, x, xprev, c->d_r, c->stream);
@@ -553,6 +590,8 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
             int rc = do_build(c);
             S->t_build_ms += c->last_build_ms;
             S->builds++;
+            S->t_coarse_ms += c->last_coarse_ms;
+            S->learned_builds += c->last_coarse_learned ? 1 : 0;
             if (rc) return rc;
         }
         scal_copy(c, -1.0, c->d_r, c->d_r, N);   // b = -r (fgmres leaves d_r alone)
@@ -560,6 +599,20 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
         bool ok = false;
         int its = fgmres(c, x, c->d_r, c->d_dx, c->opt.lin_tol * r0, c->opt.lin_maxit, &ok);
         if (its < 0) return GPLMM_E_HIP;
+        if (!ok && c->last_coarse_learned) {
+            // the learned coarse operator did not carry FGMRES to the tolerance: rebuild with
+            // the exact one (same wind) for the rest of the solve and redo this step
+            gplmm_mlp* model = c->coarse_model;
+            c->coarse_model = nullptr;
+            int rc = do_build(c);
+            c->coarse_model = model;
+            S->t_build_ms += c->last_build_ms;
+            S->builds++;
+            S->t_coarse_ms += c->last_coarse_ms;
+            S->coarse_fallbacks++;
+            if (rc) return rc;
+            its += fgmres(c, x, c->d_r, c->d_dx, c->opt.lin_tol * r0, c->opt.lin_maxit, &ok);
+        }
         S->t_solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
         S->lin_its[k] = its;
         S->lin_its_total += its;
@@ -638,7 +691,7 @@ void gplmm_destroy(gplmm_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     gplmm_reset_timers(c);
-    void* ptrs[] = {c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
+    void* ptrs[] = {c->d_cl_row, c->d_cl_col, c->d_cl_feat, c->d_cl_pred, c->d_cl_scale, c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,

@@ -168,6 +168,16 @@ struct gplmm_ctx {
     double* d_cv = nullptr;              // coarse vectors (2 x nco)
     bool ready = false;
     bool built = false;
+    // learned coarse operator: pattern (the probing entries), device staging, model
+    gplmm_mlp* coarse_model = nullptr;
+    std::vector<int32_t> cl_row, cl_col;
+    int32_t* d_cl_row = nullptr;
+    int32_t* d_cl_col = nullptr;
+    float* d_cl_feat = nullptr;
+    float* d_cl_pred = nullptr;
+    float* d_cl_scale = nullptr;
+    bool last_coarse_learned = false;    // the last build took the learned coarse operator
+    double last_coarse_ms = 0.0;         // coarse assembly time of the last build (host clock)
     int builds = 0;
     int64_t gs_passes = 0, gs_reorth = 0;   // Gram-Schmidt steps, and those reorthogonalised
     double last_build_ms = 0.0;
@@ -198,6 +208,10 @@ void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipSt
 template <typename T>
 void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s);
 void launch_xcoef(gplmm_ctx* c, hipStream_t s);
+constexpr int kCoarseFeatures = 16;
+int mlp_width_in(const gplmm_mlp* m);
+int mlp_width_out(const gplmm_mlp* m);
+int coarse_features(gplmm_ctx* c, const double* wind_host, std::vector<float>& feat, std::vector<float>& scale);
 void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s);
 
 // krylov.hip

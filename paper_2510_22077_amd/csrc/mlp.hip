@@ -324,6 +324,15 @@ void gplmm_mlp_destroy(gplmm_mlp* m) {
 
 const char* gplmm_mlp_last_error(const gplmm_mlp* m) { return m ? m->err.c_str() : "null model"; }
 
+}  // extern "C"
+
+namespace gp {
+int mlp_width_in(const gplmm_mlp* m) { return m ? m->nin : -1; }
+int mlp_width_out(const gplmm_mlp* m) { return m ? m->nout : -1; }
+}  // namespace gp
+
+extern "C" {
+
 int64_t gplmm_mlp_num_params(const gplmm_mlp* m) {
     if (!m) return -1;
     int64_t n = 0;

@@ -13,6 +13,8 @@
 // colour have restricted images on disjoint coarse rows, so one prolongation,
 // one stencil application and one restriction of the colour's indicator give
 // all of their entries.
+#include <chrono>
+
 #include "internal.h"
 
 namespace gp {
@@ -137,6 +139,17 @@ __global__ void gemv_kernel(const double* __restrict__ A, const double* __restri
     if (threadIdx.x == 0) y[i] = s;
 }
 
+// Ao[row, col] = sinh(prediction) * scale for the learned coarse entries
+__global__ void learned_scatter_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+                                       const float* __restrict__ pred, const float* __restrict__ scale, int64_t n,
+                                       double* __restrict__ Ao, int nco) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    // predictions are clipped to asinh(+-4000): no entry of the normalised operator is larger
+    const double z = fmin(fmax((double)pred[k], -9.0), 9.0);
+    Ao[(int64_t)row[k] * nco + col[k]] = sinh(z) * (double)scale[k];
+}
+
 inline unsigned nb(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
 
 }  // namespace
@@ -172,6 +185,39 @@ static void restrict_(gplmm_ctx* c, const V* v, double* out) {
     if (c->nco > 0) restrict_kernel<V><<<c->nco, kB, 0, c->stream>>>(v, c->d_grp_ptr, c->d_grp_slot, out);
 }
 
+// Learned coarse entries: features from the current wind (host), network inference,
+// scatter into the dense coarse operator.
+static int learned_coarse(gplmm_ctx* c) {
+    hipStream_t s = c->stream;
+    std::vector<double> wh(c->N);
+    GP_HIP(c, hipMemcpyAsync(wh.data(), c->d_wind, sizeof(double) * c->N, hipMemcpyDeviceToHost, s));
+    GP_HIP(c, hipStreamSynchronize(s));
+    std::vector<float> feat, scale;
+    coarse_features(c, wh.data(), feat, scale);
+    const int64_t ne = (int64_t)c->cl_row.size();
+    if (!c->d_cl_row) {   // first learned build: device staging of the pattern
+        const size_t n1 = (size_t)std::max<int64_t>(ne, 1);
+        GP_HIP(c, hipMalloc((void**)&c->d_cl_row, sizeof(int32_t) * n1));
+        GP_HIP(c, hipMalloc((void**)&c->d_cl_col, sizeof(int32_t) * n1));
+        GP_HIP(c, hipMalloc((void**)&c->d_cl_feat, sizeof(float) * n1 * kCoarseFeatures));
+        GP_HIP(c, hipMalloc((void**)&c->d_cl_pred, sizeof(float) * n1));
+        GP_HIP(c, hipMalloc((void**)&c->d_cl_scale, sizeof(float) * n1));
+        GP_HIP(c, hipMemcpy(c->d_cl_row, c->cl_row.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice));
+        GP_HIP(c, hipMemcpy(c->d_cl_col, c->cl_col.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice));
+    }
+    GP_HIP(c, hipMemcpyAsync(c->d_cl_feat, feat.data(), sizeof(float) * feat.size(), hipMemcpyHostToDevice, s));
+    GP_HIP(c, hipMemcpyAsync(c->d_cl_scale, scale.data(), sizeof(float) * ne, hipMemcpyHostToDevice, s));
+    GP_HIP(c, hipStreamSynchronize(s));
+    int rc = gplmm_mlp_forward(c->coarse_model, c->d_cl_feat, (int)ne, c->d_cl_pred);
+    if (rc != GPLMM_OK) return fail(c, rc, "coarse model inference failed");
+    GP_HIP(c, hipDeviceSynchronize());
+    learned_scatter_kernel<<<nb(ne), kB, 0, s>>>(c->d_cl_row, c->d_cl_col, c->d_cl_pred, c->d_cl_scale, ne, c->d_Ao,
+                                                 c->nco);
+    GP_HIP(c, hipGetLastError());
+    GP_HIP(c, hipStreamSynchronize(s));
+    return GPLMM_OK;
+}
+
 template <typename T>
 int build_precond(gplmm_ctx* c) {
     hipStream_t s = c->stream;
@@ -193,8 +239,29 @@ int build_precond(gplmm_ctx* c) {
     GP_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(c, hipStreamSynchronize(s));
     if (flag) return fail(c, GPLMM_E_BREAKDOWN, "zero or non-finite pivot in a local factorisation");
-    // 4. coarse operator Rhat X Phat by probing, in FP64
+    // 4. coarse operator Rhat X Phat: predicted by the learned model when one is set (an
+    //    operator that cannot be factorised falls back to the exact one), else by probing
     const int nco = c->nco;
+    c->last_coarse_learned = false;
+    auto tc0 = std::chrono::steady_clock::now();
+    if (nco > 0 && c->coarse_model) {
+        GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * (int64_t)nco * nco, s));
+        int rc = learned_coarse(c);
+        if (rc == GPLMM_OK) {
+            c->last_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
+            rc = coarse_invert(c);
+            if (rc == GPLMM_OK) {
+                c->last_coarse_learned = true;
+                GP_HIP(c, hipStreamSynchronize(s));
+                c->built = true;
+                c->builds++;
+                return GPLMM_OK;
+            }
+        }
+        if (rc != GPLMM_E_BREAKDOWN) return rc;
+        c->err.clear();
+        tc0 = std::chrono::steady_clock::now();
+    }
     if (nco > 0) {
         GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * (int64_t)nco * nco, s));
         double* e = c->d_cv;
@@ -211,6 +278,8 @@ int build_precond(gplmm_ctx* c) {
             int64_t p0 = c->color_off[k], p1 = c->color_off[k + 1];
             probe_scatter_kernel<<<nb(p1 - p0), kB, 0, s>>>(c->d_probe + p0, p1 - p0, tco, c->d_Ao, nco);
         }
+        GP_HIP(c, hipStreamSynchronize(s));
+        c->last_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
         int rc = coarse_invert(c);
         if (rc != GPLMM_OK) return rc;
     }

@@ -1,0 +1,117 @@
+"""Learned coarse coefficients: the pattern and labels the library exposes, the
+exact-operator fallback, and what a trained network gains or loses against the
+exact coarse operator (printed; the FP64 outer residual decides convergence, so
+the solution must match the exact-operator solve to the FP32-mode tolerance)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(name, seed, **kw):
+    from paper_2510_22077_amd import Solver
+    from synth import make_workload
+    w = make_workload(name, seed)
+    return Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"], precision="fp32",
+                  restart=64, newton_tol=1e-8, lin_tol=1e-9, lin_maxit=400, **kw)
+
+
+def _solver_tight(name, seed):
+    from paper_2510_22077_amd import Solver
+    from synth import make_workload
+    w = make_workload(name, seed)
+    return Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"], precision="fp32",
+                  restart=64, newton_tol=1e-12, lin_tol=1e-13, lin_maxit=400)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_pattern_covers_the_exact_coarse_operator():
+    torch = _torch()
+    s = _solver("spheres3d_24", 0)
+    s.build()
+    A = s.coarse_operator()
+    e = s.coarse_entries(exact=True)
+    mask = np.zeros_like(A, dtype=bool)
+    mask[e["rows"], e["cols"]] = True
+    assert np.all(A[~mask] == 0.0)
+    assert np.array_equal(e["exact"], A[e["rows"], e["cols"]])
+    assert np.all(e["scale"] > 0) and np.all(np.isfinite(e["feat"]))
+    kinds = e["feat"][:, :6]
+    assert np.all(kinds.sum(1) == 1.0)
+
+
+def test_a_model_giving_a_singular_operator_falls_back_to_the_exact_one():
+    torch = _torch()
+    from paper_2510_22077_amd import Mlp
+    s = _solver("spheres3d_24", 1)
+    x_exact, st_exact = s.newton_solve()
+    m = Mlp(16, 32, 2, 1, max_batch=1024)          # zero weights: every entry predicted 0
+    s.set_coarse_model(m)
+    x_l, st_l = s.newton_solve()
+    assert st_l["learned_builds"] == 0 and st_l["converged"]
+    assert torch.equal(x_l, x_exact)
+    s.set_coarse_model(None)
+    m.close()
+
+
+def test_trained_model_gain_against_the_exact_operator():
+    torch = _torch()
+    from paper_2510_22077_amd import Mlp
+    from oracle import mlp as R
+    feats, targets = [], []
+    for seed in (0, 1, 2, 3):
+        s = _solver("spheres3d_24", seed)
+        s.newton_solve()
+        e = s.coarse_entries(exact=True)
+        feats.append(e["feat"])
+        targets.append(np.arcsinh(e["exact"] / e["scale"]))
+        s.close()
+    X = np.concatenate(feats)
+    T = np.concatenate(targets)[:, None].astype(np.float32)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(len(X))
+    X, T = X[perm], T[perm]
+    mu = X.mean(0)
+    sd = X.std(0)
+    const = sd < 1e-6
+    sd[const], mu[const] = 1.0, 0.0
+    m = Mlp(16, 128, 3, 1, max_batch=2048)
+    params = R.init_params(16, 128, 3, 1, rng)
+    m.set_params(np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params]).astype(np.float32))
+    loss = m.train(((X - mu) / sd).astype(np.float32), T, epochs=150, batch=512, lr=1e-3)
+    # fold the feature standardisation into the first layer
+    flat = m.get_params()
+    W1 = flat[:16 * 128].reshape(16, 128)
+    b1 = flat[16 * 128:16 * 128 + 128]
+    b1 -= (mu / sd) @ W1
+    W1 /= sd[:, None]
+    m.set_params(flat)
+    s = _solver_tight("spheres3d_24", 5)
+    x_exact, st_exact = s.newton_solve()
+    e = s.coarse_entries(exact=True)
+    z = m.forward(e["feat"]).cpu().numpy()[:, 0]
+    zt = np.arcsinh(e["exact"] / e["scale"])
+    r2 = 1.0 - np.mean((z - zt) ** 2) / np.var(zt)
+    s.set_coarse_model(m)
+    x_l, st_l = s.newton_solve()
+    print("train loss %.3f (target var %.3f); unseen geometry: R2 %.3f" % (loss, float(np.var(T)), r2))
+    print("exact:   newton %d, fgmres %s, coarse assembly %.2f ms, total %.1f ms"
+          % (st_exact["newton_its"], st_exact["lin_its"], st_exact["t_coarse_ms"], st_exact["t_total_ms"]))
+    print("learned: newton %d, fgmres %s, coarse assembly %.2f ms, total %.1f ms, learned builds %d, fallbacks %d"
+          % (st_l["newton_its"], st_l["lin_its"], st_l["t_coarse_ms"], st_l["t_total_ms"], st_l["learned_builds"],
+             st_l["coarse_fallbacks"]))
+    assert st_l["converged"]
+    assert loss < 0.5 * float(np.var(T))
+    assert _rel(x_l.cpu().numpy(), x_exact.cpu().numpy()) <= 1e-8
+    s.set_coarse_model(None)
+    m.close()
