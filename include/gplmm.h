@@ -228,6 +228,29 @@ const char* gplmm_last_error(const gplmm_ctx* ctx);
 
 void gplmm_destroy(gplmm_ctx* ctx);
 
+/* Launch parameters of the hot kernels chosen by gplmm_autotune. */
+typedef struct {
+    int red_blocks;          /* blocks of the Krylov dot-product / update kernels */
+    int stencil_block;       /* threads per block of the stencil kernels */
+    int trsv_mode;           /* 0: subdomain solution kept in LDS during the solves, 1: in HBM */
+    int from_cache;          /* 1 when read from the cache file instead of measured */
+    double t_reduction_ms;   /* best measured Gram-Schmidt step (half a restart cycle of vectors) */
+    double t_stencil_ms;     /* best measured X v + J v */
+    double t_trsv_ms;        /* best measured dual + primary triangular solves (0 if not built) */
+} gplmm_tuning;
+
+/* Measure the candidate launch parameters on this problem (reduction blocks 256..2048,
+ * stencil blocks 128/256/512, triangular-solve variant when the preconditioner is
+ * built) and keep the fastest for every later call on ctx.  cache_path (may be NULL): a
+ * text file of earlier results, one line per (architecture, N, Np, Nc, precision); a
+ * matching line is used without measuring, a new result is appended.  Calls that
+ * overlap on one context race.  Errors: GPLMM_E_STATE (host-only), GPLMM_E_HIP. */
+int gplmm_autotune(gplmm_ctx* ctx, const char* cache_path, gplmm_tuning* out);
+
+/* Set the launch parameters directly (red_blocks 64..2048, stencil_block 128/256/512,
+ * trsv_mode 0/1; the timing fields are ignored).  Errors: GPLMM_E_ARG. */
+int gplmm_set_tuning(gplmm_ctx* ctx, const gplmm_tuning* t);
+
 /* ---------------------------------------------------------------------------
  * Learned coarse coefficients: a small MLP (hidden layers of equal width, GELU
  * in its tanh form, linear output) trained by mean-squared error with Adam.

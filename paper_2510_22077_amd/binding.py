@@ -29,6 +29,12 @@ class Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("line_search", ctypes.c_int)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("red_blocks", ctypes.c_int), ("stencil_block", ctypes.c_int), ("trsv_mode", ctypes.c_int),
+                ("from_cache", ctypes.c_int), ("t_reduction_ms", ctypes.c_double),
+                ("t_stencil_ms", ctypes.c_double), ("t_trsv_ms", ctypes.c_double)]
+
+
 class Layout(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("nrec", ctypes.c_int), ("ncell", ctypes.c_int64),
                 ("N", ctypes.c_int64), ("nface_active", ctypes.c_int64), ("Np", ctypes.c_int),
@@ -64,7 +70,8 @@ EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_g
            "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy",
            "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
            "gplmm_mlp_forward", "gplmm_mlp_grad", "gplmm_mlp_adam", "gplmm_mlp_train", "gplmm_mlp_last_error",
-           "gplmm_mlp_destroy", "gplmm_set_coarse_model", "gplmm_coarse_entries"]
+           "gplmm_mlp_destroy", "gplmm_set_coarse_model", "gplmm_coarse_entries",
+           "gplmm_autotune", "gplmm_set_tuning"]
 
 _lib = None
 
@@ -140,6 +147,10 @@ def load():
     lib.gplmm_set_coarse_model.restype = I
     lib.gplmm_coarse_entries.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P, P, P, P, P]
     lib.gplmm_coarse_entries.restype = I
+    lib.gplmm_autotune.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(Tuning)]
+    lib.gplmm_autotune.restype = I
+    lib.gplmm_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.gplmm_set_tuning.restype = I
     _lib = lib
     return lib
 
@@ -313,6 +324,17 @@ class Solver:
                                                   feat.ctypes.data, scale.ctypes.data,
                                                   ex.ctypes.data if exact else None), "coarse_entries")
         return dict(rows=rows, cols=cols, feat=feat, scale=scale, exact=ex)
+
+    def autotune(self, cache_path=None):
+        """Pick the launch parameters of the hot kernels by measurement (see gplmm_autotune)."""
+        t = Tuning()
+        self._check(self.lib.gplmm_autotune(self.ctx, cache_path.encode() if cache_path else None,
+                                            ctypes.byref(t)), "autotune")
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+    def set_tuning(self, red_blocks=1024, stencil_block=256, trsv_mode=0):
+        t = Tuning(red_blocks, stencil_block, trsv_mode, 0, 0.0, 0.0, 0.0)
+        self._check(self.lib.gplmm_set_tuning(self.ctx, ctypes.byref(t)), "set_tuning")
 
     def set_coarse_model(self, mlp):
         self._check(self.lib.gplmm_set_coarse_model(self.ctx, mlp.m if mlp is not None else None),

@@ -178,6 +178,10 @@ struct gplmm_ctx {
     float* d_cl_scale = nullptr;
     bool last_coarse_learned = false;    // the last build took the learned coarse operator
     double last_coarse_ms = 0.0;         // coarse assembly time of the last build (host clock)
+    // launch parameters chosen by gplmm_autotune (defaults until then)
+    int red_blocks = 1024;               // blocks of the Krylov reductions (<= 2048)
+    int stencil_block = 256;             // threads per block of the stencil kernels (<= 512)
+    int trsv_mode = 0;                   // 0: solution in LDS when it fits, 1: in place in HBM
     int builds = 0;
     int64_t gs_passes = 0, gs_reorth = 0;   // Gram-Schmidt steps, and those reorthogonalised
     double last_build_ms = 0.0;

@@ -8,7 +8,7 @@ namespace gp {
 
 namespace {
 
-constexpr int kRedBlocks = 1024;
+constexpr int kMaxRedBlocks = 2048;   // scratch is sized for this many reduction blocks
 constexpr int kThreads = 256;
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -136,13 +136,13 @@ inline unsigned nb_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThre
 
 }  // namespace
 
-// Device scratch layout in c->d_red: [0, kRedBlocks*(kMaxRestart+1)) partials, then results.
+// Device scratch layout in c->d_red: [0, kMaxRedBlocks*(kMaxRestart+2)) partials, then results.
 static double* partials(gplmm_ctx* c) { return c->d_red; }
-static double* results(gplmm_ctx* c) { return c->d_red + (int64_t)kRedBlocks * (kMaxRestart + 2); }
+static double* results(gplmm_ctx* c) { return c->d_red + (int64_t)kMaxRedBlocks * (kMaxRestart + 2); }
 
 double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n) {
-    multidot_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(a, 0, 1, b, n, partials(c));
-    reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, results(c));
+    multidot_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(a, 0, 1, b, n, partials(c));
+    reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), c->red_blocks, results(c));
     hipMemcpyAsync(c->h_red, results(c), sizeof(double), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
     return c->h_red[0];
@@ -161,8 +161,8 @@ void scal_copy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n
 // h = V[0..k)^T w into device results(c)[0..k) (no host sync)
 static void multi_dot_dev(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* w, int64_t n,
                           double* out_dev) {
-    multidot_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, w, n, partials(c));
-    reduce_kernel<<<k, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, out_dev);
+    multidot_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(V, ldv, k, w, n, partials(c));
+    reduce_kernel<<<k, kThreads, 0, c->stream>>>(partials(c), c->red_blocks, out_dev);
 }
 
 // Classical Gram-Schmidt with the Daniel-Gragg-Kaufman-Stewart reorthogonalisation
@@ -179,11 +179,11 @@ void cgs2(gplmm_ctx* c, const double* V, int64_t ldv, int k, double* w, int64_t 
     const bool fused = w == V + (int64_t)k * ldv;
     multi_dot_dev(c, V, ldv, fused ? k + 1 : k, w, n, h1);
     if (!fused) {
-        multidot_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(w, 0, 1, w, n, partials(c));
-        reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, h1 + k);
+        multidot_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(w, 0, 1, w, n, partials(c));
+        reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), c->red_blocks, h1 + k);
     }
-    update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h1, w, n, partials(c));
-    reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, nr);
+    update_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(V, ldv, k, h1, w, n, partials(c));
+    reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), c->red_blocks, nr);
     hipMemcpyAsync(c->h_red, h1, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, c->stream);
     hipMemcpyAsync(c->h_red + (kMaxRestart + 2), nr, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
@@ -193,8 +193,8 @@ void cgs2(gplmm_ctx* c, const double* V, int64_t ldv, int k, double* w, int64_t 
     c->gs_passes++;
     if (!(after > 0.5 * before)) {
         multi_dot_dev(c, V, ldv, k, w, n, h2);
-        update_kernel<<<kRedBlocks, kThreads, 0, c->stream>>>(V, ldv, k, h2, w, n, partials(c));
-        reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), kRedBlocks, nr);
+        update_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(V, ldv, k, h2, w, n, partials(c));
+        reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), c->red_blocks, nr);
         hipMemcpyAsync(c->h_red, h2, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream);
         hipMemcpyAsync(c->h_red + (kMaxRestart + 2), nr, sizeof(double), hipMemcpyDeviceToHost, c->stream);
         hipStreamSynchronize(c->stream);
@@ -221,6 +221,6 @@ template void convert<double, float>(gplmm_ctx*, const double*, float*, int64_t)
 template void convert<float, double>(gplmm_ctx*, const float*, double*, int64_t);
 template void convert<double, double>(gplmm_ctx*, const double*, double*, int64_t);
 
-int64_t red_scratch_doubles() { return (int64_t)kRedBlocks * (kMaxRestart + 2) + 4 * (kMaxRestart + 2) + 64; }
+int64_t red_scratch_doubles() { return (int64_t)kMaxRedBlocks * (kMaxRestart + 2) + 4 * (kMaxRestart + 2) + 64; }
 
 }  // namespace gp

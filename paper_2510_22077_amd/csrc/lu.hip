@@ -614,7 +614,7 @@ void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vi
     const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)rows * (3.0 * sizeof(T) + 4.0);
     timer_begin(c, "trsv");
     const size_t lds = (size_t)c->maxT * kT * sizeof(T);
-    if (lds <= kTrsvLdsMax)
+    if (lds <= kTrsvLdsMax && c->trsv_mode == 0)
         trsv_sub_kernel<T, true><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
                                                                 c->d_sub_slots, vin, out_local, c->d_local_off);
     else

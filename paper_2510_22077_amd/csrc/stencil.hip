@@ -25,7 +25,7 @@ namespace gp {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;   // largest block size the stencil kernels are compiled for
 
 // r(x): momentum and mass residual.
 template <int ND>
@@ -217,25 +217,25 @@ __global__ void bB_kernel(DevGeo g, Phys ph, double* __restrict__ out) {
     out[nr * c + ND] = 0.0;
 }
 
-inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+inline dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
 
 }  // namespace
 
 void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s) {
-    if (c->ndim == 3) residual_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, x, xprev, r);
-    else residual_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, x, xprev, r);
+    if (c->ndim == 3) residual_kernel<3><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, x, xprev, r);
+    else residual_kernel<2><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, x, xprev, r);
 }
 
 void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s) {
-    if (c->ndim == 3) jv_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, xk, v, y);
-    else jv_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, xk, v, y);
+    if (c->ndim == 3) jv_kernel<3><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, xk, v, y);
+    else jv_kernel<2><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, xk, v, y);
 }
 
 void launch_xcoef(gplmm_ctx* c, hipStream_t s) {
     if (c->ndim == 3)
-        xcoef_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+        xcoef_kernel<3><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
     else
-        xcoef_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+        xcoef_kernel<2><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
 }
 
 template <typename T>
@@ -248,13 +248,13 @@ const float* xcoef_table<float>(gplmm_ctx* c) { return c->d_xcoef_f; }
 template <typename T>
 void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s) {
     const T* cf = xcoef_table<T>(c);
-    if (c->ndim == 3) xv_kernel<3, T><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, cf, sub_from, v, y);
-    else xv_kernel<2, T><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, cf, sub_from, v, y);
+    if (c->ndim == 3) xv_kernel<3, T><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, cf, sub_from, v, y);
+    else xv_kernel<2, T><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, cf, sub_from, v, y);
 }
 
 void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s) {
-    if (c->ndim == 3) bB_kernel<3><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, bB);
-    else bB_kernel<2><<<grid_for(c->ncell), kBlock, 0, s>>>(c->geo, c->phys, bB);
+    if (c->ndim == 3) bB_kernel<3><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, bB);
+    else bB_kernel<2><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, bB);
 }
 
 template void launch_xv<float>(gplmm_ctx*, const float*, float*, const float*, hipStream_t);
