@@ -102,6 +102,10 @@ typedef struct {
                                 lambda * delta with lambda = 1, 1/2, ... >= 1/64, the first
                                 lambda with ||r(x + lambda delta)|| <= (1 - 1e-4 lambda) ||r(x)||
                                 (the smallest if none); 0: full steps */
+    int use_graph;           /* 1 (default): the preconditioner application is captured once
+                                in a HIP graph and replayed (input and output staged through
+                                buffers owned by the context); 0: launched kernel by kernel.
+                                Timed runs (gplmm_set_timing) always launch kernel by kernel */
 } gplmm_options;
 
 typedef struct {

@@ -246,9 +246,52 @@ int do_build(gplmm_ctx* c) {
     return rc;
 }
 
+static int apply_eager(gplmm_ctx* c, const double* v, double* z) {
+    return c->opt.precision == GPLMM_FP32 ? apply_precond<float>(c, v, z) : apply_precond<double>(c, v, z);
+}
+
+// Capture one application, from the staging input to the staging output, on a private
+// stream (the context's stream may be the default stream, which cannot be captured).
+static int capture_apply(gplmm_ctx* c) {
+    if (c->apply_exec) {
+        (void)hipGraphExecDestroy(c->apply_exec);
+        c->apply_exec = nullptr;
+    }
+    if (c->apply_graph) {
+        (void)hipGraphDestroy(c->apply_graph);
+        c->apply_graph = nullptr;
+    }
+    if (!c->cap_stream) GP_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->d_gin) {
+        GP_TRY(alloc(c, (void**)&c->d_gin, sizeof(double) * c->N));
+        GP_TRY(alloc(c, (void**)&c->d_gout, sizeof(double) * c->N));
+    }
+    GP_HIP(c, hipStreamSynchronize(c->stream));
+    hipStream_t keep = c->stream;
+    c->stream = c->cap_stream;
+    GP_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = apply_eager(c, c->d_gin, c->d_gout);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = keep;
+    if (rc != GPLMM_OK) return rc;
+    if (e != hipSuccess) return fail(c, GPLMM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    c->apply_graph = g;
+    GP_HIP(c, hipGraphInstantiate(&c->apply_exec, g, nullptr, nullptr, 0));
+    c->graph_valid = true;
+    return GPLMM_OK;
+}
+
 int do_apply(gplmm_ctx* c, const double* v, double* z) {
+    if (c->opt.use_graph && !c->timing) {
+        if (!c->graph_valid) GP_TRY(capture_apply(c));
+        GP_HIP(c, hipMemcpyAsync(c->d_gin, v, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
+        GP_HIP(c, hipGraphLaunch(c->apply_exec, c->stream));
+        GP_HIP(c, hipMemcpyAsync(z, c->d_gout, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
+        return GPLMM_OK;
+    }
     timer_begin(c, "precond_apply");
-    int rc = c->opt.precision == GPLMM_FP32 ? apply_precond<float>(c, v, z) : apply_precond<double>(c, v, z);
+    int rc = apply_eager(c, v, z);
     timer_end(c, "precond_apply", c->apply_bytes);
     return rc;
 }
@@ -344,6 +387,7 @@ void gplmm_default_options(gplmm_options* o) {
     o->newton_tol = 1e-8;
     o->lin_tol = 1e-9;
     o->line_search = 1;
+    o->use_graph = 1;
     o->newton_maxit = 30;
     o->lin_maxit = 600;
     o->tile = 0;
@@ -691,7 +735,10 @@ void gplmm_destroy(gplmm_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     gplmm_reset_timers(c);
-    void* ptrs[] = {c->d_cl_row, c->d_cl_col, c->d_cl_feat, c->d_cl_pred, c->d_cl_scale, c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
+    if (c->apply_exec) (void)hipGraphExecDestroy(c->apply_exec);
+    if (c->apply_graph) (void)hipGraphDestroy(c->apply_graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    void* ptrs[] = {c->d_gin, c->d_gout, c->d_cl_row, c->d_cl_col, c->d_cl_feat, c->d_cl_pred, c->d_cl_scale, c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,

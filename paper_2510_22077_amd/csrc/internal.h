@@ -182,6 +182,13 @@ struct gplmm_ctx {
     int red_blocks = 1024;               // blocks of the Krylov reductions (<= 2048)
     int stencil_block = 256;             // threads per block of the stencil kernels (<= 512)
     int trsv_mode = 0;                   // 0: solution in LDS when it fits, 1: in place in HBM
+    // graph of one preconditioner application (captured on first use, replayed after)
+    hipGraph_t apply_graph = nullptr;
+    hipGraphExec_t apply_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    double* d_gin = nullptr;
+    double* d_gout = nullptr;
+    bool graph_valid = false;
     int builds = 0;
     int64_t gs_passes = 0, gs_reorth = 0;   // Gram-Schmidt steps, and those reorthogonalised
     double last_build_ms = 0.0;

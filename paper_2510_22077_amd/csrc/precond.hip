@@ -150,7 +150,19 @@ __global__ void learned_scatter_kernel(const int32_t* __restrict__ row, const in
     Ao[(int64_t)row[k] * nco + col[k]] = sinh(z) * (double)scale[k];
 }
 
+template <typename T>
+__global__ void zero_kernel(T* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (T)0;
+}
+
 inline unsigned nb(int64_t n) { return (unsigned)((n + kB - 1) / kB); }
+
+// zero fill as a kernel (the application is captured in a graph, which gets no memset nodes)
+template <typename T>
+void zero_fill(gplmm_ctx* c, T* p, int64_t n) {
+    if (n > 0) zero_kernel<T><<<nb(n), kB, 0, c->stream>>>(p, n);
+}
 
 }  // namespace
 
@@ -171,7 +183,7 @@ static T* pvec(gplmm_ctx* c, int k) {
 // Phat coef (FP64 coarse vector) -> z (type O)
 template <typename T, typename O>
 static void prolong(gplmm_ctx* c, const double* coef, O* z) {
-    hipMemsetAsync(z, 0, sizeof(O) * c->N, c->stream);
+    zero_fill<O>(c, z, c->N);
     if (c->Np > 0)
         prolong_prim_kernel<T, O><<<nb(c->prim_rows), kB, 0, c->stream>>>(
             (const T*)c->d_phi, c->d_phi_off, c->d_phi_cols_off, c->d_phi_cols, c->d_subs, c->d_row_sub,
@@ -306,7 +318,7 @@ int apply_precond(gplmm_ctx* c, const double* v, double* z) {
         gemv_kernel<<<c->nco, kB, 0, s>>>(c->d_Ao, c->d_cv, c->d_cv + c->nco, c->nco);
         prolong<T, T>(c, c->d_cv + c->nco, zG);
     } else {
-        hipMemsetAsync(zG, 0, sizeof(T) * N, s);
+        zero_fill<T>(c, zG, N);
     }
     const T* vin;
     if constexpr (sizeof(T) == sizeof(double)) {
@@ -321,11 +333,11 @@ int apply_precond(gplmm_ctx* c, const double* v, double* z) {
         trsv_gather<T>(c, c->d_sub_ids + c->Np, c->Nc, r1, loc);
         gather_dual_kernel<T><<<nb(N), kB, 0, s>>>(c->d_dinv_ptr, c->d_dinv, loc, zd, N);
     } else {
-        hipMemsetAsync(zd, 0, sizeof(T) * N, s);
+        zero_fill<T>(c, zd, N);
     }
     // r2 = r1 - X z_d ; z_p = M_p^-1 r2 (disjoint primaries)
     launch_xv<T>(c, zd, r2, r1, s);
-    hipMemsetAsync(zp, 0, sizeof(T) * N, s);
+    zero_fill<T>(c, zp, N);
     trsv_gather<T>(c, c->d_sub_ids, c->Np, r2, loc);
     scatter_prim_kernel<T><<<nb(c->prim_rows), kB, 0, s>>>(c->d_sub_slots, c->d_row_sub, c->d_subs, c->d_local_off,
                                                            loc, zp, c->prim_rows);

@@ -158,6 +158,7 @@ extern "C" int gplmm_autotune(gplmm_ctx* c, const char* cache_path, gplmm_tuning
     t.red_blocks = c->red_blocks;
     t.stencil_block = c->stencil_block;
     t.trsv_mode = c->trsv_mode;
+    c->graph_valid = false;
     if (out) *out = t;
     return GPLMM_OK;
 }
@@ -171,5 +172,6 @@ extern "C" int gplmm_set_tuning(gplmm_ctx* c, const gplmm_tuning* t) {
     c->red_blocks = t->red_blocks;
     c->stencil_block = t->stencil_block;
     c->trsv_mode = t->trsv_mode;
+    c->graph_valid = false;   // the captured application holds the old launch shapes
     return GPLMM_OK;
 }
