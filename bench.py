@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--restart", type=int, default=128)
     ap.add_argument("--cpu-crop", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true",
+                    help="skip the comparison solve with the plain FP64 preconditioner")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, five times (the reference "
                          "point for scaling hardware byte counters)")
@@ -118,13 +121,16 @@ def main():
     setup_s = time.perf_counter() - t0
     info = s.info()
     log("setup %.1f s: %s" % (setup_s, json.dumps(info)))
+    tuning = None
+    if not args.no_autotune:
+        s.build()
+        tuning = s.autotune()
+        log("autotune: %s" % json.dumps(tuning))
 
     for k in range(args.warmup):
         x, st = s.newton_solve()
         torch.cuda.synchronize()
         log("warmup %d: %s" % (k, json.dumps({a: st[a] for a in ("newton_its", "lin_its", "t_total_ms")})))
-    s.reset_timers()
-    s.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -135,9 +141,16 @@ def main():
                                                                 "t_solve_ms", "t_total_ms")})))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    s.set_timing(False)
     st = stats[-1]
     sec = el / args.steps
+    # one more solve with per-launch event timers (kernel by kernel, no graph replay) for
+    # the kernel-level figures; not part of the timed steps
+    s.reset_timers()
+    s.set_timing(True)
+    xt, stt = s.newton_solve()
+    torch.cuda.synchronize()
+    s.set_timing(False)
+    log("timed solve: %s" % json.dumps({a: stt[a] for a in ("newton_its", "lin_its", "t_total_ms")}))
 
     # achieved Reynolds number Re = rho U l / mu, U = U_D / phi, l = V_s / A_w
     nrec = info["nrec"]
@@ -193,6 +206,22 @@ def main():
                      "launches": tr["samples"]},
         "kernel_times": kt,
     }
+    out["autotune"] = tuning
+    if not args.no_fp64_plain:
+        log("plain FP64 preconditioner on the same workload ...")
+        del s
+        torch.cuda.empty_cache()
+        s64 = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"],
+                     precision="fp64", newton_tol=1e-8, lin_tol=1e-9, restart=args.restart)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x64, st64 = s64.newton_solve()
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        out["fp64_plain"] = {"s": t64, "newton_its": st64["newton_its"], "fgmres_its_total": st64["lin_its_total"],
+                             "t_build_ms": st64["t_build_ms"],
+                             "rel_diff_vs_fp32_solution": float(torch.linalg.norm(x64 - x) / torch.linalg.norm(x64))}
+        del s64
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a %d^3 crop) ..." % args.cpu_crop)
         out["cpu_baseline"] = _cpu_baseline(w, args.cpu_crop)
