@@ -3,64 +3,206 @@
 // turned into an explicit inverse so that each application of M_G is one dense
 // GEMV (the coarse system is small and ill-conditioned; the paper solves it
 // directly at every application, Section 8's complexity discussion).
+//
+// Blocked right-looking LU with panels of 32 columns: the panel is factorised by
+// one workgroup (pivot search, row interchange and rank-1 updates inside the
+// panel), the interchanges are applied to the other columns, the block row of U
+// is a unit-lower triangular solve, and the trailing matrix takes a rank-32 update
+// (a tiled FP64 product).  The inverse U^-1 L^-1 P is formed by the same two
+// kernels: a forward sweep (triangular solve of a block row, rank-32 update of the
+// rows below) and a backward sweep with U.
 #include "internal.h"
 
 namespace gp {
 
 namespace {
 
-constexpr int kB = 256;
+constexpr int kNB = 32;        // panel width
+constexpr int kPT = 1024;      // panel workgroup
+constexpr int kGT = 64;        // update tile (kGT x kGT outputs, 256 threads, 4 x 4 each)
 
-// Pivot search in column k (rows k..n-1), row swap, column scaling.  One block.
-__global__ void lu_pivot_kernel(double* __restrict__ A, int n, int k, int32_t* __restrict__ piv,
-                                int* __restrict__ flag) {
-    __shared__ double bv[kB];
-    __shared__ int bi[kB];
-    double best = -1.0;
-    int bidx = k;
-    for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
-        double v = fabs(A[(int64_t)i * n + k]);
-        if (v > best) {
-            best = v;
-            bidx = i;
-        }
+// Factor columns [k0, k0 + w) of rows [k0, n) (row-major A, leading dimension n) through
+// a column-major copy P (w columns of length n, so that every pass over the panel is a
+// contiguous, coalesced sweep held in L2); pivot rows are chosen by largest magnitude,
+// lowest index on ties.
+__global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int n, int k0, int w,
+                                                    int32_t* __restrict__ piv, int* __restrict__ flag,
+                                                    double* __restrict__ P) {
+    __shared__ double bv[kPT / 64];
+    __shared__ int bi[kPT / 64];
+    __shared__ double prow[kNB];
+    __shared__ int pivot;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = n - k0;
+    for (int64_t x = tid; x < (int64_t)m * w; x += kPT) {
+        const int t = (int)(x / m), r = k0 + (int)(x % m);
+        P[(int64_t)t * n + r] = A[(int64_t)r * n + k0 + t];
     }
-    bv[threadIdx.x] = best;
-    bi[threadIdx.x] = bidx;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            double o = bv[threadIdx.x + off];
-            int oi = bi[threadIdx.x + off];
-            if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-                bv[threadIdx.x] = o;
-                bi[threadIdx.x] = oi;
+    for (int j = 0; j < w; ++j) {
+        const int col = k0 + j;
+        const double* pc = P + (int64_t)j * n;
+        double best = -1.0;
+        int bidx = n;
+        for (int r = col + tid; r < n; r += kPT) {
+            const double v = fabs(pc[r]);
+            if (v > best) {   // rows visited in increasing order: ties keep the lower index
+                best = v;
+                bidx = r;
             }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_down(best, off, 64);
+            const int oi = __shfl_down(bidx, off, 64);
+            if (ov > best || (ov == best && oi < bidx)) {
+                best = ov;
+                bidx = oi;
+            }
+        }
+        if (lane == 0) {
+            bv[wv] = best;
+            bi[wv] = bidx;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double b = bv[0];
+            int p = bi[0];
+            for (int u = 1; u < kPT / 64; ++u)
+                if (bv[u] > b || (bv[u] == b && bi[u] < p)) {
+                    b = bv[u];
+                    p = bi[u];
+                }
+            if (!(b > 0.0) || !isfinite(b) || p >= n) {
+                atomicOr(flag, 2);
+                p = col;
+            }
+            pivot = p;
+            piv[col] = p;
+        }
+        __syncthreads();
+        const int p = pivot;
+        if (tid < w) {   // interchange inside the panel; keep the pivot row
+            double* q = P + (int64_t)tid * n;
+            const double a = q[col], b = q[p];
+            q[col] = b;
+            q[p] = a;
+            prow[tid] = b;
+        }
+        __syncthreads();
+        const double d = prow[j];
+        for (int r = col + 1 + tid; r < n; r += kPT) {
+            const double l = P[(int64_t)j * n + r] / d;
+            P[(int64_t)j * n + r] = l;
+            for (int t = j + 1; t < w; ++t) P[(int64_t)t * n + r] -= l * prow[t];
         }
         __syncthreads();
     }
-    const int p = bi[0];
-    if (threadIdx.x == 0) {
-        piv[k] = p;
-        if (!(bv[0] > 0.0) || !isfinite(bv[0])) atomicOr(flag, 2);
+    for (int64_t x = tid; x < (int64_t)m * w; x += kPT) {
+        const int t = (int)(x / m), r = k0 + (int)(x % m);
+        A[(int64_t)r * n + k0 + t] = P[(int64_t)t * n + r];
     }
-    if (p != k)
-        for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            double t = A[(int64_t)k * n + j];
-            A[(int64_t)k * n + j] = A[(int64_t)p * n + j];
-            A[(int64_t)p * n + j] = t;
-        }
-    __syncthreads();
-    const double d = A[(int64_t)k * n + k];
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[(int64_t)i * n + k] /= d;
 }
 
-// Trailing update A[i][j] -= A[i][k] A[k][j], i, j > k.
-__global__ void lu_update_kernel(double* __restrict__ A, int n, int k) {
-    const int j = k + 1 + blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = k + 1 + blockIdx.y;
-    if (j >= n || i >= n) return;
-    A[(int64_t)i * n + j] -= A[(int64_t)i * n + k] * A[(int64_t)k * n + j];
+// Apply the interchanges of rows k0 .. k0 + w - 1 (in order) to every column outside
+// [k0, k0 + w), one thread per column.
+__global__ void swap_kernel(double* __restrict__ A, int n, int k0, int w, const int32_t* __restrict__ piv) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || (c >= k0 && c < k0 + w)) return;
+    for (int j = 0; j < w; ++j) {
+        const int r = k0 + j, p = piv[r];
+        if (p != r) {
+            const double t = A[(int64_t)r * n + c];
+            A[(int64_t)r * n + c] = A[(int64_t)p * n + c];
+            A[(int64_t)p * n + c] = t;
+        }
+    }
+}
+
+// Triangular solve of the w-row block starting at row k0 of B (leading dimension ldb),
+// for columns [c0, c1), with the w x w diagonal block of the factor F (leading
+// dimension n) at (k0, k0): lower = 1: unit lower (L), lower = 0: upper with diagonal (U).
+__global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restrict__ F, int n, int k0, int w,
+                                                         double* __restrict__ B, int64_t ldb, int c0, int c1,
+                                                         int lower) {
+    __shared__ double T[kNB][kNB + 1];
+    for (int x = threadIdx.x; x < kNB * kNB; x += blockDim.x) {
+        const int i = x / kNB, j = x % kNB;
+        T[i][j] = (i < w && j < w) ? F[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
+    }
+    __syncthreads();
+    const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    double x[kNB];
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) x[i] = i < w ? B[(int64_t)(k0 + i) * ldb + c] : 0.0;
+    if (lower) {
+#pragma unroll
+        for (int i = 0; i < kNB; ++i) {
+            double v = x[i];
+#pragma unroll
+            for (int s = 0; s < i; ++s) v -= T[i][s] * x[s];
+            x[i] = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = kNB - 1; i >= 0; --i) {
+            if (i >= w) continue;
+            double v = x[i];
+#pragma unroll
+            for (int s = i + 1; s < kNB; ++s)
+                if (s < w) v -= T[i][s] * x[s];
+            x[i] = v / T[i][i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kNB; ++i)
+        if (i < w) B[(int64_t)(k0 + i) * ldb + c] = x[i];
+}
+
+// C[r0 + i][c0 + j] -= sum_{t < w} L[r0 + i][kc + t] * B[kb + t][c0 + j], i < M, j < N.
+// L has leading dimension n, B and C leading dimension ldb (C aliases B).  64 x 64 output
+// tiles, 256 threads, 4 x 4 outputs per thread; operand tiles staged in LDS.
+__global__ void __launch_bounds__(256) rank_update_kernel(const double* __restrict__ L, int n, int kc,
+                                                          const double* B, int64_t ldb, int kb, double* C,
+                                                          int r0, int M, int c0, int N, int w) {
+    __shared__ double La[kGT][kNB + 1];
+    __shared__ double Bb[kNB][kGT + 1];
+    const int ti = blockIdx.y * kGT, tj = blockIdx.x * kGT;
+    const int tid = threadIdx.x;
+    for (int x = tid; x < kGT * kNB; x += 256) {
+        const int i = x / kNB, t = x % kNB;
+        La[i][t] = (ti + i < M && t < w) ? L[(int64_t)(r0 + ti + i) * n + kc + t] : 0.0;
+    }
+    for (int x = tid; x < kNB * kGT; x += 256) {
+        const int t = x / kGT, j = x % kGT;
+        Bb[t][j] = (t < w && tj + j < N) ? B[(int64_t)(kb + t) * ldb + c0 + tj + j] : 0.0;
+    }
+    __syncthreads();
+    const int ty = tid / 16, tx = tid % 16;
+    double acc[4][4] = {};
+#pragma unroll 8
+    for (int t = 0; t < kNB; ++t) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = La[ty + 16 * u][t];
+            b[u] = Bb[t][tx + 16 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = ti + ty + 16 * u;
+        if (i >= M) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = tj + tx + 16 * v;
+            if (j < N) C[(int64_t)(r0 + i) * ldb + c0 + j] -= acc[u][v];
+        }
+    }
 }
 
 // Position of the 1 in column t of P (P A = L U): the recorded swaps applied in order.
@@ -76,92 +218,15 @@ __global__ void perm_pos_kernel(const int32_t* __restrict__ piv, int n, int32_t*
     pos[t] = p;
 }
 
-// Inverse from P A = L U, blocked: block b owns columns [32b, 32b + 32) of X and solves
-// L U X = P I on them, 64 rows at a time (forward with unit L, then backward with U);
-// the off-diagonal updates are 64 x 16 x 32 products staged through LDS.
-constexpr int kIR = 64, kIC = 32, kIK = 16;
-
-__global__ void __launch_bounds__(256) inverse_trsm_kernel(const double* __restrict__ LU,
-                                                           const int32_t* __restrict__ pos, int n,
-                                                           double* __restrict__ X) {
-    __shared__ double At[kIR][kIC + 1];
-    __shared__ double Lk[kIR][kIK + 1];
-    __shared__ double Xk[kIK][kIC + 1];
-    const int c0 = blockIdx.x * kIC;
-    const int tid = threadIdx.x;
-    const int tr = tid >> 3;          // 0..31: rows tr and tr + 32
-    const int tc = (tid & 7) * 4;     // 4 columns
-    const int nb = (n + kIR - 1) / kIR;
-    // X = P I on the owned columns
-    for (int x = tid; x < n * kIC; x += blockDim.x) {
-        int i = x / kIC, t = c0 + x % kIC;
-        if (t < n) X[(int64_t)i * n + t] = (pos[t] == i) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-        const bool fwd = pass == 0;
-        for (int bi = 0; bi < nb; ++bi) {
-            const int I = fwd ? bi : nb - 1 - bi;
-            const int r0 = I * kIR;
-            double acc[2][4];
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 4; ++b) {
-                    int i = r0 + tr + 32 * a, t = c0 + tc + b;
-                    acc[a][b] = (i < n && t < n) ? X[(int64_t)i * n + t] : 0.0;
-                }
-            // off-diagonal blocks: rows [0, r0) forward, [r0 + 64, n) backward
-            const int k_lo = fwd ? 0 : r0 + kIR, k_hi = fwd ? r0 : n;
-            for (int k0 = k_lo; k0 < k_hi; k0 += kIK) {
-                __syncthreads();
-                for (int x = tid; x < kIR * kIK; x += blockDim.x) {
-                    int i = x / kIK, k = x % kIK;
-                    int gi = r0 + i, gk = k0 + k;
-                    Lk[i][k] = (gi < n && gk < k_hi) ? LU[(int64_t)gi * n + gk] : 0.0;
-                }
-                for (int x = tid; x < kIK * kIC; x += blockDim.x) {
-                    int k = x / kIC, t = x % kIC;
-                    int gk = k0 + k, gt = c0 + t;
-                    Xk[k][t] = (gk < k_hi && gt < n) ? X[(int64_t)gk * n + gt] : 0.0;
-                }
-                __syncthreads();
-#pragma unroll 4
-                for (int k = 0; k < kIK; ++k) {
-                    double l0 = Lk[tr][k], l1 = Lk[tr + 32][k];
-                    for (int b = 0; b < 4; ++b) {
-                        double xv = Xk[k][tc + b];
-                        acc[0][b] -= l0 * xv;
-                        acc[1][b] -= l1 * xv;
-                    }
-                }
-            }
-            __syncthreads();
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 4; ++b) At[tr + 32 * a][tc + b] = acc[a][b];
-            // diagonal block: unit-lower forward or upper backward substitution, column-parallel
-            __syncthreads();
-            const int rows = min(kIR, n - r0);
-            for (int st = 0; st < rows; ++st) {
-                const int r = fwd ? st : rows - 1 - st;
-                if (!fwd) {
-                    if (tid < kIC) At[r][tid] /= LU[(int64_t)(r0 + r) * n + (r0 + r)];
-                }
-                __syncthreads();
-                for (int x = tid; x < kIR * kIC; x += blockDim.x) {
-                    int i = x / kIC, t = x % kIC;
-                    bool below = fwd ? (i > r && i < rows) : (i < r);
-                    if (below) At[i][t] -= LU[(int64_t)(r0 + i) * n + (r0 + r)] * At[r][t];
-                }
-                __syncthreads();
-            }
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 4; ++b) {
-                    int i = r0 + tr + 32 * a, t = c0 + tc + b;
-                    if (i < n && t < n) X[(int64_t)i * n + t] = At[tr + 32 * a][tc + b];
-                }
-            __syncthreads();
-        }
-    }
+// X = P I: X[i][t] = (pos[t] == i)
+__global__ void perm_matrix_kernel(const int32_t* __restrict__ pos, int n, double* __restrict__ X) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)n * n) return;
+    const int i = (int)(x / n), t = (int)(x % n);
+    X[x] = pos[t] == i ? 1.0 : 0.0;
 }
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
@@ -169,18 +234,40 @@ int coarse_invert(gplmm_ctx* c) {
     const int n = c->nco;
     hipStream_t s = c->stream;
     double* A = c->d_Aowork;
+    double* X = c->d_Ao;
     GP_HIP(c, hipMemcpyAsync(A, c->d_Ao, sizeof(double) * (int64_t)n * n, hipMemcpyDeviceToDevice, s));
     GP_HIP(c, hipMemcpyAsync(c->d_Aoasm, c->d_Ao, sizeof(double) * (int64_t)n * n, hipMemcpyDeviceToDevice, s));
     GP_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
-    for (int k = 0; k < n; ++k) {
-        lu_pivot_kernel<<<1, kB, 0, s>>>(A, n, k, c->d_piv, c->d_flag);
-        if (k + 1 < n) {
-            dim3 grid((unsigned)((n - k - 1 + kB - 1) / kB), (unsigned)(n - k - 1));
-            lu_update_kernel<<<grid, kB, 0, s>>>(A, n, k);
+    // LU with partial pivoting, panel by panel
+    for (int k0 = 0; k0 < n; k0 += kNB) {
+        const int w = std::min(kNB, n - k0);
+        panel_kernel<<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel);
+        swap_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, c->d_piv);
+        const int r = k0 + w, m = n - r;
+        if (m > 0) {
+            block_trsm_kernel<<<blocks(m, 256), 256, 0, s>>>(A, n, k0, w, A, n, r, n, 1);
+            rank_update_kernel<<<dim3(blocks(m, kGT), blocks(m, kGT)), 256, 0, s>>>(A, n, k0, A, n, k0, A, r, m,
+                                                                                   r, m, w);
         }
     }
-    perm_pos_kernel<<<(n + 255) / 256, 256, 0, s>>>(c->d_piv, n, c->d_piv + n);
-    inverse_trsm_kernel<<<(n + kIC - 1) / kIC, 256, 0, s>>>(A, c->d_piv + n, n, c->d_Ao);
+    // inverse: X = P I, then L^-1 (forward sweep), then U^-1 (backward sweep)
+    perm_pos_kernel<<<blocks(n, 256), 256, 0, s>>>(c->d_piv, n, c->d_piv + n);
+    perm_matrix_kernel<<<blocks((int64_t)n * n, 256), 256, 0, s>>>(c->d_piv + n, n, X);
+    for (int k0 = 0; k0 < n; k0 += kNB) {
+        const int w = std::min(kNB, n - k0);
+        block_trsm_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, X, n, 0, n, 1);
+        const int r = k0 + w, m = n - r;
+        if (m > 0)
+            rank_update_kernel<<<dim3(blocks(n, kGT), blocks(m, kGT)), 256, 0, s>>>(A, n, k0, X, n, k0, X, r, m, 0,
+                                                                                   n, w);
+    }
+    for (int k0 = ((n - 1) / kNB) * kNB; k0 >= 0; k0 -= kNB) {
+        const int w = std::min(kNB, n - k0);
+        block_trsm_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, X, n, 0, n, 0);
+        if (k0 > 0)
+            rank_update_kernel<<<dim3(blocks(n, kGT), blocks(k0, kGT)), 256, 0, s>>>(A, n, k0, X, n, k0, X, 0, k0,
+                                                                                    0, n, w);
+    }
     int flag = 0;
     GP_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(c, hipStreamSynchronize(s));

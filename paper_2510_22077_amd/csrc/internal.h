@@ -189,6 +189,7 @@ struct gplmm_ctx {
     double* d_gin = nullptr;
     double* d_gout = nullptr;
     bool graph_valid = false;
+    double* d_panel = nullptr;            // coarse LU panel scratch (32 x nco)
     int builds = 0;
     int64_t gs_passes = 0, gs_reorth = 0;   // Gram-Schmidt steps, and those reorthogonalised
     double last_build_ms = 0.0;
