@@ -88,8 +88,8 @@ typedef struct {
     int tag_layers;          /* faces within this Chebyshev distance of an interface cell carry
                                 no inertia in X (default 1) */
     int dual_dilations;      /* face-neighbour growths of each interface into its dual grid;
-                                -1 = default (2 in 2D, 0 in 3D) */
-    int restart;             /* FGMRES restart length (default 30, at most 256) */
+                                -1 = default (1 in 2D, 0 in 3D) */
+    int restart;             /* FGMRES restart length (default 30, at most 1024) */
     double newton_tol;       /* stop when ||r(x)|| <= newton_tol * ||r(0)|| (default 1e-8) */
     double lin_tol;          /* FGMRES stops when ||J d + r|| <= lin_tol * ||r(0)|| (default 1e-9) */
     int newton_maxit;        /* default 30 */

@@ -41,10 +41,12 @@ paper asks only for a thinnest separating set, which it does not construct):
 * tags: a face is tagged iff one of its two cells lies within Chebyshev
   distance ``tag_layers`` of an interface cell;
 * dual grid j: the cells of interface j, grown ``dual_dilations`` times by
-  face neighbours through the void space (default 2 in 2D, 0 in 3D: a 3D
+  face neighbours through the void space (default 1 in 2D, 0 in 3D: a 3D
   interface sheet already covers a large share of the cells, and the default
   keeps the union of the dual grids near the 10-30% of the void space the
-  paper reports in its complexity discussion);
+  paper reports in its complexity discussion; wider dual grids overlap more,
+  and the additive sum over overlapping duals then over-corrects: two
+  dilations in 2D stall FGMRES on large disk packings);
 * the unknowns of a cell set: its cells plus every active face with at least
   one flanking cell in the set.
 """
@@ -203,7 +205,7 @@ def free_faces(g, owner, walled):
 
 def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
     if dual_dilations is None:
-        dual_dilations = 2 if g.ndim == 2 else 0
+        dual_dilations = 1 if g.ndim == 2 else 0
     lab_grid = np.asarray(labels)
     if lab_grid.ndim == 2:
         lab_grid = lab_grid[None]

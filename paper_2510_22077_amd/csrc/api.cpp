@@ -408,7 +408,7 @@ int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double m
         *out = c;
         return GPLMM_E_ARG;
     };
-    if (c->opt.restart > kMaxRestart) return bad("restart must be <= 256");
+    if (c->opt.restart > kMaxRestart) return bad("restart must be <= 1024");
     if (c->opt.tile != 32) return bad("only tile = 32 is supported");
     if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return bad("image dimensions must be positive");
     if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024) return bad("image dimensions must be <= 1024");

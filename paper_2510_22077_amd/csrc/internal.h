@@ -13,7 +13,7 @@
 
 namespace gp {
 
-constexpr int kMaxRestart = 256;
+constexpr int kMaxRestart = 1024;
 
 // Geometry as the device kernels see it.
 struct DevGeo {

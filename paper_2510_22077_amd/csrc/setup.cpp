@@ -307,7 +307,7 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
             }
     }
     // ---- dual grids: each interface grown dual_dilations times through face neighbours
-    int dd = c->opt.dual_dilations >= 0 ? c->opt.dual_dilations : (nd == 2 ? 2 : 0);
+    int dd = c->opt.dual_dilations >= 0 ? c->opt.dual_dilations : (nd == 2 ? 1 : 0);
     c->dual_cells.assign(c->Nc, {});
     for (int j = 0; j < c->Nc; ++j) {
         std::vector<int32_t> cur = c->icells[j];
