@@ -113,7 +113,7 @@ typedef struct {
     int64_t ncell, N;        /* kept fluid cells; vector length */
     int64_t nface_active;    /* velocity unknowns */
     int Np, Nc, Ny;          /* primaries, contact interfaces, coarse correction unknowns */
-    int64_t pin;             /* cell whose mass row is replaced by p = 0 */
+    int64_t pin;             /* cell whose mass row is replaced by p = 0 (first sample's in a batch) */
     int64_t ndual_cells;     /* cells covered by at least one dual grid */
     int64_t local_unknowns;  /* sum of the local problem sizes (closure, primary, dual) */
     int64_t factor_bytes;    /* device bytes held by the local factors */
@@ -151,6 +151,36 @@ void gplmm_default_options(gplmm_options* opt);
  * GPLMM_E_GEOMETRY (no fluid), GPLMM_E_HIP. */
 int gplmm_setup(const uint8_t* mask, const int32_t* pore_labels, double rho, double mu,
                 const double body[3], double dt, const gplmm_options* opt, gplmm_ctx** out);
+
+/* A batch of independent samples in one context (many samples of uneven size solved
+ * together: every kernel launch covers all subdomains of all samples).  Sample s is the
+ * host image masks[s] / labels[s] of dims[3s..3s+2] = (nx, ny, nz) voxels (nz = 1 for 2D;
+ * all samples 2D or all 3D, each axis <= 1024), with its own rho[s], mu[s], body force
+ * body[3s..3s+2] and backward-Euler step dt[s] (dt may be NULL: all steady).  The
+ * periodicity, h and every other option come from *opt and apply to every sample.  Each
+ * sample is decomposed exactly as gplmm_setup decomposes it alone (Section 3.2.1);
+ * the batch numbers the cells, primaries and interfaces of sample s after those of
+ * samples 0..s-1 (offsets from gplmm_batch_info), and voxels in the concatenation of
+ * the images.  Each sample keeps its own pinned cell.  The batch is one block-diagonal
+ * system: the coarse operator has one dense block per sample.  gplmm_newton_solve scales
+ * each sample's equations by 1 / ||r_s(0)|| so that FGMRES meets lin_tol ||r_s(0)|| and
+ * Newton newton_tol ||r_s(0)|| on every sample s; res_hist then holds
+ * max_s ||r_s(x_k)|| / ||r_s(0)||, and the line search backtracks per sample.
+ * 1 <= nsamples <= 1024.  Errors as gplmm_setup; the message names the sample. */
+int gplmm_setup_batch(int nsamples, const uint8_t* const* masks, const int32_t* const* pore_labels,
+                      const int32_t* dims, const double* rho, const double* mu, const double* body,
+                      const double* dt, const gplmm_options* opt, gplmm_ctx** out);
+
+/* Offsets of the samples of a batch (a single-image context is a batch of one): arrays
+ * of nsamples + 1 entries, owned by the caller, any may be NULL: cell_off (kept cells;
+ * the vector slots of sample s are [nrec cell_off[s], nrec cell_off[s+1])), voxel_off
+ * (concatenated images), prim_off, iface_off. */
+int gplmm_batch_info(const gplmm_ctx* ctx, int* nsamples, int64_t* cell_off, int64_t* voxel_off,
+                     int32_t* prim_off, int32_t* iface_off);
+
+/* out_host[s] = ||r_s(x)|| / ||r_s(0)|| for every sample s (one entry for a single image):
+ * the relative residual each sample reached. */
+int gplmm_sample_residuals(gplmm_ctx* ctx, const double* x_dev, const double* x_prev_dev, double* out_host);
 
 /* Sizes of the layout and of the decomposition. */
 int gplmm_layout_info(const gplmm_ctx* ctx, gplmm_layout* out);

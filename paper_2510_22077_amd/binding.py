@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                     coarse_fallbacks=self.coarse_fallbacks)
 
 
-EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_layout_info", "gplmm_get_maps",
+EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_setup_batch", "gplmm_batch_info",
+           "gplmm_sample_residuals", "gplmm_layout_info", "gplmm_get_maps",
            "gplmm_get_duals", "gplmm_get_subdomains", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
            "gplmm_precond_apply", "gplmm_get_coarse", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
            "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy",
@@ -91,6 +92,12 @@ def load():
     lib.gplmm_setup.argtypes = [P, P, D, D, ctypes.POINTER(ctypes.c_double), D, ctypes.POINTER(Options),
                                 ctypes.POINTER(ctypes.c_void_p)]
     lib.gplmm_setup.restype = I
+    lib.gplmm_setup_batch.argtypes = [I, P, P, P, P, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]
+    lib.gplmm_setup_batch.restype = I
+    lib.gplmm_batch_info.argtypes = [P, ctypes.POINTER(ctypes.c_int), P, P, P, P]
+    lib.gplmm_batch_info.restype = I
+    lib.gplmm_sample_residuals.argtypes = [P, P, P, P]
+    lib.gplmm_sample_residuals.restype = I
     lib.gplmm_layout_info.argtypes = [P, ctypes.POINTER(Layout)]
     lib.gplmm_layout_info.restype = I
     lib.gplmm_get_maps.argtypes = [P, P, P, P, P, P]
@@ -166,13 +173,7 @@ def _ptr(t):
 class Solver:
     """One gplmm context (one sample, one stream)."""
 
-    def __init__(self, mask, labels, rho=1.0, mu=1.0, body=(1.0, 0.0, 0.0), dt=0.0, h=1.0,
-                 periodic=(1, 0, 0), precision="fp64", wind="stokes", tag_layers=1,
-                 dual_dilations=-1, restart=30, newton_tol=1e-8, lin_tol=1e-9,
-                 newton_maxit=30, lin_maxit=600, host_only=False, stream=None, line_search=True,
-                 use_graph=True):
-        lib = load()
-        self.lib = lib
+    def __init__(self, mask, labels, rho=1.0, mu=1.0, body=(1.0, 0.0, 0.0), dt=0.0, **kw):
         mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
         if mask.ndim == 2:
@@ -181,6 +182,20 @@ class Solver:
         if mask.shape != labels.shape:
             raise ValueError("mask and labels must have the same shape")
         nz, ny, nx = mask.shape
+        o = self._prepare(nx, ny, nz, **kw)
+        b = (ctypes.c_double * 3)(*[float(v) for v in body])
+        ctx = ctypes.c_void_p()
+        rc = self.lib.gplmm_setup(mask.ctypes.data, labels.ctypes.data, float(rho), float(mu), b, float(dt),
+                                  ctypes.byref(o), ctypes.byref(ctx))
+        self._finish(ctx, rc, "gplmm_setup")
+        self.shape = mask.shape
+
+    def _prepare(self, nx, ny, nz, h=1.0, periodic=(1, 0, 0), precision="fp64", wind="stokes", tag_layers=1,
+                 dual_dilations=-1, restart=30, newton_tol=1e-8, lin_tol=1e-9, newton_maxit=30, lin_maxit=600,
+                 host_only=False, stream=None, line_search=True, use_graph=True):
+        lib = load()
+        self.lib = lib
+        self.ctx = ctypes.c_void_p()
         o = Options()
         lib.gplmm_default_options(ctypes.byref(o))
         o.nx, o.ny, o.nz = nx, ny, nz
@@ -209,23 +224,41 @@ class Solver:
                 stream = torch.cuda.current_stream()
             o.stream = ctypes.c_void_p(stream.cuda_stream)
             self.stream = stream
-        b = (ctypes.c_double * 3)(*[float(v) for v in body])
-        ctx = ctypes.c_void_p()
-        rc = lib.gplmm_setup(mask.ctypes.data, labels.ctypes.data, float(rho), float(mu), b, float(dt),
-                             ctypes.byref(o), ctypes.byref(ctx))
+        return o
+
+    def _finish(self, ctx, rc, what):
+        lib = self.lib
         self.ctx = ctx
         if rc != 0:
             msg = lib.gplmm_last_error(ctx).decode() if ctx.value else ""
             if ctx.value:
                 lib.gplmm_destroy(ctx)
                 self.ctx = ctypes.c_void_p()
-            raise GplmmError("gplmm_setup failed (%d, %s): %s" % (rc, ERRORS.get(rc, "?"), msg))
-        self.opts = o
-        self.shape = mask.shape
+            raise GplmmError("%s failed (%d, %s): %s" % (what, rc, ERRORS.get(rc, "?"), msg))
         L = Layout()
         lib.gplmm_layout_info(ctx, ctypes.byref(L))
         self.layout = L
         self.N = L.N
+
+    def batch_info(self):
+        """Per-sample offsets: cells, voxels, primaries, interfaces (nsamples + 1 each)."""
+        ns = ctypes.c_int()
+        self._check(self.lib.gplmm_batch_info(self.ctx, ctypes.byref(ns), None, None, None, None), "batch_info")
+        n = ns.value
+        out = dict(cell_off=np.zeros(n + 1, np.int64), voxel_off=np.zeros(n + 1, np.int64),
+                   prim_off=np.zeros(n + 1, np.int32), iface_off=np.zeros(n + 1, np.int32))
+        self._check(self.lib.gplmm_batch_info(self.ctx, ctypes.byref(ns), *[a.ctypes.data for a in out.values()]),
+                    "batch_info")
+        out["nsamples"] = n
+        return out
+
+    def sample_residuals(self, x, x_prev=None):
+        """||r_s(x)|| / ||r_s(0)|| of every sample (host array)."""
+        n = self.batch_info()["nsamples"]
+        out = np.zeros(n)
+        self._check(self.lib.gplmm_sample_residuals(self.ctx, _ptr(self._vec(x)), _ptr(self._vec(x_prev)),
+                                                    out.ctypes.data), "sample_residuals")
+        return out
 
     # ---- housekeeping
     def close(self):
@@ -368,6 +401,51 @@ class Solver:
 
     def reset_timers(self):
         self.lib.gplmm_reset_timers(self.ctx)
+
+
+
+class BatchSolver(Solver):
+    """Many independent samples in one gplmm context: one block-diagonal system whose
+    subdomains are all factorised and solved in the same launches."""
+
+    def __init__(self, masks, labels, rho=1.0, mu=1.0, bodies=None, dt=None, **kw):
+        ns = len(masks)
+        if ns < 1 or len(labels) != ns:
+            raise ValueError("need one label image per mask")
+        ms, ls, dims = [], [], []
+        for m, l in zip(masks, labels):
+            m = np.ascontiguousarray(np.asarray(m, dtype=np.uint8))
+            l = np.ascontiguousarray(np.asarray(l, dtype=np.int32))
+            if m.ndim == 2:
+                m, l = m[None], l[None]
+            if m.shape != l.shape:
+                raise ValueError("mask and labels must have the same shape")
+            ms.append(m)
+            ls.append(l)
+            dims += [m.shape[2], m.shape[1], m.shape[0]]
+        o = self._prepare(dims[0], dims[1], dims[2], **kw)
+        per = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (ns,)))
+        rho_a, mu_a = per(rho), per(mu)
+        dt_a = per(0.0 if dt is None else dt)
+        if bodies is None:
+            bodies = [(1.0, 0.0, 0.0)] * ns
+        body_a = np.zeros((ns, 3))
+        for s_, b in enumerate(bodies):
+            body_a[s_, :len(b)] = b
+        mptr = (ctypes.c_void_p * ns)(*[m.ctypes.data for m in ms])
+        lptr = (ctypes.c_void_p * ns)(*[l.ctypes.data for l in ls])
+        dims_a = np.asarray(dims, dtype=np.int32)
+        self._keep = (ms, ls, rho_a, mu_a, dt_a, body_a, dims_a)
+        ctx = ctypes.c_void_p()
+        rc = self.lib.gplmm_setup_batch(ns, mptr, lptr, dims_a.ctypes.data, rho_a.ctypes.data, mu_a.ctypes.data,
+                                        body_a.ctypes.data, dt_a.ctypes.data, ctypes.byref(o), ctypes.byref(ctx))
+        self._finish(ctx, rc, "gplmm_setup_batch")
+        self.shapes = [m.shape for m in ms]
+
+    def split(self, x):
+        """Per-sample slices of a batch vector (views)."""
+        off = self.batch_info()["cell_off"] * self.layout.nrec
+        return [x[off[k]:off[k + 1]] for k in range(len(off) - 1)]
 
 
 class Mlp:

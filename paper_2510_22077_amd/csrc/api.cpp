@@ -63,14 +63,29 @@ int alloc(gplmm_ctx* c, void** p, size_t bytes) {
 
 size_t real_size(const gplmm_ctx* c) { return c->opt.precision == GPLMM_FP32 ? 4 : 8; }
 
+// Position of coarse entry (row, col) in the block-diagonal storage (same block assumed).
+int64_t coarse_pos(const gplmm_ctx* c, int row, int col) {
+    const int b = c->co_blk[row];
+    return c->cblk_moff[b] + (int64_t)c->co_loc[row] * c->cblk_n[b] + c->co_loc[col];
+}
+
 int upload_all(gplmm_ctx* c) {
     const int64_t nc = c->ncell, N = c->N;
     const int T = c->tile;
     // geometry
     GP_TRY(upload(c, &c->d_nb6, c->nbr));
     GP_TRY(upload(c, &c->d_tag, c->tagcell));
+    if (!c->csamp.empty()) {   // batch: per-cell sample, per-sample physics and slot ranges
+        GP_TRY(upload(c, &c->d_csamp, c->csamp));
+        GP_TRY(upload(c, &c->d_sphys, c->sphys));
+        std::vector<int64_t> seg;
+        for (const SampleGeo& sg : c->samples) seg.push_back((int64_t)c->nrec * sg.coff);
+        seg.push_back(N);
+        GP_TRY(upload(c, &c->d_seg, seg));
+        GP_TRY(alloc(c, (void**)&c->d_sscale, sizeof(double) * 2 * c->samples.size()));
+    }
     c->geo = DevGeo{c->nx, c->ny, c->nz, c->ndim, c->nrec, {c->opt.periodic[0], c->opt.periodic[1], c->opt.periodic[2]},
-                    nc, (int)c->pin, c->opt.h, c->d_nb6, c->d_tag};
+                    nc, (int)c->pin, c->opt.h, c->d_nb6, c->d_tag, c->d_csamp, c->d_sphys};
     // local problems
     const int nsub = c->Np + c->Nc;
     std::vector<int32_t> row_sub(c->sub_slots.size()), sorted_slot(c->sub_slots.size()), sorted_loc(c->sub_slots.size());
@@ -158,7 +173,8 @@ int upload_all(gplmm_ctx* c) {
                 if (jl == j) g += ih;   // -X[F, p_L] with X[F, p_L] = -1/h
                 rhs[phi_off[i] + (int64_t)k * ld + r] = g;
             }
-            rhs[phi_off[i] + (int64_t)ncp * ld + r] = c->phys.rho * c->phys.body[comp];
+            const Phys& ph = c->csamp.empty() ? c->phys : c->sphys[c->csamp[q]];
+            rhs[phi_off[i] + (int64_t)ncp * ld + r] = ph.rho * ph.body[comp];
         }
     }
     if (c->opt.precision == GPLMM_FP32) {
@@ -209,11 +225,18 @@ int upload_all(gplmm_ctx* c) {
     GP_TRY(upload(c, &c->d_probe, c->probe));
     GP_TRY(upload(c, &c->d_color_cols, c->color_cols));
     const int nco = c->nco;
-    GP_TRY(alloc(c, (void**)&c->d_Ao, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
-    GP_TRY(alloc(c, (void**)&c->d_Aowork, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
-    GP_TRY(alloc(c, (void**)&c->d_Aoasm, sizeof(double) * (int64_t)std::max(nco, 1) * std::max(nco, 1)));
-    GP_TRY(alloc(c, (void**)&c->d_piv, sizeof(int32_t) * 2 * std::max(nco, 1)));
-    GP_TRY(alloc(c, (void**)&c->d_panel, sizeof(double) * 32 * std::max(nco, 1)));
+    const int64_t coe = std::max<int64_t>(c->co_elems, 1);
+    GP_TRY(alloc(c, (void**)&c->d_Ao, sizeof(double) * coe));
+    GP_TRY(alloc(c, (void**)&c->d_Aowork, sizeof(double) * coe));
+    GP_TRY(alloc(c, (void**)&c->d_Aoasm, sizeof(double) * coe));
+    GP_TRY(alloc(c, (void**)&c->d_piv, sizeof(int32_t) * 2 * std::max(c->cblk_max, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_panel, sizeof(double) * 32 * std::max(c->cblk_max, 1)));
+    GP_TRY(upload(c, &c->d_co_blk, c->co_blk));
+    GP_TRY(upload(c, &c->d_co_loc, c->co_loc));
+    GP_TRY(upload(c, &c->d_cblk_n, c->cblk_n));
+    GP_TRY(upload(c, &c->d_cblk_idx, c->cblk_idx));
+    GP_TRY(upload(c, &c->d_cblk_ioff, c->cblk_ioff));
+    GP_TRY(upload(c, &c->d_cblk_moff, c->cblk_moff));
     GP_TRY(alloc(c, (void**)&c->d_cv, sizeof(double) * 2 * std::max(nco, 1)));
     GP_TRY(alloc(c, (void**)&c->d_flag, sizeof(int) * 4));
     // vectors
@@ -395,36 +418,41 @@ void gplmm_default_options(gplmm_options* o) {
     o->stream = nullptr;
 }
 
-int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double mu, const double body[3], double dt,
-                const gplmm_options* opt, gplmm_ctx** out) {
-    if (!mask || !labels || !opt || !out || !body) return GPLMM_E_ARG;
-    *out = nullptr;
-    gplmm_ctx* c = new gplmm_ctx();
-    c->opt = *opt;
+// Options check shared by the single-image and batch set-ups.
+static int check_options(gplmm_ctx* c, const gplmm_options* opt, double rho, double mu) {
     if (c->opt.restart <= 0) c->opt.restart = 30;
     if (c->opt.tile == 0) c->opt.tile = 32;
-    auto bad = [&](const char* m) {
-        c->err = m;
-        *out = c;
-        return GPLMM_E_ARG;
-    };
-    if (c->opt.restart > kMaxRestart) return bad("restart must be <= 1024");
-    if (c->opt.tile != 32) return bad("only tile = 32 is supported");
-    if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return bad("image dimensions must be positive");
-    if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024) return bad("image dimensions must be <= 1024");
-    if (!(rho > 0) || !(mu > 0) || !(opt->h > 0)) return bad("rho, mu and h must be positive");
+    if (c->opt.restart > kMaxRestart) return fail(c, GPLMM_E_ARG, "restart must be <= 1024");
+    if (c->opt.tile != 32) return fail(c, GPLMM_E_ARG, "only tile = 32 is supported");
+    if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return fail(c, GPLMM_E_ARG, "image dimensions must be positive");
+    if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024)
+        return fail(c, GPLMM_E_ARG, "image dimensions must be <= 1024");
+    if (!(rho > 0) || !(mu > 0) || !(opt->h > 0)) return fail(c, GPLMM_E_ARG, "rho, mu and h must be positive");
+    return GPLMM_OK;
+}
+
+static void set_dims(gplmm_ctx* c, int nx, int ny, int nz) {
     c->tile = 32;
-    c->nx = opt->nx;
-    c->ny = opt->ny;
-    c->nz = opt->nz;
-    c->ndim = opt->nz == 1 ? 2 : 3;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->ndim = nz == 1 ? 2 : 3;
     c->nrec = c->ndim + 1;
-    c->nvox = (int64_t)c->nx * c->ny * c->nz;
-    c->phys = Phys{rho, mu, {body[0], body[1], c->ndim == 3 ? body[2] : 0.0}, dt > 0 ? dt : 0.0};
-    c->stream = (hipStream_t)opt->stream;
-    int rc = build_decomposition(c, mask, labels);
-    if (rc == GPLMM_OK) rc = build_local_problems(c);
+    c->nvox = (int64_t)nx * ny * nz;
+}
+
+// Everything after the decomposition: local problems, probing, coarse blocks, uploads.
+static int finish_setup(gplmm_ctx* c) {
+    int rc = build_local_problems(c);
     if (rc == GPLMM_OK) rc = build_probing(c);
+    if (rc == GPLMM_OK) {
+        build_coarse_blocks(c);
+        for (const ProbeEntry& p : c->probe)   // every coarse coupling stays inside one block
+            if (c->co_blk[p.row] != c->co_blk[p.col]) {
+                rc = fail(c, GPLMM_E_GEOMETRY, "a coarse coupling crosses two samples");
+                break;
+            }
+    }
     if (rc == GPLMM_OK && !c->opt.host_only) rc = upload_all(c);
     if (rc == GPLMM_OK && !c->opt.host_only) {   // X of the zero wind until the first build
         launch_xcoef(c, c->stream);
@@ -435,13 +463,99 @@ int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double m
         // every local factor read once, the shape vectors once, the coarse inverse once,
         // and about 16 vector passes over N slots
         const double rs = (double)real_size(c);
-        c->apply_bytes = rs * (double)c->factor_elems + rs * (double)c->phi_elems +
-                         8.0 * (double)c->nco * c->nco + 16.0 * rs * (double)c->N;
+        c->apply_bytes = rs * (double)c->factor_elems + rs * (double)c->phi_elems + 8.0 * (double)c->co_elems +
+                         16.0 * rs * (double)c->N;
         c->jv_bytes = 8.0 * 3.0 * (double)c->N + 24.0 * (double)c->ncell;
         c->ready = true;
     }
-    *out = c;
     return rc;
+}
+
+int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double mu, const double body[3], double dt,
+                const gplmm_options* opt, gplmm_ctx** out) {
+    if (!mask || !labels || !opt || !out || !body) return GPLMM_E_ARG;
+    *out = nullptr;
+    gplmm_ctx* c = new gplmm_ctx();
+    c->opt = *opt;
+    *out = c;
+    int rc = check_options(c, opt, rho, mu);
+    if (rc != GPLMM_OK) return rc;
+    set_dims(c, opt->nx, opt->ny, opt->nz);
+    c->phys = Phys{rho, mu, {body[0], body[1], c->ndim == 3 ? body[2] : 0.0}, dt > 0 ? dt : 0.0};
+    c->stream = (hipStream_t)opt->stream;
+    rc = build_decomposition(c, mask, labels);
+    c->samples.assign(1, SampleGeo{0, 0, c->nx, c->ny, c->nz, 0, 0});
+    if (rc == GPLMM_OK) rc = finish_setup(c);
+    return rc;
+}
+
+int gplmm_setup_batch(int nsamples, const uint8_t* const* masks, const int32_t* const* labels, const int32_t* dims,
+                      const double* rho, const double* mu, const double* body, const double* dt,
+                      const gplmm_options* opt, gplmm_ctx** out) {
+    if (!out) return GPLMM_E_ARG;
+    *out = nullptr;
+    if (nsamples < 1 || !masks || !labels || !dims || !rho || !mu || !body || !opt) return GPLMM_E_ARG;
+    gplmm_ctx* c = new gplmm_ctx();
+    c->opt = *opt;
+    *out = c;
+    c->stream = (hipStream_t)opt->stream;
+    if (nsamples > kMaxSamples) return fail(c, GPLMM_E_ARG, "at most 1024 samples per batch");
+    int rc0 = check_options(c, opt, rho[0], mu[0]);
+    if (rc0 != GPLMM_OK) return rc0;
+    const int nd = dims[2] == 1 ? 2 : 3;
+    std::vector<gplmm_ctx*> parts;
+    int rc = GPLMM_OK;
+    for (int s = 0; s < nsamples && rc == GPLMM_OK; ++s) {
+        gplmm_options o = *opt;
+        o.nx = dims[3 * s];
+        o.ny = dims[3 * s + 1];
+        o.nz = dims[3 * s + 2];
+        o.host_only = 1;
+        gplmm_ctx* p = new gplmm_ctx();
+        p->opt = o;
+        parts.push_back(p);
+        rc = check_options(p, &o, rho[s], mu[s]);
+        if (rc == GPLMM_OK && (o.nz == 1 ? 2 : 3) != nd) rc = fail(p, GPLMM_E_ARG, "samples of mixed dimension");
+        if (rc == GPLMM_OK && (!masks[s] || !labels[s])) rc = fail(p, GPLMM_E_ARG, "null image");
+        if (rc == GPLMM_OK) {
+            set_dims(p, o.nx, o.ny, o.nz);
+            rc = build_decomposition(p, masks[s], labels[s]);
+        }
+        if (rc != GPLMM_OK) c->err = "sample " + std::to_string(s) + ": " + p->err;
+        const double d = dt ? dt[s] : 0.0;
+        c->sphys.push_back(Phys{rho[s], mu[s], {body[3 * s], body[3 * s + 1], nd == 3 ? body[3 * s + 2] : 0.0},
+                                d > 0 ? d : 0.0});
+    }
+    if (rc == GPLMM_OK) {
+        c->opt.nx = parts[0]->nx;
+        c->opt.ny = parts[0]->ny;
+        c->opt.nz = parts[0]->nz;
+        set_dims(c, parts[0]->nx, parts[0]->ny, parts[0]->nz);
+        c->phys = c->sphys[0];
+        rc = merge_samples(c, parts);
+    }
+    for (gplmm_ctx* p : parts) delete p;
+    if (rc == GPLMM_OK && nsamples == 1) {   // one sample: the plain context
+        c->csamp.clear();
+        c->sphys.clear();
+    }
+    if (rc == GPLMM_OK) rc = finish_setup(c);
+    return rc;
+}
+
+int gplmm_batch_info(const gplmm_ctx* c, int* nsamples, int64_t* cell_off, int64_t* voxel_off, int32_t* prim_off,
+                     int32_t* iface_off) {
+    if (!c) return GPLMM_E_ARG;
+    const int ns = (int)c->samples.size();
+    if (nsamples) *nsamples = ns;
+    for (int s = 0; s <= ns; ++s) {
+        const bool end = s == ns;
+        if (cell_off) cell_off[s] = end ? c->ncell : c->samples[s].coff;
+        if (voxel_off) voxel_off[s] = end ? c->nvox : c->samples[s].voff;
+        if (prim_off) prim_off[s] = end ? c->Np : c->samples[s].p0;
+        if (iface_off) iface_off[s] = end ? c->Nc : c->samples[s].i0;
+    }
+    return GPLMM_OK;
 }
 
 int gplmm_layout_info(const gplmm_ctx* c, gplmm_layout* o) {
@@ -566,10 +680,9 @@ int gplmm_coarse_entries(gplmm_ctx* c, int64_t* nent, int32_t* rows, int32_t* co
     if (exact) {
         if (!c->built || c->last_coarse_learned)
             return gp::fail(c, GPLMM_E_STATE, "exact coarse values need a preceding build with the exact operator");
-        const int nco = c->nco;
-        std::vector<double> A((size_t)nco * nco);
+        std::vector<double> A((size_t)c->co_elems);
         GP_HIP(c, hipMemcpy(A.data(), c->d_Aoasm, sizeof(double) * A.size(), hipMemcpyDeviceToHost));
-        for (int64_t e = 0; e < ne; ++e) exact[e] = A[(size_t)c->cl_row[e] * nco + c->cl_col[e]];
+        for (int64_t e = 0; e < ne; ++e) exact[e] = A[coarse_pos(c, c->cl_row[e], c->cl_col[e])];
     }
     return GPLMM_OK;
 }
@@ -580,9 +693,17 @@ int gplmm_get_coarse(gplmm_ctx* c, double* ao, int* nco_out) {
     if (!ao) return GPLMM_OK;
     if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
     if (!c->built) return fail(c, GPLMM_E_STATE, "gplmm_build must precede gplmm_get_coarse");
-    GP_HIP(c, hipMemcpyAsync(ao, c->d_Aoasm, sizeof(double) * (int64_t)c->nco * c->nco, hipMemcpyDeviceToHost,
-                             c->stream));
+    std::vector<double> A((size_t)c->co_elems);
+    GP_HIP(c, hipMemcpyAsync(A.data(), c->d_Aoasm, sizeof(double) * A.size(), hipMemcpyDeviceToHost, c->stream));
     GP_HIP(c, hipStreamSynchronize(c->stream));
+    const int64_t nco = c->nco;
+    std::fill(ao, ao + nco * nco, 0.0);
+    for (size_t b = 0; b < c->cblk_n.size(); ++b) {
+        const int n = c->cblk_n[b];
+        const int32_t* idx = c->cblk_idx.data() + c->cblk_ioff[b];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) ao[idx[i] * nco + idx[j]] = A[c->cblk_moff[b] + (int64_t)i * n + j];
+    }
     return GPLMM_OK;
 }
 
@@ -606,11 +727,38 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
     auto T0 = std::chrono::steady_clock::now();
     const int64_t N = c->N;
     const int64_t reorth0 = c->gs_reorth;
+    // A batch is one block-diagonal system.  Each sample's equations are scaled by
+    // 1 / ||r_s(0)||, so that one FGMRES on the whole batch with the absolute tolerance
+    // lin_tol meets lin_tol * ||r_s(0)|| on every sample, and Newton stops when the
+    // largest relative residual max_s ||r_s|| / ||r_s(0)|| reaches newton_tol.
+    const bool batch = !c->csamp.empty();
+    const int ns = (int)c->samples.size();
+    std::vector<double> r0s(ns, 0.0), rns(ns, 0.0), rts(ns, 0.0);
+    double* d_r2 = nullptr;
+    auto rel_max = [&](const std::vector<double>& v) {
+        double m = 0.0;
+        for (int s = 0; s < ns; ++s) m = std::max(m, v[s] / r0s[s]);
+        return m;
+    };
     // ||r(0)||: the residual at the origin (previous time level also zero)
     launch_residual(c, c->d_zero, c->d_zero, c->d_r, c->stream);
     const double r0 = nrm2(c, c->d_r, N);
     S->r0_norm = r0;
     if (!(r0 > 0)) return fail(c, GPLMM_E_ARG, "the residual at the origin is zero (no driving force)");
+    if (batch) {
+        seg_sumsq(c, c->d_r, r0s.data());
+        std::vector<double> sc(2 * ns);
+        for (int s = 0; s < ns; ++s) {
+            r0s[s] = std::sqrt(r0s[s]);
+            if (!(r0s[s] > 0))
+                return fail(c, GPLMM_E_ARG, "sample " + std::to_string(s) + " has no driving force");
+            sc[s] = -1.0 / r0s[s];   // b = -D r
+            sc[ns + s] = r0s[s];     // d = D^-1 y
+        }
+        GP_HIP(c, hipMemcpy(c->d_sscale, sc.data(), sizeof(double) * 2 * ns, hipMemcpyHostToDevice));
+        d_r2 = (double*)c->d_V;   // trial residuals of the line search (the Krylov basis is free then)
+    }
+    const double lin_abs = batch ? c->opt.lin_tol : c->opt.lin_tol * r0;
     const int mode = c->opt.wind_mode;
     if (mode != GPLMM_WIND_CALLER || !c->built) {
         if (mode != GPLMM_WIND_CALLER) hipMemsetAsync(c->d_wind, 0, sizeof(double) * N, c->stream);
@@ -623,10 +771,16 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
     }
     launch_residual(c, x, xprev, c->d_r, c->stream);
     double rn = nrm2(c, c->d_r, N);
-    S->res_hist[0] = rn / r0;
+    double rel = rn / r0;
+    if (batch) {
+        seg_sumsq(c, c->d_r, rns.data());
+        for (auto& v : rns) v = std::sqrt(v);
+        rel = rel_max(rns);
+    }
+    S->res_hist[0] = rel;
     int rcode = 1;
     for (int k = 0; k < c->opt.newton_maxit && k < 64; ++k) {
-        if (rn <= c->opt.newton_tol * r0) {
+        if (rel <= c->opt.newton_tol) {
             rcode = 0;
             break;
         }
@@ -639,10 +793,11 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
             S->learned_builds += c->last_coarse_learned ? 1 : 0;
             if (rc) return rc;
         }
-        scal_copy(c, -1.0, c->d_r, c->d_r, N);   // b = -r (fgmres leaves d_r alone)
+        if (batch) seg_scale(c, c->d_sscale, c->d_r);      // b = -D r
+        else scal_copy(c, -1.0, c->d_r, c->d_r, N);       // b = -r (fgmres leaves d_r alone)
         auto t1 = std::chrono::steady_clock::now();
         bool ok = false;
-        int its = fgmres(c, x, c->d_r, c->d_dx, c->opt.lin_tol * r0, c->opt.lin_maxit, &ok);
+        int its = fgmres(c, x, c->d_r, c->d_dx, lin_abs, c->opt.lin_maxit, &ok);
         if (its < 0) return GPLMM_E_HIP;
         if (!ok && c->last_coarse_learned) {
             // the learned coarse operator did not carry FGMRES to the tolerance: rebuild with
@@ -656,13 +811,47 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
             S->t_coarse_ms += c->last_coarse_ms;
             S->coarse_fallbacks++;
             if (rc) return rc;
-            its += fgmres(c, x, c->d_r, c->d_dx, c->opt.lin_tol * r0, c->opt.lin_maxit, &ok);
+            its += fgmres(c, x, c->d_r, c->d_dx, lin_abs, c->opt.lin_maxit, &ok);
         }
+        if (batch) seg_scale(c, c->d_sscale + ns, c->d_dx);   // d = D^-1 y
         S->t_solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
         S->lin_its[k] = its;
         S->lin_its_total += its;
         S->newton_its = k + 1;
-        if (c->opt.line_search) {
+        if (batch && c->opt.line_search) {
+            // backtracking per sample: each sample keeps the first trial step that meets its
+            // own sufficient-decrease test (the samples are independent)
+            std::vector<char> acc(ns, 0);
+            int nacc = 0;
+            double lam = 1.0, lam_min = 1.0;
+            for (;;) {
+                GP_HIP(c, hipMemcpyAsync(c->d_tmp, x, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+                axpy(c, lam, c->d_dx, c->d_tmp, N);
+                launch_residual(c, c->d_tmp, xprev, d_r2, c->stream);
+                seg_sumsq(c, d_r2, rts.data());
+                const bool last = lam <= 1.0 / 64.0;
+                for (int s = 0; s < ns; ++s) {
+                    if (acc[s]) continue;
+                    const double rt = std::sqrt(rts[s]);
+                    if (rt <= (1.0 - 1e-4 * lam) * rns[s] || last) {
+                        acc[s] = 1;
+                        ++nacc;
+                        rns[s] = rt;
+                        lam_min = std::min(lam_min, lam);
+                        const int64_t a = (int64_t)c->nrec * c->samples[s].coff;
+                        const int64_t b = s + 1 < ns ? (int64_t)c->nrec * c->samples[s + 1].coff : N;
+                        GP_HIP(c, hipMemcpyAsync(x + a, c->d_tmp + a, sizeof(double) * (b - a),
+                                                 hipMemcpyDeviceToDevice, c->stream));
+                        GP_HIP(c, hipMemcpyAsync(c->d_r + a, d_r2 + a, sizeof(double) * (b - a),
+                                                 hipMemcpyDeviceToDevice, c->stream));
+                    }
+                }
+                if (nacc == ns) break;
+                lam *= 0.5;
+            }
+            rel = rel_max(rns);
+            S->step_length[k] = lam_min;
+        } else if (c->opt.line_search) {
             // backtracking on ||r||, trial points in d_tmp; d_r ends holding r(x_new)
             double lam = 1.0;
             for (;;) {
@@ -677,22 +866,48 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
                 }
                 lam *= 0.5;
             }
+            rel = rn / r0;
             S->step_length[k] = lam;
         } else {
             axpy(c, 1.0, c->d_dx, x, N);
             launch_residual(c, x, xprev, c->d_r, c->stream);
             rn = nrm2(c, c->d_r, N);
+            rel = rn / r0;
+            if (batch) {
+                seg_sumsq(c, c->d_r, rns.data());
+                for (auto& v : rns) v = std::sqrt(v);
+                rel = rel_max(rns);
+            }
             S->step_length[k] = 1.0;
         }
-        S->res_hist[k + 1] = rn / r0;
+        S->res_hist[k + 1] = rel;
     }
-    if (rn <= c->opt.newton_tol * r0) rcode = 0;
+    if (rel <= c->opt.newton_tol) rcode = 0;
     S->converged = rcode == 0;
     S->gs_reorth = (int)(c->gs_reorth - reorth0);
     GP_HIP(c, hipStreamSynchronize(c->stream));
     GP_HIP(c, hipGetLastError());
     S->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
     return rcode;
+}
+
+int gplmm_sample_residuals(gplmm_ctx* c, const double* x, const double* xprev, double* out) {
+    if (!c || !x || !out) return GPLMM_E_ARG;
+    if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    const int ns = (int)c->samples.size();
+    std::vector<double> a(ns), b(ns);
+    auto norms = [&](std::vector<double>& v) {
+        if (c->csamp.empty()) v[0] = dot(c, c->d_tmp, c->d_tmp, c->N);
+        else seg_sumsq(c, c->d_tmp, v.data());
+        for (auto& t : v) t = std::sqrt(std::max(0.0, t));
+    };
+    launch_residual(c, c->d_zero, c->d_zero, c->d_tmp, c->stream);
+    norms(a);
+    launch_residual(c, x, xprev, c->d_tmp, c->stream);
+    norms(b);
+    GP_HIP(c, hipGetLastError());
+    for (int s = 0; s < ns; ++s) out[s] = a[s] > 0 ? b[s] / a[s] : b[s];
+    return GPLMM_OK;
 }
 
 int gplmm_set_timing(gplmm_ctx* c, int on) {
@@ -746,7 +961,9 @@ void gplmm_destroy(gplmm_ctx* c) {
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_r, c->d_tmp,
                     c->d_dx, c->d_zero, c->d_V, c->d_Z, c->d_red, c->d_pv, c->d_local, c->d_cv, c->d_row_sub,
                     c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids,
-                    c->d_noclose, c->d_Aoasm, c->d_sub_order[0], c->d_sub_order[1]};
+                    c->d_noclose, c->d_Aoasm, c->d_sub_order[0], c->d_sub_order[1], c->d_co_blk, c->d_co_loc,
+                    c->d_cblk_n, c->d_cblk_idx, c->d_cblk_ioff, c->d_cblk_moff, c->d_csamp, c->d_sphys, c->d_seg,
+                    c->d_sscale};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_red) hipHostFree(c->h_red);

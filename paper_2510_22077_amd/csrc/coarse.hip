@@ -230,14 +230,10 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-int coarse_invert(gplmm_ctx* c) {
-    const int n = c->nco;
+// Invert one dense block in place: A (n x n, row-major) is overwritten by its LU factors and
+// X receives the inverse.
+static void invert_block(gplmm_ctx* c, double* A, double* X, int n) {
     hipStream_t s = c->stream;
-    double* A = c->d_Aowork;
-    double* X = c->d_Ao;
-    GP_HIP(c, hipMemcpyAsync(A, c->d_Ao, sizeof(double) * (int64_t)n * n, hipMemcpyDeviceToDevice, s));
-    GP_HIP(c, hipMemcpyAsync(c->d_Aoasm, c->d_Ao, sizeof(double) * (int64_t)n * n, hipMemcpyDeviceToDevice, s));
-    GP_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
     // LU with partial pivoting, panel by panel
     for (int k0 = 0; k0 < n; k0 += kNB) {
         const int w = std::min(kNB, n - k0);
@@ -267,6 +263,20 @@ int coarse_invert(gplmm_ctx* c) {
         if (k0 > 0)
             rank_update_kernel<<<dim3(blocks(n, kGT), blocks(k0, kGT)), 256, 0, s>>>(A, n, k0, X, n, k0, X, 0, k0,
                                                                                     0, n, w);
+    }
+}
+
+// The coarse operator is block diagonal (one block per sample of a batch, one block for a
+// single image): each block is factorised and inverted on its own.
+int coarse_invert(gplmm_ctx* c) {
+    hipStream_t s = c->stream;
+    const int64_t ne = c->co_elems;
+    GP_HIP(c, hipMemcpyAsync(c->d_Aowork, c->d_Ao, sizeof(double) * ne, hipMemcpyDeviceToDevice, s));
+    GP_HIP(c, hipMemcpyAsync(c->d_Aoasm, c->d_Ao, sizeof(double) * ne, hipMemcpyDeviceToDevice, s));
+    GP_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+    for (size_t b = 0; b < c->cblk_n.size(); ++b) {
+        const int n = c->cblk_n[b];
+        if (n > 0) invert_block(c, c->d_Aowork + c->cblk_moff[b], c->d_Ao + c->cblk_moff[b], n);
     }
     int flag = 0;
     GP_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));

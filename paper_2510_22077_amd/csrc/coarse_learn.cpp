@@ -92,7 +92,8 @@ int coarse_features(gplmm_ctx* c, const double* wind_host, std::vector<float>& f
             }
             s += std::sqrt(w2);
         }
-        re[g] = c->phys.rho * (s / (double)o.cells.size()) * o.len * c->opt.h / c->phys.mu;
+        const Phys& ph = c->csamp.empty() ? c->phys : c->sphys[c->csamp[o.cells[0]]];
+        re[g] = ph.rho * (s / (double)o.cells.size()) * o.len * c->opt.h / ph.mu;
     }
     // pores of each interface; interfaces of each pore (coarse ids)
     std::vector<std::vector<int32_t>> iface_pores(c->Nc);
@@ -143,7 +144,8 @@ int coarse_features(gplmm_ctx* c, const double* wind_host, std::vector<float>& f
         }
         f[12] = (float)rel;
         f[15] = 1.f;
-        scale[e] = (float)(c->phys.mu * std::sqrt(obj[r].len * obj[k].len));
+        const double mu = (c->csamp.empty() || obj[r].cells.empty()) ? c->phys.mu : c->sphys[c->csamp[obj[r].cells[0]]].mu;
+        scale[e] = (float)(mu * std::sqrt(obj[r].len * obj[k].len));
     }
     return GPLMM_OK;
 }

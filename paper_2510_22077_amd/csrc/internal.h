@@ -14,20 +14,38 @@
 namespace gp {
 
 constexpr int kMaxRestart = 1024;
+constexpr int kMaxSamples = 1024;   // samples of one batch
+
+struct Phys {
+    double rho, mu, body[3], dt;   // dt <= 0: steady
+};
+
+constexpr uint8_t kPinBit = 0x80;   // tag bit of a pinned cell (one per sample)
 
 // Geometry as the device kernels see it.
 struct DevGeo {
     int nx, ny, nz, ndim, nrec;
     int per[3];
     int64_t ncell;
-    int pin;                 // pinned cell
+    int pin;                 // pinned cell of the first sample (the kernels test kPinBit)
     double h;
     const int32_t* nb6;      // cell * 6 + 2 d + t -> cell -/+ e_d (periodic wrap) or -1
-    const uint8_t* tag;      // cell -> bit a: lower a-face carries no inertia in X
+    const uint8_t* tag;      // cell -> bit a: lower a-face carries no inertia in X; kPinBit: pinned
+    const int32_t* csamp;    // cell -> sample of a batch, or nullptr for one sample
+    const Phys* sphys;       // per-sample physics of a batch (indexed by csamp)
 };
 
-struct Phys {
-    double rho, mu, body[3], dt;   // dt <= 0: steady
+// Physics of a cell: its sample's in a batch, else the context's.
+__host__ __device__ __forceinline__ const Phys& cell_phys(const DevGeo& g, const Phys& ph, int64_t c) {
+    return g.csamp ? g.sphys[g.csamp[c]] : ph;
+}
+
+// One sample of a batch: its voxels, cells, primaries and interfaces are contiguous
+// ranges starting at these offsets; the image dimensions place its voxels.
+struct SampleGeo {
+    int64_t voff, coff;
+    int nx, ny, nz;
+    int p0, i0;              // first primary, first interface
 };
 
 // One local problem (primary closure / primary block / dual block).
@@ -73,6 +91,9 @@ struct gplmm_ctx {
     std::vector<uint8_t> tagcell;     // per cell bits
     int Np = 0, Nc = 0, Ny = 0;
     int64_t pin = 0;
+    std::vector<gp::SampleGeo> samples; // one entry for a single image
+    std::vector<gp::Phys> sphys;      // per-sample physics (batch)
+    std::vector<int32_t> csamp;       // cell -> sample (batch only)
     std::vector<std::vector<int32_t>> Cp;          // interfaces of each primary
     std::vector<std::vector<int32_t>> icells;      // cells of each interface
     std::vector<std::vector<int32_t>> dual_cells;  // cells of each dual grid
@@ -106,6 +127,12 @@ struct gplmm_ctx {
     std::vector<int64_t> color_col_off;
     std::vector<int32_t> color_cols;
     int nco = 0;                      // coarse size Nc + Ny
+    // block-diagonal coarse storage: one dense block per sample, over the coarse indices
+    // cblk_idx[cblk_ioff[b] .. cblk_ioff[b+1]) (row-major n_b x n_b at cblk_moff[b])
+    std::vector<int32_t> cblk_n, cblk_idx, co_blk, co_loc;
+    std::vector<int64_t> cblk_ioff, cblk_moff;
+    int64_t co_elems = 0;             // sum of n_b^2
+    int cblk_max = 0;
 
     // ---- device buffers
     gp::DevGeo geo{};
@@ -143,7 +170,17 @@ struct gplmm_ctx {
     int32_t* d_grp_slot = nullptr;
     int64_t* d_dinv_ptr = nullptr;       // per slot: local rows of the dual grids holding it
     int64_t* d_dinv = nullptr;
-    double* d_Ao = nullptr;              // coarse operator, then its inverse (nco x nco, row-major)
+    int32_t* d_co_blk = nullptr;         // per coarse index: block, local index within it
+    int32_t* d_co_loc = nullptr;
+    int32_t* d_cblk_n = nullptr;
+    int32_t* d_cblk_idx = nullptr;
+    int64_t* d_cblk_ioff = nullptr;
+    int64_t* d_cblk_moff = nullptr;
+    int32_t* d_csamp = nullptr;          // batch: cell -> sample
+    gp::Phys* d_sphys = nullptr;         // batch: per-sample physics
+    int64_t* d_seg = nullptr;            // batch: slot offset of each sample (nsamples + 1)
+    double* d_sscale = nullptr;          // batch: per-sample scale factors
+    double* d_Ao = nullptr;              // coarse operator blocks, then their inverses
     double* d_Aowork = nullptr;
     double* d_Aoasm = nullptr;           // the assembled coarse operator (kept for inspection)
     int32_t* d_piv = nullptr;
@@ -213,6 +250,8 @@ int fail(gplmm_ctx* c, int code, const std::string& msg);
 int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels);
 int build_local_problems(gplmm_ctx* c);
 int build_probing(gplmm_ctx* c);
+void build_coarse_blocks(gplmm_ctx* c);
+int merge_samples(gplmm_ctx* c, std::vector<gplmm_ctx*>& parts);
 
 // stencil.hip
 void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s);
@@ -229,6 +268,8 @@ void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s);
 // krylov.hip
 double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n);
 double nrm2(gplmm_ctx* c, const double* a, int64_t n);
+void seg_sumsq(gplmm_ctx* c, const double* a, double* out_host);   // per-sample sums of squares
+void seg_scale(gplmm_ctx* c, const double* scale_dev, double* a);   // a *= scale[sample] (in place)
 void axpy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n);
 void scal_copy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n);
 template <typename A, typename B>

@@ -132,6 +132,31 @@ __global__ void convert_kernel(const A* __restrict__ x, B* __restrict__ y, int64
     if (i < n) y[i] = (B)x[i];
 }
 
+// Per-sample partial sums of squares: block (ch, s) strides over sample s's slots
+// [seg[s], seg[s+1]); partial[s * gridDim.x + ch].
+__global__ void __launch_bounds__(kThreads) seg_sumsq_kernel(const double* __restrict__ a,
+                                                             const int64_t* __restrict__ seg,
+                                                             double* __restrict__ partial) {
+    __shared__ double sh[16];
+    const int s = blockIdx.y;
+    const int64_t e = seg[s + 1];
+    double acc = 0.0;
+    for (int64_t r = seg[s] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < e;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const double v = a[r];
+        acc += v * v;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[(int64_t)s * gridDim.x + blockIdx.x] = t;
+}
+
+// a[r] *= scale[sample of r's cell]
+__global__ void seg_scale_kernel(const int32_t* __restrict__ csamp, int nrec, const double* __restrict__ scale,
+                                 double* __restrict__ a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] *= scale[csamp[i / nrec]];
+}
+
 inline unsigned nb_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -149,6 +174,20 @@ double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n) {
 }
 
 double nrm2(gplmm_ctx* c, const double* a, int64_t n) { return std::sqrt(std::max(0.0, dot(c, a, a, n))); }
+
+void seg_sumsq(gplmm_ctx* c, const double* a, double* out_host) {
+    constexpr int kChunks = 64;
+    const int ns = (int)c->samples.size();
+    seg_sumsq_kernel<<<dim3(kChunks, ns), kThreads, 0, c->stream>>>(a, c->d_seg, partials(c));
+    reduce_kernel<<<ns, kThreads, 0, c->stream>>>(partials(c), kChunks, results(c));
+    hipMemcpyAsync(c->h_red, results(c), sizeof(double) * ns, hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    for (int s = 0; s < ns; ++s) out_host[s] = c->h_red[s];
+}
+
+void seg_scale(gplmm_ctx* c, const double* scale_dev, double* a) {
+    seg_scale_kernel<<<nb_for(c->N), kThreads, 0, c->stream>>>(c->d_csamp, c->nrec, scale_dev, a, c->N);
+}
 
 void axpy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n) {
     axpy_kernel<<<nb_for(n), kThreads, 0, c->stream>>>(alpha, x, y, n);

@@ -102,7 +102,7 @@ __global__ void assemble_kernel(DevGeo g, const double* __restrict__ coef, Env e
             emit(nr * c + ND, ih);
             emit((int64_t)nr * L + ND, -ih);
         }
-    } else if (c == g.pin) {
+    } else if ((g.tag[c] & kPinBit)) {
         emit(gs, 1.0);
     } else {
 #pragma unroll

@@ -83,13 +83,29 @@ __global__ void prolong_iface_kernel(const int64_t* __restrict__ gptr, const int
     for (int64_t t = gptr[j] + threadIdx.x; t < gptr[j + 1]; t += blockDim.x) z[gslot[t]] = (O)coef[j];
 }
 
+// Block-diagonal coarse storage: one dense row-major block per sample over the coarse
+// indices idx[ioff[b] .. ioff[b+1]); blk/loc give each coarse index's block and position.
+struct CoBlk {
+    const int32_t* blk;
+    const int32_t* loc;
+    const int32_t* n;
+    const int32_t* idx;
+    const int64_t* ioff;
+    const int64_t* moff;
+};
+
+__device__ __forceinline__ int64_t co_pos(const CoBlk& cb, int row, int col) {
+    const int b = cb.blk[row];
+    return cb.moff[b] + (int64_t)cb.loc[row] * cb.n[b] + cb.loc[col];
+}
+
 // Ao[row, col] = t[row] for the colour's (row, col) entries.
 __global__ void probe_scatter_kernel(const ProbeEntry* __restrict__ ent, int64_t n, const double* __restrict__ t,
-                                     double* __restrict__ Ao, int nco) {
+                                     double* __restrict__ Ao, CoBlk cb) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     ProbeEntry p = ent[k];
-    Ao[(int64_t)p.row * nco + p.col] = t[p.row];
+    Ao[co_pos(cb, p.row, p.col)] = t[p.row];
 }
 
 __global__ void set_ones_kernel(const int32_t* __restrict__ cols, int64_t n, double* __restrict__ e, double val) {
@@ -127,14 +143,17 @@ __global__ void combine_kernel(const T* __restrict__ a, const T* __restrict__ b,
     if (s < N) z[s] = (double)a[s] + (double)b[s] + (double)c[s];
 }
 
-// y = A x for the dense coarse inverse (row-major), one block per row
-__global__ void gemv_kernel(const double* __restrict__ A, const double* __restrict__ x, double* __restrict__ y,
-                            int n) {
+// y = A x for the block-diagonal coarse inverse, one workgroup per coarse row: the row
+// of its sample's block against x gathered over the block's coarse indices.
+__global__ void gemv_kernel(const double* __restrict__ A, CoBlk cb, const double* __restrict__ x,
+                            double* __restrict__ y) {
     __shared__ double sh[16];
     const int i = blockIdx.x;
-    const double* a = A + (int64_t)i * n;
+    const int b = cb.blk[i], n = cb.n[b];
+    const double* a = A + cb.moff[b] + (int64_t)cb.loc[i] * n;
+    const int32_t* idx = cb.idx + cb.ioff[b];
     double acc = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) acc += a[j] * x[j];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) acc += a[j] * x[idx[j]];
     double s = block_sum(acc, sh);
     if (threadIdx.x == 0) y[i] = s;
 }
@@ -142,12 +161,12 @@ __global__ void gemv_kernel(const double* __restrict__ A, const double* __restri
 // Ao[row, col] = sinh(prediction) * scale for the learned coarse entries
 __global__ void learned_scatter_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ col,
                                        const float* __restrict__ pred, const float* __restrict__ scale, int64_t n,
-                                       double* __restrict__ Ao, int nco) {
+                                       double* __restrict__ Ao, CoBlk cb) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     // predictions are clipped to asinh(+-4000): no entry of the normalised operator is larger
     const double z = fmin(fmax((double)pred[k], -9.0), 9.0);
-    Ao[(int64_t)row[k] * nco + col[k]] = sinh(z) * (double)scale[k];
+    Ao[co_pos(cb, row[k], col[k])] = sinh(z) * (double)scale[k];
 }
 
 template <typename T>
@@ -174,6 +193,10 @@ template <typename T>
 int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure);
 template <typename T>
 int factor_set(gplmm_ctx* c, int set);
+
+static CoBlk coblk(const gplmm_ctx* c) {
+    return CoBlk{c->d_co_blk, c->d_co_loc, c->d_cblk_n, c->d_cblk_idx, c->d_cblk_ioff, c->d_cblk_moff};
+}
 
 template <typename T>
 static T* pvec(gplmm_ctx* c, int k) {
@@ -224,7 +247,7 @@ static int learned_coarse(gplmm_ctx* c) {
     if (rc != GPLMM_OK) return fail(c, rc, "coarse model inference failed");
     GP_HIP(c, hipDeviceSynchronize());
     learned_scatter_kernel<<<nb(ne), kB, 0, s>>>(c->d_cl_row, c->d_cl_col, c->d_cl_pred, c->d_cl_scale, ne, c->d_Ao,
-                                                 c->nco);
+                                                 coblk(c));
     GP_HIP(c, hipGetLastError());
     GP_HIP(c, hipStreamSynchronize(s));
     return GPLMM_OK;
@@ -257,7 +280,7 @@ int build_precond(gplmm_ctx* c) {
     c->last_coarse_learned = false;
     auto tc0 = std::chrono::steady_clock::now();
     if (nco > 0 && c->coarse_model) {
-        GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * (int64_t)nco * nco, s));
+        GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * c->co_elems, s));
         int rc = learned_coarse(c);
         if (rc == GPLMM_OK) {
             c->last_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
@@ -275,7 +298,7 @@ int build_precond(gplmm_ctx* c) {
         tc0 = std::chrono::steady_clock::now();
     }
     if (nco > 0) {
-        GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * (int64_t)nco * nco, s));
+        GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * c->co_elems, s));
         double* e = c->d_cv;
         double* tco = c->d_cv + nco;
         double* pv = c->d_r;     // FP64 scratch vectors
@@ -288,7 +311,7 @@ int build_precond(gplmm_ctx* c) {
             launch_xv<double>(c, pv, xv, nullptr, s);
             restrict_<double>(c, xv, tco);
             int64_t p0 = c->color_off[k], p1 = c->color_off[k + 1];
-            probe_scatter_kernel<<<nb(p1 - p0), kB, 0, s>>>(c->d_probe + p0, p1 - p0, tco, c->d_Ao, nco);
+            probe_scatter_kernel<<<nb(p1 - p0), kB, 0, s>>>(c->d_probe + p0, p1 - p0, tco, c->d_Ao, coblk(c));
         }
         GP_HIP(c, hipStreamSynchronize(s));
         c->last_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
@@ -315,7 +338,7 @@ int apply_precond(gplmm_ctx* c, const double* v, double* z) {
     // coarse correction z_G = Phat Ao^-1 Rhat v
     if (c->nco > 0) {
         restrict_<double>(c, v, c->d_cv);
-        gemv_kernel<<<c->nco, kB, 0, s>>>(c->d_Ao, c->d_cv, c->d_cv + c->nco, c->nco);
+        gemv_kernel<<<c->nco, kB, 0, s>>>(c->d_Ao, coblk(c), c->d_cv, c->d_cv + c->nco);
         prolong<T, T>(c, c->d_cv + c->nco, zG);
     } else {
         zero_fill<T>(c, zG, N);

@@ -305,6 +305,7 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
                     c->tagcell[q] |= (uint8_t)(1u << a);
                 }
             }
+        c->tagcell[c->pin] |= kPinBit;
     }
     // ---- dual grids: each interface grown dual_dilations times through face neighbours
     int dd = c->opt.dual_dilations >= 0 ? c->opt.dual_dilations : (nd == 2 ? 1 : 0);
@@ -362,11 +363,15 @@ std::vector<int64_t> unknowns_of(const gplmm_ctx* c, const std::vector<int32_t>&
 std::vector<int64_t> local_keys(const gplmm_ctx* c, const std::vector<int32_t>& cells, const std::vector<int64_t>& u) {
     const int nd = c->ndim;
     const int n = (int)cells.size();
-    const int dims[3] = {c->nx, c->ny, c->nz};
+    // the sample holding the set (a subdomain never spans two samples of a batch)
+    size_t si = 0;
+    while (si + 1 < c->samples.size() && c->samples[si + 1].coff <= (int64_t)cells[0]) ++si;
+    const SampleGeo& sg = c->samples[si];
+    const int dims[3] = {sg.nx, sg.ny, sg.nz};
     std::vector<std::array<int, 3>> co(n);
     for (int t = 0; t < n; ++t) {
-        int64_t v = c->cell_voxel[cells[t]];
-        co[t] = {(int)(v % c->nx), (int)((v / c->nx) % c->ny), (int)(v / ((int64_t)c->nx * c->ny))};
+        int64_t v = c->cell_voxel[cells[t]] - sg.voff;
+        co[t] = {(int)(v % sg.nx), (int)((v / sg.nx) % sg.ny), (int)(v / ((int64_t)sg.nx * sg.ny))};
     }
     for (int a = 0; a < 3; ++a) {
         if (!c->opt.periodic[a] || dims[a] < 2) continue;
@@ -448,7 +453,7 @@ void row_pattern(const gplmm_ctx* c, int64_t s, std::vector<int64_t>& cols) {
             }
         cols.push_back(slot(c, q, nd));
         cols.push_back(slot(c, l0, nd));
-    } else if (q != c->pin) {
+    } else if (!(c->tagcell[q] & kPinBit)) {
         for (int a = 0; a < nd; ++a) {
             if (NB(q, a, 0) >= 0) cols.push_back(slot(c, q, a));
             int64_t up = NB(q, a, 1);
@@ -588,7 +593,8 @@ int build_local_problems(gplmm_ctx* c) {
         for (int t = 0; t < c->subs[i].n && !nonzero; ++t) {
             int64_t s = c->sub_slots[c->subs[i].slot_off + t];
             int comp = (int)(s % c->nrec);
-            if (comp < c->ndim && c->phys.body[comp] != 0.0) nonzero = true;
+            const Phys& ph = c->csamp.empty() ? c->phys : c->sphys[c->csamp[s / c->nrec]];
+            if (comp < c->ndim && ph.body[comp] != 0.0) nonzero = true;
         }
         if (nonzero) c->ycol[i] = c->Nc + ny++;
         c->phi_cols.push_back(c->ycol[i]);
@@ -690,6 +696,107 @@ int build_probing(gplmm_ctx* c) {
         c->color_col_off[k + 1] = (int64_t)c->color_cols.size();
     }
     return GPLMM_OK;
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Batches: the decompositions of independent samples placed side by side
+// ------------------------------------------------------------------------------------------
+
+// Concatenate the decompositions of the parts (each built alone from its own image): cells,
+// primaries, interfaces and slots of sample s follow those of samples 0..s-1, every index
+// shifted by the offsets of its kind.  No cell of one sample neighbours a cell of another, so
+// the stencils, subdomains and coarse couplings of the batch are those of the samples.
+int merge_samples(gplmm_ctx* c, std::vector<gplmm_ctx*>& parts) {
+    c->samples.clear();
+    c->cidx.clear();
+    c->cell_voxel.clear();
+    c->nbr.clear();
+    c->iface.clear();
+    c->prim.clear();
+    c->owner.clear();
+    c->tagslot.clear();
+    c->noclose.clear();
+    c->tagcell.clear();
+    c->Cp.clear();
+    c->icells.clear();
+    c->dual_cells.clear();
+    c->csamp.clear();
+    c->Np = c->Nc = 0;
+    c->nface = 0;
+    int64_t voff = 0, coff = 0;
+    for (size_t si = 0; si < parts.size(); ++si) {
+        const gplmm_ctx* p = parts[si];
+        if (p->ndim != c->ndim) return fail(c, GPLMM_E_ARG, "all samples of a batch must have the same dimension");
+        c->samples.push_back(SampleGeo{voff, coff, p->nx, p->ny, p->nz, c->Np, c->Nc});
+        for (int32_t q : p->cidx) c->cidx.push_back(q >= 0 ? (int32_t)(q + coff) : -1);
+        for (int32_t v : p->cell_voxel) c->cell_voxel.push_back((int32_t)(v + voff));
+        for (int32_t q : p->nbr) c->nbr.push_back(q >= 0 ? (int32_t)(q + coff) : -1);
+        for (int32_t j : p->iface) c->iface.push_back(j >= 0 ? j + c->Nc : -1);
+        for (int32_t i : p->prim) c->prim.push_back(i >= 0 ? i + c->Np : -1);
+        for (int32_t o : p->owner) c->owner.push_back(o >= 0 ? o + c->Np : o);
+        c->tagslot.insert(c->tagslot.end(), p->tagslot.begin(), p->tagslot.end());
+        c->noclose.insert(c->noclose.end(), p->noclose.begin(), p->noclose.end());
+        c->tagcell.insert(c->tagcell.end(), p->tagcell.begin(), p->tagcell.end());
+        for (const auto& v : p->Cp) {
+            std::vector<int32_t> w(v);
+            for (auto& j : w) j += c->Nc;
+            c->Cp.push_back(w);
+        }
+        for (const auto& v : p->icells) {
+            std::vector<int32_t> w(v);
+            for (auto& q : w) q += (int32_t)coff;
+            c->icells.push_back(w);
+        }
+        for (const auto& v : p->dual_cells) {
+            std::vector<int32_t> w(v);
+            for (auto& q : w) q += (int32_t)coff;
+            c->dual_cells.push_back(w);
+        }
+        c->csamp.insert(c->csamp.end(), (size_t)p->ncell, (int32_t)si);
+        if (si == 0) c->pin = p->pin;
+        c->Np += p->Np;
+        c->Nc += p->Nc;
+        c->nface += p->nface;
+        voff += p->nvox;
+        coff += p->ncell;
+    }
+    if (coff > INT32_MAX / 8) return fail(c, GPLMM_E_ARG, "the batch has too many cells");
+    c->nvox = voff;
+    c->ncell = coff;
+    c->N = (int64_t)c->nrec * coff;
+    return GPLMM_OK;
+}
+
+// Coarse blocks: the interfaces and correction unknowns of one sample couple only among
+// themselves, so the coarse operator is block diagonal with one block per sample.
+void build_coarse_blocks(gplmm_ctx* c) {
+    c->cblk_n.clear();
+    c->cblk_idx.clear();
+    c->cblk_ioff.assign(1, 0);
+    c->cblk_moff.assign(1, 0);
+    c->co_blk.assign(c->nco, -1);
+    c->co_loc.assign(c->nco, -1);
+    const int ns = (int)c->samples.size();
+    for (int si = 0; si < ns; ++si) {
+        const int i0 = c->samples[si].i0, i1 = si + 1 < ns ? c->samples[si + 1].i0 : c->Nc;
+        const int p0 = c->samples[si].p0, p1 = si + 1 < ns ? c->samples[si + 1].p0 : c->Np;
+        const int b = (int)c->cblk_n.size();
+        int n = 0;
+        auto add = [&](int g) {
+            c->co_blk[g] = b;
+            c->co_loc[g] = n++;
+            c->cblk_idx.push_back(g);
+        };
+        for (int j = i0; j < i1; ++j) add(j);
+        for (int i = p0; i < p1; ++i)
+            if (c->ycol[i] >= 0) add(c->ycol[i]);
+        c->cblk_n.push_back(n);
+        c->cblk_ioff.push_back((int64_t)c->cblk_idx.size());
+        c->cblk_moff.push_back(c->cblk_moff.back() + (int64_t)n * n);
+    }
+    c->co_elems = c->cblk_moff.back();
+    c->cblk_max = c->cblk_n.empty() ? 0 : *std::max_element(c->cblk_n.begin(), c->cblk_n.end());
 }
 
 }  // namespace gp

@@ -12,7 +12,7 @@
 // grain (wall half a cell away); first-order upwind inertia
 // rho * sum_d a_d D_d u with a_x = u_F and transverse a_d the mean of the four
 // d-faces of the face's two cells; gradient (p_R - p_L)/h; mass row -div u;
-// the pinned cell's mass row is p = 0.
+// the pinned cell's mass row (one per sample of a batch) is p = 0.
 //
 // X is fixed between builds, so its momentum rows are tabulated once per build
 // (kNC coefficients per face, structure of arrays over cells); X v is then a
@@ -29,10 +29,11 @@ constexpr int kBlock = 512;   // largest block size the stencil kernels are comp
 
 // r(x): momentum and mass residual.
 template <int ND>
-__global__ void __launch_bounds__(kBlock) residual_kernel(DevGeo g, Phys ph, const double* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) residual_kernel(DevGeo g, Phys ph0, const double* __restrict__ x,
                                                           const double* __restrict__ xold, double* __restrict__ r) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
+    const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
     const Nb<ND> nc = load_nb<ND>(g, c);
     const double ih = 1.0 / g.h, vis = ph.mu * ih * ih;
@@ -63,7 +64,7 @@ __global__ void __launch_bounds__(kBlock) residual_kernel(DevGeo g, Phys ph, con
         r[nr * c + a] = out;
     }
     double m;
-    if (c == g.pin) {
+    if ((g.tag[c] & kPinBit)) {
         m = x[nr * c + ND];
     } else {
         m = 0.0;
@@ -79,10 +80,11 @@ __global__ void __launch_bounds__(kBlock) residual_kernel(DevGeo g, Phys ph, con
 
 // y = J(xk) v with the upwind branches frozen at xk.
 template <int ND>
-__global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph, const double* __restrict__ xk,
+__global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph0, const double* __restrict__ xk,
                                                     const double* __restrict__ v, double* __restrict__ y) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
+    const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
     const Nb<ND> nc = load_nb<ND>(g, c);
     const double ih = 1.0 / g.h, vis = ph.mu * ih * ih;
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph, const dou
         y[nr * c + a] = out;
     }
     double m;
-    if (c == g.pin) {
+    if ((g.tag[c] & kPinBit)) {
         m = v[nr * c + ND];
     } else {
         m = 0.0;
@@ -134,10 +136,11 @@ __global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph, const dou
 // Momentum rows of X = J~_w: coef[(k * ND + a) * ncell + c], k = 0 diagonal, k = 1 + 2 d + t
 // neighbour face (d, t); all zero for an inactive face.  FP64 and, if cf32 != nullptr, FP32.
 template <int ND>
-__global__ void __launch_bounds__(kBlock) xcoef_kernel(DevGeo g, Phys ph, const double* __restrict__ wind,
+__global__ void __launch_bounds__(kBlock) xcoef_kernel(DevGeo g, Phys ph0, const double* __restrict__ wind,
                                                        double* __restrict__ cf64, float* __restrict__ cf32) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
+    const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
     const Nb<ND> nc = load_nb<ND>(g, c);
     const int64_t nce = g.ncell;
@@ -191,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restric
         y[s] = a ? (T)(a[s] - acc) : acc;
     }
     T m;
-    if (c == g.pin) {
+    if ((g.tag[c] & kPinBit)) {
         m = pc;
     } else {
         m = 0;
@@ -207,9 +210,10 @@ __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restric
 
 // b_B = -r(u = 0, p = 0) of the steady equations: rho * body on every active face.
 template <int ND>
-__global__ void bB_kernel(DevGeo g, Phys ph, double* __restrict__ out) {
+__global__ void bB_kernel(DevGeo g, Phys ph0, double* __restrict__ out) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
+    const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
     const Nb<ND> nc = load_nb<ND>(g, c);
 #pragma unroll

@@ -12,7 +12,7 @@ in for them.
 """
 from .packing import disk_packing_rsa, boolean_packing, channel
 from .watershed import watershed_labels
-from .workloads import make_workload, WORKLOADS
+from .workloads import make_workload, make_batch, WORKLOADS
 
 __all__ = ["disk_packing_rsa", "boolean_packing", "channel",
-           "watershed_labels", "make_workload", "WORKLOADS"]
+           "watershed_labels", "make_workload", "make_batch", "WORKLOADS"]

@@ -92,3 +92,26 @@ def make_workload(name, seed=0, re=None, **over):
     bx = body_force_for_re(mask, re_t, rho, mu)
     return dict(mask=mask, labels=labels, rho=rho, mu=mu, body=(bx, 0.0, 0.0),
                 name=name, seed=seed, re_target=re_t)
+
+
+def make_batch(nsamples, seed=0, sizes=(48, 96), porosity=(0.3, 0.6), re=(0.1, 20.0), mean_r=8.0,
+               sigma=0.3, ndim=3, footprint=5, min_size=200, max_size=1500, block=8):
+    """A batch of independent samples of uneven size: per sample, each axis drawn
+    uniformly from sizes[0]..sizes[1] voxels, the porosity uniformly from ``porosity``
+    and the target Re log-uniformly from ``re``; overlapping lognormal grains (Boolean
+    model, the grain law of the 3D packings above), labelled by the same watershed.
+    Returns a list of workload dicts (as make_workload)."""
+    rng = np.random.default_rng(1000003 + seed)
+    out = []
+    for k in range(nsamples):
+        shp = tuple(int(v) for v in rng.integers(sizes[0], sizes[1] + 1, size=3))
+        if ndim == 2:
+            shp = (1,) + shp[1:]
+        phi = float(rng.uniform(*porosity))
+        re_t = float(np.exp(rng.uniform(np.log(re[0]), np.log(re[1]))))
+        mask = boolean_packing(shp, mean_r, sigma, phi, int(rng.integers(1 << 30)))
+        labels = watershed_labels(mask, footprint=footprint, min_size=min_size, max_size=max_size, block=block)
+        bx = body_force_for_re(mask, re_t)
+        out.append(dict(mask=mask, labels=labels, rho=1.0, mu=1.0, body=(bx, 0.0, 0.0),
+                        name="batch%d_%d" % (seed, k), seed=seed, re_target=re_t, porosity=phi))
+    return out
