@@ -136,6 +136,7 @@ int upload_all(gplmm_ctx* c) {
         std::vector<int32_t> ord;
         for (int sidx = s0; sidx < s1; ++sidx) ord.push_back(sidx);
         std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return c->subs[a].nT > c->subs[b].nT; });
+        c->maxT_set[set] = ord.empty() ? 0 : c->subs[ord[0]].nT;
         GP_TRY(upload(c, &c->d_sub_order[set], ord));
     }
     c->prim_factor_elems = c->Nc > 0 ? c->subs[c->Np].diag_off : c->factor_elems;

@@ -108,6 +108,7 @@ struct gplmm_ctx {
     std::vector<int64_t> env_lrow, env_urow; // element offsets of the L and U tile rows
     int64_t factor_elems = 0;
     int maxT = 0;
+    int maxT_set[2] = {0, 0};          // largest tile count among the primaries / the duals
     // LU schedule: per step K, (sub, I) pairs for the row-update kernel
     std::vector<int64_t> lu_step_off[2];     // [set][K], set 0 = primaries, 1 = primaries + duals
     std::vector<int32_t> lu_step_pairs[2];

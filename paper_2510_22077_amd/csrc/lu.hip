@@ -391,15 +391,15 @@ __device__ __forceinline__ void load_row(T (&buf)[kPF], const T* __restrict__ sr
         if (t < n) buf[t] = src[(int64_t)t * kTT];
 }
 
-// sum_{t < n} buf[t] y[t kT]: entries past the row read the (always valid) ysafe and
-// are dropped after the product, so nothing outside the row reaches the sum
+// sum_{t < n} buf[t] y[t kT]; n is the same for the whole workgroup, so the loop leaves
+// at the end of the row with a uniform branch (no LDS read or product past the row)
 template <typename T, int kPF>
-__device__ __forceinline__ T buf_dot(const T (&buf)[kPF], const T* y, int n, const T* ysafe) {
+__device__ __forceinline__ T buf_dot(const T (&buf)[kPF], const T* y, int n) {
     T acc = 0;
 #pragma unroll
     for (int t = 0; t < kPF; ++t) {
-        const T p = buf[t] * *(t < n ? y + t * kT : ysafe);
-        acc += t < n ? p : (T)0;
+        if (t >= n) break;
+        acc += buf[t] * y[t * kT];
     }
     return acc;
 }
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     auto fwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
         const int j0 = tfc[I], nt = I - j0;
         const T* y = x + j0 * kT + c;
-        T acc = buf_dot(buf, y, nb, x + c);
+        T acc = buf_dot(buf, y, nb);
         if (nt > kPF) acc += tail_dot<T>(F + lrow[I] + tid, y, kPF, nt);
         fetch_l(I + 2, buf, nb);
         acc = sum32(acc);
@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     auto bwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
         const int nt = tlc[I] - I;
         const T* y = x + (I + 1) * kT + c;
-        T acc = buf_dot(buf, y, nb, x + c);
+        T acc = buf_dot(buf, y, nb);
         if (nt > kPF) acc += tail_dot<T>(F + urow[I] + tid, y, kPF, nt);
         fetch_u(I - 2, buf, nb);
         acc = sum32(acc);
@@ -503,6 +503,181 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     }
     if (kLds)
         for (int i = tid; i < len; i += 1024) xo[i] = x[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// The same substitutions for small subdomains (the dual grids): one 256-thread block per
+// subdomain, so that many subdomains share a compute unit.  Thread (r, q) = (tid / 8,
+// tid % 8) owns the four elements (r, 4q .. 4q + 3) of every tile it touches (one 16- or
+// 32-byte load per tile), reads the four matching solution entries with one LDS read, and
+// the row sums are reduced over the 8 lanes of a row (three DPP steps).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct Quad {
+    T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Quad<T> ld4(const T* p) {
+    Quad<T> q;
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        q.v[0] = a.x; q.v[1] = a.y; q.v[2] = a.z; q.v[3] = a.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        q.v[0] = a.x; q.v[1] = a.y; q.v[2] = b.x; q.v[3] = b.y;
+    }
+    return q;
+}
+
+template <typename T>
+__device__ __forceinline__ T dot4(const Quad<T>& a, const Quad<T>& b) {
+    return a.v[0] * b.v[0] + a.v[1] * b.v[1] + a.v[2] * b.v[2] + a.v[3] * b.v[3];
+}
+
+// Sum over the 8 lanes of a row, result in every lane: quad_perm [1,0,3,2], [2,3,0,1],
+// then row_half_mirror (lane i <-> 7 - i inside each group of 8).
+template <typename T>
+__device__ __forceinline__ T sum8(T v) {
+    if constexpr (sizeof(T) == 4) {
+        v += dpp_f<0xb1>(v);
+        v += dpp_f<0x4e>(v);
+        return v + dpp_f<0x141>(v);
+    } else {
+        v += dpp_d<0xb1>(v);
+        v += dpp_d<0x4e>(v);
+        return v + dpp_d<0x141>(v);
+    }
+}
+
+template <typename T>
+constexpr int pf_small() { return sizeof(T) == 4 ? 6 : 3; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restrict__ F,
+                                                         const int32_t* __restrict__ order,
+                                                         const int32_t* __restrict__ slots,
+                                                         const T* __restrict__ vin, T* __restrict__ out,
+                                                         const int64_t* __restrict__ off) {
+    constexpr int kPF = pf_small<T>();
+    extern __shared__ double2 small_lds[];
+    __shared__ __align__(16) T part[kT];
+    const int s = order[blockIdx.x];
+    const Sub sb = e.subs[s];
+    const int nT = sb.nT;
+    if (nT == 0) return;
+    T* xo = out + off[s];
+    T* x = reinterpret_cast<T*>(small_lds);
+    const int tid = threadIdx.x, r = tid >> 3, q = tid & 7;
+    const int el = r * kT + 4 * q;   // first of this thread's four elements in a tile
+    const int32_t* tfc = e.tfc + sb.env_off;
+    const int32_t* tlc = e.tlc + sb.env_off;
+    const int64_t* lrow = e.lrow + sb.env_off;
+    const int64_t* urow = e.urow + sb.env_off;
+    const int32_t* sl = slots + sb.slot_off;
+    const T* D = F + sb.diag_off + el;
+    const int len = nT * kT;
+    for (int i = tid; i < len; i += 256) x[i] = i < sb.n ? vin[sl[i]] : (T)0;
+    Quad<T> bufA[kPF], bufB[kPF];
+    int nA = 0, nB = 0;
+    Quad<T> dA, dB;
+    auto load = [&](Quad<T>(&buf)[kPF], const T* src, int n) {
+#pragma unroll
+        for (int t = 0; t < kPF; ++t)
+            if (t < n) buf[t] = ld4(src + (int64_t)t * kTT);
+    };
+    auto dot = [&](const Quad<T>(&buf)[kPF], const T* y, int n) {
+        T acc = 0;
+#pragma unroll
+        for (int t = 0; t < kPF; ++t) {
+            if (t >= n) break;
+            acc += dot4(buf[t], ld4(y + t * kT));
+        }
+        return acc;
+    };
+    auto tail = [&](const T* src, const T* y, int t0, int nt) {
+        T acc = 0;
+        int t = t0;
+        for (; t + 4 <= nt; t += 4) {
+            Quad<T> a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = ld4(src + (int64_t)(t + u) * kTT);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += dot4(a[u], ld4(y + (t + u) * kT));
+        }
+        for (; t < nt; ++t) acc += dot4(ld4(src + (int64_t)t * kTT), ld4(y + t * kT));
+        return acc;
+    };
+    auto fetch_l = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
+        const int Ic = min(I, nT - 1);
+        nb = min(Ic - tfc[Ic], kPF);
+        load(buf, F + lrow[Ic] + el, nb);
+    };
+    auto fetch_u = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
+        const int Ic = max(I, 0);
+        nb = min(tlc[Ic] - Ic, kPF);
+        load(buf, F + urow[Ic] + el, nb);
+    };
+    fetch_l(0, bufA, nA);
+    fetch_l(1, bufB, nB);
+    dA = ld4(D);
+    dB = ld4(D + (int64_t)min(1, nT - 1) * kTT);
+    __syncthreads();
+    // ---- forward: L y = b (inv(L_II) strictly lower, unit diagonal implied)
+    auto fwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
+        const int j0 = tfc[I], nt = I - j0;
+        const T* y = x + j0 * kT + 4 * q;
+        T acc = dot(buf, y, nb);
+        if (nt > kPF) acc += tail(F + lrow[I] + el, y, kPF, nt);
+        fetch_l(I + 2, buf, nb);
+        acc = sum8(acc);
+        if (q == 0) part[r] = x[I * kT + r] - acc;
+        __syncthreads();
+        const Quad<T> p4 = ld4(part + 4 * q);
+        T v = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int col = 4 * q + m;
+            v += (col < r ? db.v[m] : (col == r ? (T)1 : (T)0)) * p4.v[m];
+        }
+        v = sum8(v);
+        if (q == 0) x[I * kT + r] = v;
+        db = ld4(D + (int64_t)min(I + 2, nT - 1) * kTT);
+        __syncthreads();
+    };
+    for (int I = 0; I < nT; I += 2) {
+        fwd_row(I, bufA, nA, dA);
+        if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
+    }
+    // ---- backward: U x = y (inv(U_II) on and above the diagonal)
+    auto bwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
+        const int nt = tlc[I] - I;
+        const T* y = x + (I + 1) * kT + 4 * q;
+        T acc = dot(buf, y, nb);
+        if (nt > kPF) acc += tail(F + urow[I] + el, y, kPF, nt);
+        fetch_u(I - 2, buf, nb);
+        acc = sum8(acc);
+        if (q == 0) part[r] = x[I * kT + r] - acc;
+        __syncthreads();
+        const Quad<T> p4 = ld4(part + 4 * q);
+        T v = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v += (4 * q + m >= r ? db.v[m] : (T)0) * p4.v[m];
+        v = sum8(v);
+        if (q == 0) x[I * kT + r] = v;
+        db = ld4(D + (int64_t)max(I - 2, 0) * kTT);
+        __syncthreads();
+    };
+    fetch_u(nT - 1, bufA, nA);
+    fetch_u(nT - 2, bufB, nB);
+    dA = ld4(D + (int64_t)(nT - 1) * kTT);
+    dB = ld4(D + (int64_t)max(nT - 2, 0) * kTT);
+    for (int I = nT - 1; I >= 0; I -= 2) {
+        bwd_row(I, bufA, nA, dA);
+        if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+    }
+    for (int i = tid; i < len; i += 256) xo[i] = x[i];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -613,13 +788,19 @@ void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vi
                          c->subs[s0].slot_off;
     const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)rows * (3.0 * sizeof(T) + 4.0);
     timer_begin(c, "trsv");
+    timer_begin(c, duals ? "trsv_d" : "trsv_p");
     const size_t lds = (size_t)c->maxT * kT * sizeof(T);
-    if (lds <= kTrsvLdsMax && c->trsv_mode == 0)
+    const size_t lds_set = (size_t)c->maxT_set[set] * kT * sizeof(T);
+    if (duals && lds_set <= kTrsvLdsMax)
+        trsv_small_kernel<T><<<nsub, 256, lds_set, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
+                                                               c->d_sub_slots, vin, out_local, c->d_local_off);
+    else if (lds <= kTrsvLdsMax && c->trsv_mode == 0)
         trsv_sub_kernel<T, true><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
                                                                 c->d_sub_slots, vin, out_local, c->d_local_off);
     else
         trsv_sub_kernel<T, false><<<nsub, 1024, 0, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
                                                                c->d_sub_slots, vin, out_local, c->d_local_off);
+    timer_end(c, duals ? "trsv_d" : "trsv_p", bytes);
     timer_end(c, "trsv", bytes);
 }
 
