@@ -142,6 +142,7 @@ int upload_all(gplmm_ctx* c) {
     c->prim_factor_elems = c->Nc > 0 ? c->subs[c->Np].diag_off : c->factor_elems;
     c->prim_rows = c->Nc > 0 ? c->subs[c->Np].slot_off : (int64_t)c->sub_slots.size();
     GP_TRY(alloc(c, &c->d_factor, real_size(c) * c->factor_elems));
+    GP_TRY(alloc(c, (void**)&c->d_inv64, sizeof(double) * 1024 * std::max(nsub, 1)));
     GP_TRY(alloc(c, &c->d_local, real_size(c) * local_off[nsub]));
     // shape/correction blocks: column-major with ld = nT * T, right-hand sides built here
     std::vector<int64_t> phi_off(c->Np + 1, 0);
@@ -964,7 +965,7 @@ void gplmm_destroy(gplmm_ctx* c) {
                     c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids,
                     c->d_noclose, c->d_Aoasm, c->d_sub_order[0], c->d_sub_order[1], c->d_co_blk, c->d_co_loc,
                     c->d_cblk_n, c->d_cblk_idx, c->d_cblk_ioff, c->d_cblk_moff, c->d_csamp, c->d_sphys, c->d_seg,
-                    c->d_sscale};
+                    c->d_sscale, c->d_inv64};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_red) hipHostFree(c->h_red);

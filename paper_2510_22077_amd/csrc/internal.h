@@ -158,6 +158,7 @@ struct gplmm_ctx {
     int32_t* d_step_pairs[2] = {nullptr, nullptr};
     int32_t* d_sub_list[2] = {nullptr, nullptr};
     void* d_factor = nullptr;            // real (float or double) tiles
+    double* d_inv64 = nullptr;           // per subdomain: FP64 inverses of the current LU step's diagonal tile
     int64_t prim_factor_elems = 0;       // primaries' tiles come first
     int64_t prim_rows = 0;               // primaries' rows come first in the slot lists
     void* d_phi = nullptr;               // real shape/correction vectors (column-major, ld = nT*T)

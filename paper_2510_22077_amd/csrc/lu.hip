@@ -129,92 +129,174 @@ __global__ void pad_kernel(Env e, T* F, int first_sub, int nsub) {
 }
 
 // ---------------------------------------------------------------------------------------
-// LU step K, part 1 (one block per active subdomain): factor the diagonal tile and
-// form the U panel U_KJ = L_KK^-1 A_KJ.
+// Tile products on the matrix cores (FP32 factors).  v_mfma_f32_32x32x2f32 takes, in lane
+// l, A[l % 32][k] and B[k][l % 32] with k = l / 32, and accumulates the 32 x 32 product
+// into 16 registers per lane: register v of lane l holds C[8 (v / 4) + 4 (l / 32) + v % 4]
+// [l % 32].  Sixteen such steps (k = 2 s + l / 32, s = 0..15) make one 32 x 32 x 32 product.
+// ---------------------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int mrow(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+__device__ __forceinline__ f32x16 mfma_tile(f32x16 acc, const float (&a)[16], const float (&b)[16]) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc, 0, 0, 0);
+    return acc;
+}
+
+// b[s] = B[2 s + l / 32][l % 32] of a row-major tile in global memory (coalesced rows)
+__device__ __forceinline__ void load_b(float (&b)[16], const float* tile, int lane) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) b[s] = tile[(2 * s + (lane >> 5)) * kT + (lane & 31)];
+}
+
+// ---------------------------------------------------------------------------------------
+// LU step K, part 1 (one block per active subdomain): factor the diagonal tile in FP64,
+// store its packed inverses (inv(L_KK) strictly below the diagonal, unit diagonal
+// implied; inv(U_KK) on and above it: the form the triangular solves use), and form the
+// U panel U_KJ = inv(L_KK) A_KJ.
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, const int32_t* __restrict__ list,
-                                                      int K, int* __restrict__ flag) {
-    __shared__ T D[kT][kT + 1];
-    __shared__ T B[kT][kT + 1];
-    const Sub sb = e.subs[list[blockIdx.x]];
+                                                      int K, int* __restrict__ flag, double* __restrict__ inv64) {
+    __shared__ double A[kT][kT + 1];
+    __shared__ double X[kT][kT + 1];
+    __shared__ double B[kT][kT + 1];
+    const int sub = list[blockIdx.x];
+    const Sub sb = e.subs[sub];
     const int tid = threadIdx.x;
     T* dp = F + sb.diag_off + (int64_t)K * kTT;
-    for (int x = tid; x < kTT; x += blockDim.x) D[x / kT][x % kT] = dp[x];
+    for (int x = tid; x < kTT; x += blockDim.x) A[x / kT][x % kT] = (double)dp[x];
     __syncthreads();
     for (int k = 0; k < kT; ++k) {
-        const T piv = D[k][k];
-        if (tid == 0 && (!(piv == piv) || piv == (T)0 || fabs((double)piv) > 1e300)) atomicOr(flag, 1);
-        if (tid > k && tid < kT) D[tid][k] = D[tid][k] / piv;
+        const double piv = A[k][k];
+        if (tid == 0 && (!(piv == piv) || piv == 0.0 || fabs(piv) > 1e300)) atomicOr(flag, 1);
+        if (tid > k && tid < kT) A[tid][k] = A[tid][k] / piv;
         __syncthreads();
         for (int x = tid; x < kTT; x += blockDim.x) {
             int i = x / kT, j = x % kT;
-            if (i > k && j > k) D[i][j] -= D[i][k] * D[k][j];
+            if (i > k && j > k) A[i][j] -= A[i][k] * A[k][j];
         }
         __syncthreads();
     }
-    for (int x = tid; x < kTT; x += blockDim.x) dp[x] = D[x / kT][x % kT];
+    // packed inverses by substitution, one column per thread (c: inv(L) e_c, 32 + c: inv(U) e_c)
+    if (tid < 2 * kT) {
+        const int c = tid & 31;
+        if (tid < kT) {
+            double col[kT];
+#pragma unroll
+            for (int i = 0; i < kT; ++i) {
+                double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < i; ++k)
+                    if (k >= c) v -= A[i][k] * col[k];
+                col[i] = i < c ? 0.0 : v;
+            }
+#pragma unroll
+            for (int i = 0; i < kT; ++i)
+                if (i > c) X[i][c] = col[i];
+        } else {
+            double col[kT];
+#pragma unroll
+            for (int i = kT - 1; i >= 0; --i) {
+                double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = i + 1; k < kT; ++k)
+                    if (k <= c) v -= A[i][k] * col[k];
+                col[i] = i > c ? 0.0 : v / A[i][i];
+            }
+#pragma unroll
+            for (int i = 0; i < kT; ++i)
+                if (i <= c) X[i][c] = col[i];
+        }
+    }
+    __syncthreads();
+    for (int x = tid; x < kTT; x += blockDim.x) {
+        dp[x] = (T)X[x / kT][x % kT];
+        inv64[(int64_t)sub * kTT + x] = X[x / kT][x % kT];   // FP64 copy for the L panel of this step
+    }
     const int32_t* tfr = e.tfr + sb.env_off;
+    // U panel: U_KJ = inv(L_KK) A_KJ in FP64 (unit lower inverse), rounded to T
     for (int J = K + 1; J < sb.nT && tfr[J] <= K; ++J) {
         T* up = tile_ptr(F, e, sb, K, J);
         __syncthreads();
-        for (int x = tid; x < kTT; x += blockDim.x) B[x / kT][x % kT] = up[x];
+        for (int x = tid; x < kTT; x += blockDim.x) B[x / kT][x % kT] = (double)up[x];
         __syncthreads();
-        for (int k = 0; k < kT - 1; ++k) {   // unit lower forward substitution, all columns at once
-            for (int x = tid; x < kTT; x += blockDim.x) {
-                int i = x / kT, j = x % kT;
-                if (i > k) B[i][j] -= D[i][k] * B[k][j];
-            }
-            __syncthreads();
+        for (int x = tid; x < kTT; x += blockDim.x) {
+            const int i = x / kT, j = x % kT;
+            double acc = B[i][j];
+            for (int m = 0; m < i; ++m) acc += X[i][m] * B[m][j];
+            up[x] = (T)acc;
         }
-        for (int x = tid; x < kTT; x += blockDim.x) up[x] = B[x / kT][x % kT];
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// LU step K, part 2 (one block per (subdomain, tile row I > K)): L_IK = A_IK U_KK^-1,
-// then A_IJ -= L_IK U_KJ for every J > K in the envelope.
+// LU step K, part 2 (one block per (subdomain, tile row I > K)): L_IK = A_IK inv(U_KK),
+// then A_IJ -= L_IK U_KJ for every J > K in the envelope.  FP32: the products run on the
+// matrix cores, one wave per trailing tile; FP64: on the vector units through LDS.
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) lu_row_kernel(Env e, T* __restrict__ F, const int32_t* __restrict__ pairs,
-                                                     int K) {
-    __shared__ T U[kT][kT + 1];
+                                                     int K, const double* __restrict__ inv64) {
     __shared__ T Lt[kT][kT + 1];
     __shared__ T Bt[kT][kT + 1];
-    const Sub sb = e.subs[pairs[2 * blockIdx.x]];
+    __shared__ double Ad[kT][kT + 1];
+    __shared__ double Ui[kT][kT + 1];
+    const int sub = pairs[2 * blockIdx.x];
+    const Sub sb = e.subs[sub];
     const int I = pairs[2 * blockIdx.x + 1];
     const int tid = threadIdx.x;
-    const T* dp = F + sb.diag_off + (int64_t)K * kTT;
+    const double* ip = inv64 + (int64_t)sub * kTT;   // packed FP64 inverses of step K; inv(U_KK) on and above
     T* lp = tile_ptr(F, e, sb, I, K);
+    const int32_t* tfr = e.tfr + sb.env_off;
+    int J1 = K + 1;
+    while (J1 < sb.nT && tfr[J1] <= K) ++J1;
+    // L panel: L_IK = A_IK inv(U_KK) in FP64, rounded to T
     for (int x = tid; x < kTT; x += blockDim.x) {
-        U[x / kT][x % kT] = dp[x];
-        Lt[x / kT][x % kT] = lp[x];
+        Ad[x / kT][x % kT] = (double)lp[x];
+        Ui[x / kT][x % kT] = ip[x];
     }
     __syncthreads();
-    // X U = A, column by column (U upper with its diagonal)
-    for (int k = 0; k < kT; ++k) {
-        if (tid < kT) Lt[tid][k] = Lt[tid][k] / U[k][k];
-        __syncthreads();
-        for (int x = tid; x < kTT; x += blockDim.x) {
-            int i = x / kT, j = x % kT;
-            if (j > k) Lt[i][j] -= Lt[i][k] * U[k][j];
-        }
-        __syncthreads();
+    for (int x = tid; x < kTT; x += blockDim.x) {
+        const int i = x / kT, j = x % kT;
+        double acc = 0.0;
+        for (int m = 0; m <= j; ++m) acc += Ad[i][m] * Ui[m][j];
+        Lt[i][j] = (T)acc;
+        lp[x] = (T)acc;
     }
-    for (int x = tid; x < kTT; x += blockDim.x) lp[x] = Lt[x / kT][x % kT];
-    const int32_t* tfr = e.tfr + sb.env_off;
-    for (int J = K + 1; J < sb.nT && tfr[J] <= K; ++J) {
-        const T* up = tile_ptr(F, e, sb, K, J);
-        T* ap = tile_ptr(F, e, sb, I, J);
-        __syncthreads();
-        for (int x = tid; x < kTT; x += blockDim.x) Bt[x / kT][x % kT] = up[x];
-        __syncthreads();
-        for (int x = tid; x < kTT; x += blockDim.x) {
-            int i = x / kT, j = x % kT;
-            T acc = 0;
+    __syncthreads();
+    if constexpr (sizeof(T) == 4) {
+        const int lane = tid & 63, w = tid >> 6;
+        float a[16];   // -L_IK in the A-operand layout
+#pragma unroll
+        for (int s = 0; s < 16; ++s) a[s] = -Lt[lane & 31][2 * s + (lane >> 5)];
+        for (int J = K + 1 + w; J < J1; J += 4) {
+            const T* up = tile_ptr(F, e, sb, K, J);
+            T* ap = tile_ptr(F, e, sb, I, J);
+            float b[16];
+            load_b(b, up, lane);
+            // the product is accumulated from zero and subtracted once, so A_IJ is rounded
+            // once per step rather than once per k-pair
+            f32x16 acc = {};
+            acc = mfma_tile(acc, a, b);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) ap[mrow(v, lane) * kT + (lane & 31)] += acc[v];
+        }
+    } else {
+        for (int J = K + 1; J < J1; ++J) {
+            const T* up = tile_ptr(F, e, sb, K, J);
+            T* ap = tile_ptr(F, e, sb, I, J);
+            __syncthreads();
+            for (int x = tid; x < kTT; x += blockDim.x) Bt[x / kT][x % kT] = up[x];
+            __syncthreads();
+            for (int x = tid; x < kTT; x += blockDim.x) {
+                int i = x / kT, j = x % kT;
+                T acc = 0;
 #pragma unroll 8
-            for (int m = 0; m < kT; ++m) acc += Lt[i][m] * Bt[m][j];
-            ap[x] -= acc;
+                for (int m = 0; m < kT; ++m) acc += Lt[i][m] * Bt[m][j];
+                ap[x] -= acc;
+            }
         }
     }
 }
@@ -681,57 +763,6 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
 }
 
 // ---------------------------------------------------------------------------------------
-// After a set is factorised: replace every diagonal tile (packed unit-lower L and upper U)
-// by its packed inverses, inv(L) strictly below the diagonal and inv(U) on and above it.
-// Columns are computed in FP64 by substitution (thread c: column c of inv(L); thread
-// 32 + c: column c of inv(U)).  One 64-thread block per (subdomain, tile stride).
-// ---------------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(64) invert_diag_kernel(Env e, T* __restrict__ F, int first_sub) {
-    __shared__ double A[kT][kT + 1];
-    __shared__ double X[kT][kT + 1];
-    const Sub sb = e.subs[first_sub + blockIdx.x];
-    const int tid = threadIdx.x, c = tid & 31;
-    const bool up = tid >= kT;
-    for (int I = blockIdx.y; I < sb.nT; I += gridDim.y) {
-        T* dp = F + sb.diag_off + (int64_t)I * kTT;
-        __syncthreads();
-        for (int x = tid; x < kTT; x += 64) A[x / kT][x % kT] = (double)dp[x];
-        __syncthreads();
-        double col[kT];
-        if (!up) {   // inv(L) e_c, L unit lower
-#pragma unroll
-            for (int i = 0; i < kT; ++i) {
-                double v = i == c ? 1.0 : 0.0;
-                if (i > c) {
-#pragma unroll
-                    for (int k = 0; k < i; ++k)
-                        if (k >= c) v -= A[i][k] * col[k];
-                }
-                col[i] = i < c ? 0.0 : v;
-            }
-        } else {      // inv(U) e_c, U upper
-#pragma unroll
-            for (int i = kT - 1; i >= 0; --i) {
-                double v = i == c ? 1.0 : 0.0;
-                if (i <= c) {
-#pragma unroll
-                    for (int k = i + 1; k < kT; ++k)
-                        if (k <= c) v -= A[i][k] * col[k];
-                }
-                col[i] = i > c ? 0.0 : v / A[i][i];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < kT; ++i)
-            if (up ? (i <= c) : (i > c)) X[i][c] = col[i];
-        __syncthreads();
-        for (int x = tid; x < kTT; x += 64) dp[x] = (T)X[x / kT][x % kT];
-    }
-}
-
-// ---------------------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------------------
 static Env make_env(gplmm_ctx* c) { return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_tlc, c->d_lrow, c->d_urow}; }
@@ -763,13 +794,11 @@ int factor_set(gplmm_ctx* c, int set) {
     for (int K = 0; K + 1 < (int)soff.size(); ++K) {
         int ns = (int)(soff[K + 1] - soff[K]);
         if (ns == 0) break;
-        lu_diag_kernel<T><<<ns, 256, 0, c->stream>>>(e, F, c->d_sub_list[set] + soff[K], K, c->d_flag);
+        lu_diag_kernel<T><<<ns, 256, 0, c->stream>>>(e, F, c->d_sub_list[set] + soff[K], K, c->d_flag, c->d_inv64);
         int np = (int)(poff[K + 1] - poff[K]);
-        if (np > 0) lu_row_kernel<T><<<np, 256, 0, c->stream>>>(e, F, c->d_step_pairs[set] + 2 * poff[K], K);
+        if (np > 0)
+            lu_row_kernel<T><<<np, 256, 0, c->stream>>>(e, F, c->d_step_pairs[set] + 2 * poff[K], K, c->d_inv64);
     }
-    const int nsub = set == 0 ? c->Np : c->Np + c->Nc;
-    if (nsub > 0)
-        invert_diag_kernel<T><<<dim3(nsub, (unsigned)std::min(c->maxT, 16)), 64, 0, c->stream>>>(e, F, 0);
     return GPLMM_OK;
 }
 
