@@ -301,8 +301,10 @@ int build_precond(gplmm_ctx* c) {
         GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * c->co_elems, s));
         double* e = c->d_cv;
         double* tco = c->d_cv + nco;
-        double* pv = c->d_r;     // FP64 scratch vectors
-        double* xv = c->d_tmp;
+        // FP64 scratch: the first two Krylov basis vectors, which hold nothing between
+        // FGMRES solves (the Newton residual and step vectors must survive a rebuild)
+        double* pv = c->d_V;
+        double* xv = c->d_V + c->N;
         for (int k = 0; k < c->ncolors; ++k) {
             int64_t c0 = c->color_col_off[k], c1 = c->color_col_off[k + 1];
             GP_HIP(c, hipMemsetAsync(e, 0, sizeof(double) * nco, s));

@@ -243,3 +243,23 @@ def test_preconditioner_parity_on_a_crop_of_the_benchmark_packing():
                 m_ = cls == nm
                 _say("  class", nm, m_.sum(), "err norm %.3e of %.3e" % (np.linalg.norm(d[m_]), np.linalg.norm(zo[m_])))
         assert err <= 1e-9
+
+
+def test_rebuild_keeps_the_newton_residual():
+    """The preconditioner rebuild before the second Newton step (wind = the Stokes
+    solution) must not disturb the Newton right-hand side: two steps of the solve equal
+    one step taken from the first iterate with a preconditioner built there."""
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    w = workload("spheres3d_24", 0, re=10.0)
+    kw = dict(rho=w["rho"], mu=w["mu"], body=w["body"], newton_tol=1e-14, lin_tol=1e-12, line_search=False)
+    a = Solver(w["mask"], w["labels"], newton_maxit=1, **kw)
+    x1, _ = a.newton_solve()
+    b = Solver(w["mask"], w["labels"], newton_maxit=2, **kw)
+    x2, st = b.newton_solve()
+    c = Solver(w["mask"], w["labels"], newton_maxit=1, wind="caller", **kw)
+    c.build(x1)
+    x2c, _ = c.newton_solve(x0=x1.clone())
+    e = (torch.linalg.norm(x2 - x2c) / torch.linalg.norm(x2c)).item()
+    _say("rebuild step difference", e, st["res_hist"])
+    assert e <= 1e-9
