@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--workload", default="spheres3d_128")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--restart", type=int, default=128)
+    ap.add_argument("--restart", type=int, default=256)
     ap.add_argument("--cpu-crop", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true",

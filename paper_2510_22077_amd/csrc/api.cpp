@@ -14,6 +14,9 @@
 
 namespace gp {
 void cgs2(gplmm_ctx* c, const double* V, int64_t ldv, int k, double* w, int64_t n, double* hout);
+void dots2(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* y, int64_t n, double* a, double* b);
+double update2(gplmm_ctx* c, double* V, int64_t ldv, int j, const double* t, const double* s, double sj,
+               double ainv, double* w, int64_t n);
 void lincomb(gplmm_ctx* c, const double* Z, int64_t ldz, int k, const double* y_host, double* x, int64_t n);
 int64_t red_scratch_doubles();
 
@@ -254,7 +257,7 @@ int upload_all(gplmm_ctx* c) {
     GP_TRY(alloc(c, (void**)&c->d_V, sizeof(double) * (int64_t)(m + 1) * N));
     GP_TRY(alloc(c, (void**)&c->d_Z, sizeof(double) * (int64_t)m * N));
     GP_TRY(alloc(c, (void**)&c->d_red, sizeof(double) * red_scratch_doubles()));
-    GP_HIP(c, hipHostMalloc((void**)&c->h_red, sizeof(double) * 4 * (kMaxRestart + 2), hipHostMallocDefault));
+    GP_HIP(c, hipHostMalloc((void**)&c->h_red, sizeof(double) * 8 * (kMaxRestart + 2), hipHostMallocDefault));
     GP_TRY(alloc(c, &c->d_pv, real_size(c) * 6 * N));
     return GPLMM_OK;
 }
@@ -323,12 +326,37 @@ int do_apply(gplmm_ctx* c, const double* v, double* z) {
 }
 
 // FGMRES(m) for J(xk) d = b, d = 0 initially; |residual| <= tol_abs.  Returns iterations.
+//
+// Arnoldi with classical Gram-Schmidt applied twice, the second projection of each basis
+// vector delayed into the next step (DCGS2: Bielich, Langou, Thomas, Swirydowicz, Yamazaki
+// and Boman, Parallel Computing 2022): step j computes the dots of V[0..j] with both the
+// tentative v_j and the new w = J z_j in one pass, then, in a second pass, finishes v_j
+// (v_j <- (v_j - V t) / alpha) and projects w against the finished basis.  The Hessenberg
+// column j - 1, whose subdiagonal entry referred to the tentative v_j, is corrected by the
+// same coefficients (J z_{j-1} = sum_i h_i v_i + beta (alpha v_j' + V t)) and only then
+// rotated, so the residual estimate lags the basis by one step.  z_j = M^-1 (tentative v_j)
+// is kept as computed: flexible GMRES needs only J Z = V H with orthonormal V.
 int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double tol_abs, int maxit, bool* ok) {
     const int64_t N = c->N;
     const int m = c->opt.restart;
     double* V = c->d_V;
     double* Z = c->d_Z;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 2);
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), a(m + 2), bb(m + 2);
+    auto Hx = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+    auto rotate = [&](int col) {   // previous rotations, then a new one eliminating H[col+1][col]
+        for (int i = 0; i < col; ++i) {
+            const double t = cs[i] * Hx(i, col) + sn[i] * Hx(i + 1, col);
+            Hx(i + 1, col) = -sn[i] * Hx(i, col) + cs[i] * Hx(i + 1, col);
+            Hx(i, col) = t;
+        }
+        const double den = std::hypot(Hx(col, col), Hx(col + 1, col));
+        cs[col] = den > 0.0 ? Hx(col, col) / den : 1.0;
+        sn[col] = den > 0.0 ? Hx(col + 1, col) / den : 0.0;
+        Hx(col, col) = den;
+        Hx(col + 1, col) = 0.0;
+        g[col + 1] = -sn[col] * g[col];
+        g[col] = cs[col] * g[col];
+    };
     hipMemsetAsync(d, 0, sizeof(double) * N, c->stream);
     hipMemcpyAsync(V, b, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream);
     double beta = nrm2(c, V, N);
@@ -338,9 +366,11 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
         scal_copy(c, 1.0 / beta, V, V, N);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        int k = 0;
+        int kdone = 0;          // finished Hessenberg columns
         bool stop = false;
-        for (int j = 0; j < m && total < maxit; ++j) {
+        double bprev = 0.0;     // norm of the projected w of the previous step
+        int j = 0;
+        for (; j < m && total < maxit; ++j) {
             double* vj = V + (int64_t)j * N;
             double* zj = Z + (int64_t)j * N;
             double* w = V + (int64_t)(j + 1) * N;
@@ -349,38 +379,79 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
             timer_begin(c, "jv");
             launch_jv(c, xk, zj, w, c->stream);
             timer_end(c, "jv", c->jv_bytes);
-            timer_begin(c, "arnoldi");
-            cgs2(c, V, N, j + 1, w, N, hcol.data());
-            timer_end(c, "arnoldi", 0.0);
-            double hn = hcol[j + 1];
-            for (int i = 0; i <= j; ++i) H[i * m + j] = hcol[i];
-            H[(j + 1) * m + j] = hn;
-            if (hn > 0.0) scal_copy(c, 1.0 / hn, w, w, N);
-            for (int i = 0; i < j; ++i) {
-                double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-                H[i * m + j] = t;
-            }
-            double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-            cs[j] = H[j * m + j] / den;
-            sn[j] = H[(j + 1) * m + j] / den;
-            H[j * m + j] = den;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
             ++total;
-            k = j + 1;
-            if (std::fabs(g[j + 1]) <= tol_abs || hn == 0.0) {
+            timer_begin(c, "arnoldi");
+            dots2(c, V, N, j + 1, w, N, a.data(), bb.data());
+            double tt = 0.0, tb = 0.0;
+            for (int i = 0; i < j; ++i) {
+                tt += a[i] * a[i];
+                tb += a[i] * bb[i];
+            }
+            const double alpha = std::sqrt(std::max(a[j] - tt, 1e-300));
+            const double sj = (bb[j] - tb) / alpha;
+            const double wn2 = update2(c, V, N, j, a.data(), bb.data(), sj, 1.0 / alpha, w, N);
+            timer_end(c, "arnoldi", 0.0);
+            const double hn = std::sqrt(std::max(wn2, 0.0));
+            if (j >= 1) {   // column j - 1 referred to the tentative v_j
+                for (int i = 0; i < j; ++i) Hx(i, j - 1) += bprev * a[i];
+                Hx(j, j - 1) = bprev * alpha;
+                rotate(j - 1);
+                kdone = j;
+                if (std::fabs(g[j]) <= tol_abs) {
+                    stop = true;
+                    break;
+                }
+            }
+            for (int i = 0; i < j; ++i) Hx(i, j) = bb[i];
+            Hx(j, j) = sj;
+            Hx(j + 1, j) = hn;
+            bprev = hn;
+            // residual estimate with column j as it stands (its subdiagonal entry changes only
+            // by the rounding-level reorthogonalisation of v_{j+1}): when it meets the
+            // tolerance, or w lies in the span of the basis, column j is final
+            double hj, hj1;
+            {
+                std::vector<double> col(j + 2);
+                for (int i = 0; i <= j; ++i) col[i] = Hx(i, j);
+                col[j + 1] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                    col[i] = t;
+                }
+                hj = col[j];
+                hj1 = col[j + 1];
+            }
+            const double den = std::hypot(hj, hj1);
+            const double est = den > 0.0 ? std::fabs(hj1 / den * g[j]) : 0.0;
+            if (est <= tol_abs || !(hn > 0.0)) {
+                rotate(j);
+                kdone = j + 1;
                 stop = true;
+                ++j;
                 break;
             }
+            scal_copy(c, 1.0 / hn, w, w, N);
         }
+        if (!stop && kdone < j) {
+            // the last column: one more pass gives the delayed projection of v_j
+            dots2(c, V, N, j + 1, V + (int64_t)j * N, N, a.data(), bb.data());
+            double tt = 0.0;
+            for (int i = 0; i < j; ++i) tt += a[i] * a[i];
+            const double alpha = std::sqrt(std::max(a[j] - tt, 1e-300));
+            for (int i = 0; i < j; ++i) Hx(i, j - 1) += bprev * a[i];
+            Hx(j, j - 1) = bprev * alpha;
+            rotate(j - 1);
+            kdone = j;
+            if (std::fabs(g[j]) <= tol_abs) stop = true;
+        }
+        const int k = kdone;
         for (int i = k - 1; i >= 0; --i) {
             double s = g[i];
-            for (int l = i + 1; l < k; ++l) s -= H[i * m + l] * y[l];
-            y[i] = s / H[i * m + i];
+            for (int l = i + 1; l < k; ++l) s -= Hx(i, l) * y[l];
+            y[i] = s / Hx(i, i);
         }
-        lincomb(c, Z, N, k, y.data(), d, N);
+        if (k > 0) lincomb(c, Z, N, k, y.data(), d, N);
         if (stop) {
             *ok = true;
             break;

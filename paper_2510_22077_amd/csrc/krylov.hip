@@ -116,6 +116,103 @@ __global__ void scal_copy_kernel(double alpha, const double* __restrict__ x, dou
     if (i < n) y[i] = alpha * x[i];
 }
 
+// Delayed classical Gram-Schmidt (the reorthogonalisation of v_j is carried out in the
+// step that projects w, so each Arnoldi step reads the basis twice): partial sums of
+// V_i . x and V_i . y for i < k in one pass; partial[i * nblk + b] and
+// partial[(k + i) * nblk + b].
+__global__ void __launch_bounds__(kThreads) multidot2_kernel(const double* __restrict__ V, int64_t ldv, int k,
+                                                             const double* __restrict__ x,
+                                                             const double* __restrict__ y, int64_t n,
+                                                             double* __restrict__ partial) {
+    __shared__ double sh[kThreads / 64][2 * kGroup];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < k; j0 += kGroup) {
+        const int kk = min(kGroup, k - j0);
+        const double* Vg = V + (int64_t)j0 * ldv;
+        double ax[kGroup], ay[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) ax[q] = ay[q] = 0.0;
+        for (int64_t r = r0; r < n; r += stride) {
+            const double xr = x[r], yr = y[r];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q)
+                if (q < kk) {
+                    const double v = Vg[(int64_t)q * ldv + r];
+                    ax[q] += v * xr;
+                    ay[q] += v * yr;
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            double a = ax[q], b = ay[q];
+            for (int off = 32; off > 0; off >>= 1) {
+                a += __shfl_down(a, off, 64);
+                b += __shfl_down(b, off, 64);
+            }
+            if (lane == 0) {
+                sh[wv][q] = a;
+                sh[wv][kGroup + q] = b;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < 2 * kk) {
+            const int q = threadIdx.x < kk ? threadIdx.x : threadIdx.x - kk;
+            const int col = threadIdx.x < kk ? q : kGroup + q;
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < kThreads / 64; ++u) t += sh[u][col];
+            const int out = threadIdx.x < kk ? j0 + q : k + j0 + q;
+            partial[(int64_t)out * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// One pass over V[0..j): v_j <- (v_j - sum_i V_i t_i) * ainv, then
+// w <- w - sum_i V_i s_i - v_j sj, with partial sums of the new ||w||^2.
+__global__ void __launch_bounds__(kThreads) update2_kernel(const double* __restrict__ V, int64_t ldv, int j,
+                                                           const double* __restrict__ coef, double sj, double ainv,
+                                                           double* __restrict__ vj, double* __restrict__ w,
+                                                           int64_t n, double* __restrict__ partial_nrm) {
+    __shared__ double sh[16];
+    __shared__ double ts[kMaxRestart], ss[kMaxRestart];
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        ts[i] = coef[i];
+        ss[i] = coef[kMaxRestart + i];
+    }
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double acc = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        double av = 0.0, aw = 0.0;
+        int i = 0;
+        for (; i + kGroup <= j; i += kGroup) {
+            double t[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) t[q] = V[(int64_t)(i + q) * ldv + r];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                av += t[q] * ts[i + q];
+                aw += t[q] * ss[i + q];
+            }
+        }
+        for (; i < j; ++i) {
+            const double t = V[(int64_t)i * ldv + r];
+            av += t * ts[i];
+            aw += t * ss[i];
+        }
+        const double vn = (vj[r] - av) * ainv;
+        vj[r] = vn;
+        const double wn = w[r] - aw - vn * sj;
+        w[r] = wn;
+        acc += wn * wn;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial_nrm[blockIdx.x] = t;
+}
+
 // x += sum_j Z_j y_j
 __global__ void lincomb_kernel(const double* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ y,
                                double* __restrict__ x, int64_t n) {
@@ -161,9 +258,13 @@ inline unsigned nb_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThre
 
 }  // namespace
 
-// Device scratch layout in c->d_red: [0, kMaxRedBlocks*(kMaxRestart+2)) partials, then results.
+// Device scratch layout in c->d_red: [0, kMaxRedBlocks * 2 (kMaxRestart + 2)) partials, then
+// results: h (kMaxRestart + 2), h2 / the dots of V with w, norms, lincomb coefficients, then
+// the coefficients of the delayed Gram-Schmidt update at 4 (kMaxRestart + 2).
+constexpr int64_t kPart = (int64_t)kMaxRedBlocks * 2 * (kMaxRestart + 2);
+constexpr int kRs = kMaxRestart + 2;
 static double* partials(gplmm_ctx* c) { return c->d_red; }
-static double* results(gplmm_ctx* c) { return c->d_red + (int64_t)kMaxRedBlocks * (kMaxRestart + 2); }
+static double* results(gplmm_ctx* c) { return c->d_red + kPart; }
 
 double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n) {
     multidot_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(a, 0, 1, b, n, partials(c));
@@ -260,6 +361,44 @@ template void convert<double, float>(gplmm_ctx*, const double*, float*, int64_t)
 template void convert<float, double>(gplmm_ctx*, const float*, double*, int64_t);
 template void convert<double, double>(gplmm_ctx*, const double*, double*, int64_t);
 
-int64_t red_scratch_doubles() { return (int64_t)kMaxRedBlocks * (kMaxRestart + 2) + 4 * (kMaxRestart + 2) + 64; }
+int64_t red_scratch_doubles() { return kPart + 8 * (int64_t)kRs + 64; }
+
+// Dots of V[0..k) with x = V[k-1] (the vector being reorthogonalised) and with y, one pass:
+// a[i] = V_i . x, b[i] = V_i . y (host).
+void dots2(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* y, int64_t n, double* a, double* b) {
+    const double* x = V + (int64_t)(k - 1) * ldv;
+    multidot2_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(V, ldv, k, x, y, n, partials(c));
+    reduce_kernel<<<2 * k, kThreads, 0, c->stream>>>(partials(c), c->red_blocks, results(c));
+    hipMemcpyAsync(c->h_red, results(c), sizeof(double) * 2 * k, hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    for (int i = 0; i < k; ++i) {
+        a[i] = c->h_red[i];
+        b[i] = c->h_red[k + i];
+    }
+    c->gs_passes++;
+}
+
+// v_j <- (v_j - V[0..j) t) ainv, w <- w - V[0..j) s - v_j sj; returns ||w||^2.
+double update2(gplmm_ctx* c, double* V, int64_t ldv, int j, const double* t, const double* s, double sj,
+               double ainv, double* w, int64_t n) {
+    double* coef = results(c) + 4 * (int64_t)kRs;   // t at [0, kMaxRestart), s at [kMaxRestart, 2 kMaxRestart)
+    double* hc = c->h_red + 4 * kRs;
+    for (int i = 0; i < j; ++i) {
+        hc[i] = t[i];
+        hc[kMaxRestart + i] = s[i];
+    }
+    if (j > 0) {
+        hipMemcpyAsync(coef, hc, sizeof(double) * j, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(coef + kMaxRestart, hc + kMaxRestart, sizeof(double) * j, hipMemcpyHostToDevice, c->stream);
+    }
+    double* nr = results(c) + 6 * (int64_t)kRs;
+    update2_kernel<<<c->red_blocks, kThreads, 0, c->stream>>>(V, ldv, j, coef, sj, ainv, V + (int64_t)j * ldv, w, n,
+                                                             partials(c));
+    reduce_kernel<<<1, kThreads, 0, c->stream>>>(partials(c), c->red_blocks, nr);
+    hipMemcpyAsync(c->h_red + 2 * kRs, nr, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    c->gs_reorth++;
+    return c->h_red[2 * kRs];
+}
 
 }  // namespace gp

@@ -16,7 +16,9 @@
 namespace gp {
 template <typename T>
 void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vin, T* out_local);
-void cgs2(gplmm_ctx* c, const double* V, int64_t ldv, int k, double* w, int64_t n, double* hout);
+void dots2(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* y, int64_t n, double* a, double* b);
+double update2(gplmm_ctx* c, double* V, int64_t ldv, int j, const double* t, const double* s, double sj,
+               double ainv, double* w, int64_t n);
 }
 
 using namespace gp;
@@ -105,14 +107,18 @@ extern "C" int gplmm_autotune(gplmm_ctx* c, const char* cache_path, gplmm_tuning
         }
     }
     if (!t.from_cache) {
-        // Krylov reductions: one Gram-Schmidt step against half a restart cycle of basis vectors
+        // Krylov reductions: one Arnoldi orthogonalisation step (both passes) against half a
+        // restart cycle of basis vectors; the coefficients are zero, so the basis is unchanged
         const int k = std::max(1, std::min(c->opt.restart / 2, 64));
-        double hbuf[kMaxRestart + 2];
+        std::vector<double> ha(k + 1), hb(k + 1), zc(k + 1, 0.0);
         double best = 1e300;
         int best_rb = c->red_blocks;
         for (int rb : {256, 512, 1024, 2048}) {
             c->red_blocks = rb;
-            const double ms = time_ms(c, [&]() { cgs2(c, c->d_V, c->N, k, c->d_V + (int64_t)k * c->N, c->N, hbuf); });
+            const double ms = time_ms(c, [&]() {
+                dots2(c, c->d_V, c->N, k, c->d_V + (int64_t)k * c->N, c->N, ha.data(), hb.data());
+                update2(c, c->d_V, c->N, k - 1, zc.data(), zc.data(), 0.0, 1.0, c->d_V + (int64_t)k * c->N, c->N);
+            });
             if (ms < best) {
                 best = ms;
                 best_rb = rb;
