@@ -161,7 +161,6 @@ __global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, 
                                                       int K, int* __restrict__ flag, double* __restrict__ inv64) {
     __shared__ double A[kT][kT + 1];
     __shared__ double X[kT][kT + 1];
-    __shared__ double B[kT][kT + 1];
     const int sub = list[blockIdx.x];
     const Sub sb = e.subs[sub];
     const int tid = threadIdx.x;
@@ -216,17 +215,41 @@ __global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, 
         inv64[(int64_t)sub * kTT + x] = X[x / kT][x % kT];   // FP64 copy for the L panel of this step
     }
     const int32_t* tfr = e.tfr + sb.env_off;
-    // U panel: U_KJ = inv(L_KK) A_KJ in FP64 (unit lower inverse), rounded to T
-    for (int J = K + 1; J < sb.nT && tfr[J] <= K; ++J) {
-        T* up = tile_ptr(F, e, sb, K, J);
-        __syncthreads();
-        for (int x = tid; x < kTT; x += blockDim.x) B[x / kT][x % kT] = (double)up[x];
-        __syncthreads();
-        for (int x = tid; x < kTT; x += blockDim.x) {
-            const int i = x / kT, j = x % kT;
-            double acc = B[i][j];
-            for (int m = 0; m < i; ++m) acc += X[i][m] * B[m][j];
-            up[x] = (T)acc;
+    int J1 = K + 1;
+    while (J1 < sb.nT && tfr[J1] <= K) ++J1;   // U tiles of row K: columns K+1 .. J1-1
+    if constexpr (sizeof(T) == 4) {
+        // U panel on the matrix cores, one wave per tile: U_KJ = inv(L_KK) A_KJ (unit lower
+        // inverse, rounded to FP32; the product accumulates from zero)
+        const int lane = tid & 63, w = tid >> 6;
+        float a[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int i = lane & 31, k = 2 * s + (lane >> 5);
+            a[s] = k < i ? (float)X[i][k] : (k == i ? 1.f : 0.f);
+        }
+        for (int J = K + 1 + w; J < J1; J += 4) {
+            T* up = tile_ptr(F, e, sb, K, J);
+            float b[16];
+            load_b(b, up, lane);
+            f32x16 acc = {};
+            acc = mfma_tile(acc, a, b);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) up[mrow(v, lane) * kT + (lane & 31)] = acc[v];
+        }
+    } else {
+        // U panel in FP64 on the vector units
+        __shared__ double B[kT][kT + 1];
+        for (int J = K + 1; J < J1; ++J) {
+            T* up = tile_ptr(F, e, sb, K, J);
+            __syncthreads();
+            for (int x = tid; x < kTT; x += blockDim.x) B[x / kT][x % kT] = (double)up[x];
+            __syncthreads();
+            for (int x = tid; x < kTT; x += blockDim.x) {
+                const int i = x / kT, j = x % kT;
+                double acc = B[i][j];
+                for (int m = 0; m < i; ++m) acc += X[i][m] * B[m][j];
+                up[x] = (T)acc;
+            }
         }
     }
 }
@@ -241,8 +264,6 @@ __global__ void __launch_bounds__(256) lu_row_kernel(Env e, T* __restrict__ F, c
                                                      int K, const double* __restrict__ inv64) {
     __shared__ T Lt[kT][kT + 1];
     __shared__ T Bt[kT][kT + 1];
-    __shared__ double Ad[kT][kT + 1];
-    __shared__ double Ui[kT][kT + 1];
     const int sub = pairs[2 * blockIdx.x];
     const Sub sb = e.subs[sub];
     const int I = pairs[2 * blockIdx.x + 1];
@@ -252,18 +273,42 @@ __global__ void __launch_bounds__(256) lu_row_kernel(Env e, T* __restrict__ F, c
     const int32_t* tfr = e.tfr + sb.env_off;
     int J1 = K + 1;
     while (J1 < sb.nT && tfr[J1] <= K) ++J1;
-    // L panel: L_IK = A_IK inv(U_KK) in FP64, rounded to T
-    for (int x = tid; x < kTT; x += blockDim.x) {
-        Ad[x / kT][x % kT] = (double)lp[x];
-        Ui[x / kT][x % kT] = ip[x];
-    }
-    __syncthreads();
-    for (int x = tid; x < kTT; x += blockDim.x) {
-        const int i = x / kT, j = x % kT;
-        double acc = 0.0;
-        for (int m = 0; m <= j; ++m) acc += Ad[i][m] * Ui[m][j];
-        Lt[i][j] = (T)acc;
-        lp[x] = (T)acc;
+    if constexpr (sizeof(T) == 4) {
+        // L panel on the matrix cores (wave 0): L_IK = A_IK inv(U_KK), inverse rounded to FP32
+        const int lane = tid & 63;
+        if (tid < 64) {
+            float a[16], b[16];
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int k = 2 * s + (lane >> 5), j = lane & 31;
+                a[s] = lp[(lane & 31) * kT + k];
+                b[s] = k <= j ? (float)ip[k * kT + j] : 0.f;
+            }
+            f32x16 acc = {};
+            acc = mfma_tile(acc, a, b);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = mrow(v, lane), j = lane & 31;
+                Lt[i][j] = acc[v];
+                lp[i * kT + j] = acc[v];
+            }
+        }
+    } else {
+        // L panel in FP64: L_IK = A_IK inv(U_KK)
+        __shared__ double Ad[kT][kT + 1];
+        __shared__ double Ui[kT][kT + 1];
+        for (int x = tid; x < kTT; x += blockDim.x) {
+            Ad[x / kT][x % kT] = (double)lp[x];
+            Ui[x / kT][x % kT] = ip[x];
+        }
+        __syncthreads();
+        for (int x = tid; x < kTT; x += blockDim.x) {
+            const int i = x / kT, j = x % kT;
+            double acc = 0.0;
+            for (int m = 0; m <= j; ++m) acc += Ad[i][m] * Ui[m][j];
+            Lt[i][j] = (T)acc;
+            lp[x] = (T)acc;
+        }
     }
     __syncthreads();
     if constexpr (sizeof(T) == 4) {
