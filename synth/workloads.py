@@ -52,6 +52,10 @@ WORKLOADS = {
     "spheres3d_128": dict(kind="boolean", shape=(128, 128, 128), mean_r=8.0, sigma=0.3,
                           porosity=0.35, footprint=5, min_size=200, max_size=1500, block=8,
                           re=1.0),
+    # 3D, 256^3, the same grain law at porosity ~0.35, target Re 10 (backward-Euler runs)
+    "spheres3d_256": dict(kind="boolean", shape=(256, 256, 256), mean_r=8.0, sigma=0.3,
+                          porosity=0.35, footprint=5, min_size=200, max_size=1500, block=8,
+                          re=10.0),
     # 3D, 64^3 crop-sized version of the above (same grain law)
     "spheres3d_64": dict(kind="boolean", shape=(64, 64, 64), mean_r=8.0, sigma=0.3,
                          porosity=0.35, footprint=5, min_size=200, max_size=1500, block=8,

@@ -263,3 +263,34 @@ def test_rebuild_keeps_the_newton_residual():
     e = (torch.linalg.norm(x2 - x2c) / torch.linalg.norm(x2c)).item()
     _say("rebuild step difference", e, st["res_hist"])
     assert e <= 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+def test_backward_euler_steps_parity(precision, tol):
+    """Three backward-Euler steps from rest (Section 1 with the time derivative), each a
+    Newton-FGMRES-gPLMM solve against the previous level, preconditioner built once with
+    the wind of the first step: every level matches the oracle's Newton with exact linear
+    solves run on the same steps."""
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    from oracle.mac import Phys
+    w = workload("spheres3d_24", 0, re=10.0)
+    dt = 0.5
+    s = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"], dt=dt, precision=precision,
+               newton_tol=1e-13, lin_tol=1e-14, wind="caller")
+    g, ops, dc, ph0 = oracle_case(w["mask"], w["labels"], w["rho"], w["mu"], w["body"], dt=dt)
+    rec = record_index(g, s.maps()["cell_voxel"])
+    s.build(None)
+    x = s.zeros()
+    xo = np.zeros(g.N)
+    for step in range(3):
+        x_prev = x.clone()
+        x, st = s.newton_solve(x0=x_prev, x_prev=x_prev)
+        assert st["converged"], st
+        xo, _ = newton.solve(ops, dc, ph0, x0=xo, x_old=xo.copy(), tol=1e-14, precond="exact")
+        xg = x.cpu().numpy()[rec]
+        u, p = slice(0, g.nu), g.p_slice
+        eu = rel(xg[u], xo[u])
+        ep = rel(xg[p] - xg[p].mean(), xo[p] - xo[p].mean())
+        _say("BE step", step, precision, "newton", st["newton_its"], st["lin_its"], "u err", eu, "p err", ep)
+        assert eu <= tol and ep <= tol
