@@ -162,10 +162,12 @@ int gplmm_setup(const uint8_t* mask, const int32_t* pore_labels, double rho, dou
  * the batch numbers the cells, primaries and interfaces of sample s after those of
  * samples 0..s-1 (offsets from gplmm_batch_info), and voxels in the concatenation of
  * the images.  Each sample keeps its own pinned cell.  The batch is one block-diagonal
- * system: the coarse operator has one dense block per sample.  gplmm_newton_solve scales
- * each sample's equations by 1 / ||r_s(0)|| so that FGMRES meets lin_tol ||r_s(0)|| and
- * Newton newton_tol ||r_s(0)|| on every sample s; res_hist then holds
- * max_s ||r_s(x_k)|| / ||r_s(0)||, and the line search backtracks per sample.
+ * system: the coarse operator has one dense block per sample.  gplmm_newton_solve runs one
+ * FGMRES Arnoldi process per sample in lockstep (the preconditioner and Jacobian launches
+ * cover all samples; dot products, Hessenberg matrices and stopping tests are per sample)
+ * to lin_tol ||r_s(0)|| on every sample s, and stops Newton at newton_tol ||r_s(0)||;
+ * res_hist holds max_s ||r_s(x_k)|| / ||r_s(0)||, lin_its the lockstep iterations (those
+ * of the slowest sample), and the line search backtracks per sample.
  * 1 <= nsamples <= 1024.  Errors as gplmm_setup; the message names the sample. */
 int gplmm_setup_batch(int nsamples, const uint8_t* const* masks, const int32_t* const* pore_labels,
                       const int32_t* dims, const double* rho, const double* mu, const double* body,

@@ -86,6 +86,19 @@ int upload_all(gplmm_ctx* c) {
         seg.push_back(N);
         GP_TRY(upload(c, &c->d_seg, seg));
         GP_TRY(alloc(c, (void**)&c->d_sscale, sizeof(double) * 2 * c->samples.size()));
+        const size_t nb = sizeof(double) * c->samples.size() * 2 * (size_t)(c->opt.restart + 2);
+        GP_TRY(alloc(c, (void**)&c->d_bres, nb));
+        GP_TRY(alloc(c, (void**)&c->d_bcoef, nb));
+        GP_TRY(alloc(c, (void**)&c->d_bsc, sizeof(double) * 2 * c->samples.size()));
+        GP_HIP(c, hipHostMalloc((void**)&c->h_bres, nb, hipHostMallocDefault));
+        std::vector<int32_t> ss(c->Np + c->Nc);   // sample of each subdomain (of its first unknown)
+        for (int i = 0; i < c->Np + c->Nc; ++i) {
+            const Sub& sb = c->subs[i];
+            ss[i] = c->csamp[c->sub_slots[sb.slot_off] / c->nrec];
+        }
+        GP_TRY(upload(c, &c->d_sub_samp, ss));
+        GP_TRY(upload(c, &c->d_sact, std::vector<uint8_t>(c->samples.size(), 1)));
+        GP_TRY(alloc(c, (void**)&c->d_alist, sizeof(int32_t) * c->samples.size()));
     }
     c->geo = DevGeo{c->nx, c->ny, c->nz, c->ndim, c->nrec, {c->opt.periodic[0], c->opt.periodic[1], c->opt.periodic[2]},
                     nc, (int)c->pin, c->opt.h, c->d_nb6, c->d_tag, c->d_csamp, c->d_sphys};
@@ -466,6 +479,222 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
     return total;
 }
 
+// FGMRES for a batch: one Arnoldi process per sample, run in lockstep.  The preconditioner
+// and the Jacobian act on all samples at once (the batch is block diagonal); the dot
+// products, Gram-Schmidt coefficients, norms, Hessenberg matrices, rotations and stopping
+// tests are per sample (the same delayed CGS2 steps as fgmres()), so each sample converges
+// to its own tolerance tol_abs[s] in as many iterations as it would need alone.  A sample
+// that has converged has its slice of the basis set to zero, which keeps it at zero.
+int fgmres_batch(gplmm_ctx* c, const double* xk, const double* b, double* d, const double* tol_abs, int maxit,
+                 bool* ok) {
+    const int64_t N = c->N;
+    const int m = c->opt.restart;
+    const int ns = (int)c->samples.size();
+    const int ld = m + 2;
+    double* V = c->d_V;
+    double* Z = c->d_Z;
+    std::vector<double> H((size_t)ns * (m + 1) * m, 0.0), cs((size_t)ns * m), sn((size_t)ns * m),
+        g((size_t)ns * (m + 1)), y((size_t)ns * ld, 0.0), a((size_t)ns * (m + 2)), bb((size_t)ns * (m + 2)),
+        coef((size_t)ns * 2 * ld, 0.0), sc((size_t)ns * 2), nrm(ns), beta(ns), bprev(ns), scale(ns);
+    std::vector<int> kdone(ns, 0);
+    std::vector<int32_t> alist;
+    std::vector<char> done(ns, 0), active(ns, 0);
+    auto Hx = [&](int s, int i, int j) -> double& { return H[((size_t)s * (m + 1) + i) * m + j]; };
+    auto rotate = [&](int s, int col) {
+        double* css = cs.data() + (size_t)s * m;
+        double* sns = sn.data() + (size_t)s * m;
+        double* gs = g.data() + (size_t)s * (m + 1);
+        for (int i = 0; i < col; ++i) {
+            const double t = css[i] * Hx(s, i, col) + sns[i] * Hx(s, i + 1, col);
+            Hx(s, i + 1, col) = -sns[i] * Hx(s, i, col) + css[i] * Hx(s, i + 1, col);
+            Hx(s, i, col) = t;
+        }
+        const double den = std::hypot(Hx(s, col, col), Hx(s, col + 1, col));
+        css[col] = den > 0.0 ? Hx(s, col, col) / den : 1.0;
+        sns[col] = den > 0.0 ? Hx(s, col + 1, col) / den : 0.0;
+        Hx(s, col, col) = den;
+        Hx(s, col + 1, col) = 0.0;
+        gs[col + 1] = -sns[col] * gs[col];
+        gs[col] = css[col] * gs[col];
+    };
+    auto seg_norms = [&](const double* v) {
+        seg_sumsq(c, v, nrm.data());
+        for (int s = 0; s < ns; ++s) beta[s] = std::sqrt(std::max(nrm[s], 0.0));
+    };
+    auto set_scale = [&](double* v) -> int {   // v slice of sample s *= scale[s]
+        GP_HIP(c, hipMemcpyAsync(c->d_sscale, scale.data(), sizeof(double) * ns, hipMemcpyHostToDevice, c->stream));
+        seg_scale(c, c->d_sscale, v);
+        return GPLMM_OK;
+    };
+    hipMemsetAsync(d, 0, sizeof(double) * N, c->stream);
+    hipMemcpyAsync(V, b, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream);
+    seg_norms(V);
+    int total = 0, ndone = 0;
+    for (int s = 0; s < ns; ++s)
+        if (beta[s] <= tol_abs[s]) {
+            done[s] = 1;
+            ++ndone;
+        }
+    std::vector<uint8_t> act8(ns, 1);
+    auto push_active = [&]() -> int {   // finished samples skip their local solves
+        for (int s = 0; s < ns; ++s) act8[s] = active[s] ? 1 : 0;
+        GP_HIP(c, hipMemcpyAsync(c->d_sact, act8.data(), ns, hipMemcpyHostToDevice, c->stream));
+        GP_HIP(c, hipStreamSynchronize(c->stream));
+        return GPLMM_OK;
+    };
+    while (ndone < ns && total < maxit) {
+        for (int s = 0; s < ns; ++s) {
+            active[s] = !done[s];
+            scale[s] = done[s] ? 0.0 : 1.0 / beta[s];
+            kdone[s] = 0;
+            std::fill(g.begin() + (size_t)s * (m + 1), g.begin() + (size_t)(s + 1) * (m + 1), 0.0);
+            g[(size_t)s * (m + 1)] = done[s] ? 0.0 : beta[s];
+        }
+        GP_TRY(set_scale(V));
+        GP_TRY(push_active());
+        int nact = ns - ndone, j = 0;
+        for (; j < m && total < maxit && nact > 0; ++j) {
+            double* vj = V + (int64_t)j * N;
+            double* zj = Z + (int64_t)j * N;
+            double* w = V + (int64_t)(j + 1) * N;
+            if (do_apply(c, vj, zj)) return -1;
+            timer_begin(c, "jv");
+            launch_jv(c, xk, zj, w, c->stream);
+            timer_end(c, "jv", c->jv_bytes);
+            ++total;
+            timer_begin(c, "arnoldi");
+            const int k = j + 1;
+            alist.clear();
+            for (int s = 0; s < ns; ++s)
+                if (active[s]) alist.push_back(s);
+            const int na = (int)alist.size();
+            seg_dots2(c, V, N, k, w, alist.data(), na, a.data(), bb.data());
+            for (int yy = 0; yy < na; ++yy) {
+                const int s = alist[yy];
+                double* as = a.data() + (size_t)yy * k;
+                const double* bs = bb.data() + (size_t)yy * k;
+                double* cf = coef.data() + (size_t)s * 2 * ld;
+                double tt = 0.0, tb = 0.0;
+                for (int i = 0; i < j; ++i) {
+                    tt += as[i] * as[i];
+                    tb += as[i] * bs[i];
+                    cf[i] = as[i];
+                    cf[ld + i] = bs[i];
+                }
+                const double alpha = std::sqrt(std::max(as[j] - tt, 1e-300));
+                sc[2 * s] = (bs[j] - tb) / alpha;
+                sc[2 * s + 1] = 1.0 / alpha;
+                as[j] = alpha;   // kept for the column correction below
+            }
+            seg_update2(c, V, N, j, coef.data(), ld, sc.data(), alist.data(), na, w, nrm.data());
+            timer_end(c, "arnoldi", 0.0);
+            bool changed = false;
+            for (int s = 0; s < ns; ++s) scale[s] = 0.0;
+            for (int yy = 0; yy < na; ++yy) {
+                const int s = alist[yy];
+                const double* as = a.data() + (size_t)yy * k;
+                const double* bs = bb.data() + (size_t)yy * k;
+                const double alpha = as[j];
+                const double hn = std::sqrt(std::max(nrm[yy], 0.0));
+                double* gs = g.data() + (size_t)s * (m + 1);
+                bool conv = false;
+                if (j >= 1) {
+                    for (int i = 0; i < j; ++i) Hx(s, i, j - 1) += bprev[s] * as[i];
+                    Hx(s, j, j - 1) = bprev[s] * alpha;
+                    rotate(s, j - 1);
+                    kdone[s] = j;
+                    conv = std::fabs(gs[j]) <= tol_abs[s];
+                }
+                if (!conv) {
+                    for (int i = 0; i < j; ++i) Hx(s, i, j) = bs[i];
+                    Hx(s, j, j) = sc[2 * s];
+                    Hx(s, j + 1, j) = hn;
+                    bprev[s] = hn;
+                    std::vector<double> col(j + 2);
+                    for (int i = 0; i <= j; ++i) col[i] = Hx(s, i, j);
+                    col[j + 1] = hn;
+                    const double* css = cs.data() + (size_t)s * m;
+                    const double* sns = sn.data() + (size_t)s * m;
+                    for (int i = 0; i < j; ++i) {
+                        const double t = css[i] * col[i] + sns[i] * col[i + 1];
+                        col[i + 1] = -sns[i] * col[i] + css[i] * col[i + 1];
+                        col[i] = t;
+                    }
+                    const double den = std::hypot(col[j], col[j + 1]);
+                    const double est = den > 0.0 ? std::fabs(col[j + 1] / den * gs[j]) : 0.0;
+                    if (est <= tol_abs[s] || !(hn > 0.0)) {
+                        rotate(s, j);
+                        kdone[s] = j + 1;
+                        conv = true;
+                    } else {
+                        scale[s] = 1.0 / hn;
+                    }
+                }
+                if (conv) {
+                    active[s] = 0;
+                    --nact;
+                    changed = true;
+                }
+            }
+            GP_TRY(set_scale(w));
+            if (changed) GP_TRY(push_active());
+        }
+        // samples still active at the end of the cycle: the delayed projection of their last
+        // basis vector completes the last Hessenberg column
+        if (nact > 0 && j >= 1) {
+            const int k = j + 1;
+            alist.clear();
+            for (int s = 0; s < ns; ++s)
+                if (active[s]) alist.push_back(s);
+            seg_dots2(c, V, N, k, V + (int64_t)j * N, alist.data(), (int)alist.size(), a.data(), bb.data());
+            for (int yy = 0; yy < (int)alist.size(); ++yy) {
+                const int s = alist[yy];
+                const double* as = a.data() + (size_t)yy * k;
+                double tt = 0.0;
+                for (int i = 0; i < j; ++i) tt += as[i] * as[i];
+                const double alpha = std::sqrt(std::max(as[j] - tt, 1e-300));
+                for (int i = 0; i < j; ++i) Hx(s, i, j - 1) += bprev[s] * as[i];
+                Hx(s, j, j - 1) = bprev[s] * alpha;
+                rotate(s, j - 1);
+                kdone[s] = j;
+            }
+        }
+        int kmax = 0;
+        for (int s = 0; s < ns; ++s) {
+            double* ys = y.data() + (size_t)s * ld;
+            std::fill(ys, ys + ld, 0.0);
+            const int k = done[s] ? 0 : kdone[s];
+            const double* gs = g.data() + (size_t)s * (m + 1);
+            for (int i = k - 1; i >= 0; --i) {
+                double t = gs[i];
+                for (int l = i + 1; l < k; ++l) t -= Hx(s, i, l) * ys[l];
+                ys[i] = t / Hx(s, i, i);
+            }
+            kmax = std::max(kmax, k);
+            if (!done[s] && (std::fabs(gs[k]) <= tol_abs[s])) {
+                done[s] = 1;
+                ++ndone;
+            }
+        }
+        if (kmax > 0) seg_lincomb(c, Z, N, kmax, y.data(), ld, d);
+        if (ndone == ns) break;
+        // restart the unfinished samples from the true residual b - J d
+        launch_jv(c, xk, d, c->d_tmp, c->stream);
+        scal_copy(c, -1.0, c->d_tmp, V, N);
+        axpy(c, 1.0, b, V, N);
+        seg_norms(V);
+        for (int s = 0; s < ns; ++s)
+            if (!done[s] && beta[s] <= tol_abs[s]) {
+                done[s] = 1;
+                ++ndone;
+            }
+    }
+    std::fill(active.begin(), active.end(), 1);   // later builds and applications cover every sample
+    GP_TRY(push_active());
+    *ok = ndone == ns;
+    return total;
+}
+
 }  // namespace
 
 extern "C" {
@@ -800,9 +1029,8 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
     auto T0 = std::chrono::steady_clock::now();
     const int64_t N = c->N;
     const int64_t reorth0 = c->gs_reorth;
-    // A batch is one block-diagonal system.  Each sample's equations are scaled by
-    // 1 / ||r_s(0)||, so that one FGMRES on the whole batch with the absolute tolerance
-    // lin_tol meets lin_tol * ||r_s(0)|| on every sample, and Newton stops when the
+    // A batch is one block-diagonal system: FGMRES runs one Arnoldi process per sample
+    // (fgmres_batch) to lin_tol * ||r_s(0)|| on every sample s, and Newton stops when the
     // largest relative residual max_s ||r_s|| / ||r_s(0)|| reaches newton_tol.
     const bool batch = !c->csamp.empty();
     const int ns = (int)c->samples.size();
@@ -818,20 +1046,22 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
     const double r0 = nrm2(c, c->d_r, N);
     S->r0_norm = r0;
     if (!(r0 > 0)) return fail(c, GPLMM_E_ARG, "the residual at the origin is zero (no driving force)");
+    std::vector<double> lin_tols(ns);
     if (batch) {
         seg_sumsq(c, c->d_r, r0s.data());
-        std::vector<double> sc(2 * ns);
         for (int s = 0; s < ns; ++s) {
             r0s[s] = std::sqrt(r0s[s]);
             if (!(r0s[s] > 0))
                 return fail(c, GPLMM_E_ARG, "sample " + std::to_string(s) + " has no driving force");
-            sc[s] = -1.0 / r0s[s];   // b = -D r
-            sc[ns + s] = r0s[s];     // d = D^-1 y
+            lin_tols[s] = c->opt.lin_tol * r0s[s];
         }
-        GP_HIP(c, hipMemcpy(c->d_sscale, sc.data(), sizeof(double) * 2 * ns, hipMemcpyHostToDevice));
         d_r2 = (double*)c->d_V;   // trial residuals of the line search (the Krylov basis is free then)
     }
-    const double lin_abs = batch ? c->opt.lin_tol : c->opt.lin_tol * r0;
+    const double lin_abs = c->opt.lin_tol * r0;
+    auto solve_step = [&](bool* ok) {
+        return batch ? fgmres_batch(c, x, c->d_r, c->d_dx, lin_tols.data(), c->opt.lin_maxit, ok)
+                     : fgmres(c, x, c->d_r, c->d_dx, lin_abs, c->opt.lin_maxit, ok);
+    };
     const int mode = c->opt.wind_mode;
     if (mode != GPLMM_WIND_CALLER || !c->built) {
         if (mode != GPLMM_WIND_CALLER) hipMemsetAsync(c->d_wind, 0, sizeof(double) * N, c->stream);
@@ -866,11 +1096,10 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
             S->learned_builds += c->last_coarse_learned ? 1 : 0;
             if (rc) return rc;
         }
-        if (batch) seg_scale(c, c->d_sscale, c->d_r);      // b = -D r
-        else scal_copy(c, -1.0, c->d_r, c->d_r, N);       // b = -r (fgmres leaves d_r alone)
+        scal_copy(c, -1.0, c->d_r, c->d_r, N);   // b = -r (fgmres leaves d_r alone)
         auto t1 = std::chrono::steady_clock::now();
         bool ok = false;
-        int its = fgmres(c, x, c->d_r, c->d_dx, lin_abs, c->opt.lin_maxit, &ok);
+        int its = solve_step(&ok);
         if (its < 0) return GPLMM_E_HIP;
         if (!ok && c->last_coarse_learned) {
             // the learned coarse operator did not carry FGMRES to the tolerance: rebuild with
@@ -884,9 +1113,8 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
             S->t_coarse_ms += c->last_coarse_ms;
             S->coarse_fallbacks++;
             if (rc) return rc;
-            its += fgmres(c, x, c->d_r, c->d_dx, lin_abs, c->opt.lin_maxit, &ok);
+            its += solve_step(&ok);
         }
-        if (batch) seg_scale(c, c->d_sscale + ns, c->d_dx);   // d = D^-1 y
         S->t_solve_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
         S->lin_its[k] = its;
         S->lin_its_total += its;
@@ -1036,10 +1264,11 @@ void gplmm_destroy(gplmm_ctx* c) {
                     c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class, c->d_local_off, c->d_sub_ids,
                     c->d_noclose, c->d_Aoasm, c->d_sub_order[0], c->d_sub_order[1], c->d_co_blk, c->d_co_loc,
                     c->d_cblk_n, c->d_cblk_idx, c->d_cblk_ioff, c->d_cblk_moff, c->d_csamp, c->d_sphys, c->d_seg,
-                    c->d_sscale, c->d_inv64};
+                    c->d_sscale, c->d_inv64, c->d_bres, c->d_bcoef, c->d_bsc, c->d_sub_samp, c->d_sact, c->d_alist};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (c->h_red) hipHostFree(c->h_red);
+    if (c->h_bres) hipHostFree(c->h_bres);
     delete c;
 }
 

@@ -182,6 +182,13 @@ struct gplmm_ctx {
     gp::Phys* d_sphys = nullptr;         // batch: per-sample physics
     int64_t* d_seg = nullptr;            // batch: slot offset of each sample (nsamples + 1)
     double* d_sscale = nullptr;          // batch: per-sample scale factors
+    double* d_bres = nullptr;            // batch Arnoldi: per-sample dot products / norms
+    double* h_bres = nullptr;            //   (pinned host mirror)
+    double* d_bcoef = nullptr;           //   per-sample projection / combination coefficients
+    double* d_bsc = nullptr;             //   per-sample (sj, 1/alpha)
+    int32_t* d_sub_samp = nullptr;       // batch: sample of each subdomain
+    uint8_t* d_sact = nullptr;           // batch: per-sample flag, 0 = skip its local solves
+    int32_t* d_alist = nullptr;          // batch: samples still iterating in FGMRES
     double* d_Ao = nullptr;              // coarse operator blocks, then their inverses
     double* d_Aowork = nullptr;
     double* d_Aoasm = nullptr;           // the assembled coarse operator (kept for inspection)
@@ -272,6 +279,11 @@ double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n);
 double nrm2(gplmm_ctx* c, const double* a, int64_t n);
 void seg_sumsq(gplmm_ctx* c, const double* a, double* out_host);   // per-sample sums of squares
 void seg_scale(gplmm_ctx* c, const double* scale_dev, double* a);   // a *= scale[sample] (in place)
+void seg_dots2(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* y, const int32_t* alist, int na,
+               double* a, double* b);
+void seg_update2(gplmm_ctx* c, double* V, int64_t ldv, int j, const double* coef_host, int ldc,
+                 const double* sc_host, const int32_t* alist, int na, double* w, double* nrm2);
+void seg_lincomb(gplmm_ctx* c, const double* Z, int64_t ldz, int k, const double* y_host, int ldy, double* x);
 void axpy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n);
 void scal_copy(gplmm_ctx* c, double alpha, const double* x, double* y, int64_t n);
 template <typename A, typename B>

@@ -213,6 +213,127 @@ __global__ void __launch_bounds__(kThreads) update2_kernel(const double* __restr
     if (threadIdx.x == 0) partial_nrm[blockIdx.x] = t;
 }
 
+// Batches: the same Arnoldi kernels per sample, over the samples still iterating
+// (alist): block (ch, y) strides over the slots [seg[s], seg[s+1]) of sample s = alist[y]
+// (nch blocks per sample), so every sample keeps its own dot products, coefficients and
+// norms.  partial[((y * 2k) + q) * nch + ch]: q < k dots with x = V[k-1], q >= k with y.
+__global__ void __launch_bounds__(kThreads) seg_multidot2_kernel(const double* __restrict__ V, int64_t ldv, int k,
+                                                                 const double* __restrict__ y,
+                                                                 const int64_t* __restrict__ seg,
+                                                                 const int32_t* __restrict__ alist,
+                                                                 double* __restrict__ partial) {
+    __shared__ double sh[kThreads / 64][2 * kGroup];
+    const int s = alist[blockIdx.y], nch = gridDim.x, ys = blockIdx.y;
+    const int64_t e = seg[s + 1];
+    const int64_t stride = (int64_t)nch * blockDim.x;
+    const int64_t r0 = seg[s] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double* x = V + (int64_t)(k - 1) * ldv;
+    for (int j0 = 0; j0 < k; j0 += kGroup) {
+        const int kk = min(kGroup, k - j0);
+        const double* Vg = V + (int64_t)j0 * ldv;
+        double ax[kGroup], ay[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) ax[q] = ay[q] = 0.0;
+        for (int64_t r = r0; r < e; r += stride) {
+            const double xr = x[r], yr = y[r];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q)
+                if (q < kk) {
+                    const double v = Vg[(int64_t)q * ldv + r];
+                    ax[q] += v * xr;
+                    ay[q] += v * yr;
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            double a = ax[q], b = ay[q];
+            for (int off = 32; off > 0; off >>= 1) {
+                a += __shfl_down(a, off, 64);
+                b += __shfl_down(b, off, 64);
+            }
+            if (lane == 0) {
+                sh[wv][q] = a;
+                sh[wv][kGroup + q] = b;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < 2 * kk) {
+            const int q = threadIdx.x < kk ? threadIdx.x : threadIdx.x - kk;
+            const int col = threadIdx.x < kk ? q : kGroup + q;
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < kThreads / 64; ++u) t += sh[u][col];
+            const int out = threadIdx.x < kk ? j0 + q : k + j0 + q;
+            partial[((int64_t)ys * 2 * k + out) * nch + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Per sample s = alist[y]: v_j <- (v_j - V[0..j) t_s) ainv_s, w <- w - V[0..j) s_s - v_j sj_s;
+// partial sums of the sample's new ||w||^2 at partial_nrm[y * nch + ch].  coef: per sample
+// 2 * ldc values (t, then s at + ldc); sc: per sample (sj, ainv).
+__global__ void __launch_bounds__(kThreads) seg_update2_kernel(const double* __restrict__ V, int64_t ldv, int j,
+                                                               const double* __restrict__ coef, int ldc,
+                                                               const double* __restrict__ sc,
+                                                               double* __restrict__ vj, double* __restrict__ w,
+                                                               const int64_t* __restrict__ seg,
+                                                               const int32_t* __restrict__ alist,
+                                                               double* __restrict__ partial_nrm) {
+    __shared__ double sh[16];
+    __shared__ double ts[kMaxRestart], ss[kMaxRestart];
+    const int s = alist[blockIdx.y], nch = gridDim.x, ys = blockIdx.y;
+    const double* cs = coef + (int64_t)s * 2 * ldc;
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        ts[i] = cs[i];
+        ss[i] = cs[ldc + i];
+    }
+    __syncthreads();
+    const double sj = sc[2 * s], ainv = sc[2 * s + 1];
+    const int64_t e = seg[s + 1];
+    const int64_t stride = (int64_t)nch * blockDim.x;
+    double acc = 0.0;
+    for (int64_t r = seg[s] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < e; r += stride) {
+        double av = 0.0, aw = 0.0;
+        int i = 0;
+        for (; i + kGroup <= j; i += kGroup) {
+            double t[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) t[q] = V[(int64_t)(i + q) * ldv + r];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                av += t[q] * ts[i + q];
+                aw += t[q] * ss[i + q];
+            }
+        }
+        for (; i < j; ++i) {
+            const double t = V[(int64_t)i * ldv + r];
+            av += t * ts[i];
+            aw += t * ss[i];
+        }
+        const double vn = (vj[r] - av) * ainv;
+        vj[r] = vn;
+        const double wn = w[r] - aw - vn * sj;
+        w[r] = wn;
+        acc += wn * wn;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial_nrm[(int64_t)ys * nch + blockIdx.x] = t;
+}
+
+// x += sum_j Z_j y[sample][j] with per-sample coefficients (ldy per sample)
+__global__ void seg_lincomb_kernel(const double* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ y,
+                                   int ldy, const int32_t* __restrict__ csamp, int nrec, double* __restrict__ x,
+                                   int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* ys = y + (int64_t)csamp[i / nrec] * ldy;
+    double s = x[i];
+    for (int j = 0; j < k; ++j) s += Z[(int64_t)j * ldz + i] * ys[j];
+    x[i] = s;
+}
+
 // x += sum_j Z_j y_j
 __global__ void lincomb_kernel(const double* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ y,
                                double* __restrict__ x, int64_t n) {
@@ -399,6 +520,64 @@ double update2(gplmm_ctx* c, double* V, int64_t ldv, int j, const double* t, con
     hipStreamSynchronize(c->stream);
     c->gs_reorth++;
     return c->h_red[2 * kRs];
+}
+
+
+// ---- batches: per-sample Arnoldi (see fgmres_batch), over the active samples alist[0..na)
+static int seg_chunks(int na, int rows_per_sample) {
+    const int64_t cap = kPart / ((int64_t)std::max(na, 1) * std::max(rows_per_sample, 1));
+    const int64_t want = (kMaxRedBlocks + na - 1) / std::max(na, 1);   // about kMaxRedBlocks blocks in all
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, cap));
+}
+
+static void push_alist(gplmm_ctx* c, const int32_t* alist, int na) {
+    hipMemcpyAsync(c->d_alist, alist, sizeof(int32_t) * na, hipMemcpyHostToDevice, c->stream);
+}
+
+// a[y * k + i] = V_i . V[k-1], b[y * k + i] = V_i . w on sample alist[y] (host arrays of na * k)
+void seg_dots2(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* y, const int32_t* alist, int na,
+               double* a, double* b) {
+    const int nch = seg_chunks(na, 2 * k);
+    push_alist(c, alist, na);
+    seg_multidot2_kernel<<<dim3(nch, na), kThreads, 0, c->stream>>>(V, ldv, k, y, c->d_seg, c->d_alist, partials(c));
+    reduce_kernel<<<na * 2 * k, kThreads, 0, c->stream>>>(partials(c), nch, c->d_bres);
+    hipMemcpyAsync(c->h_bres, c->d_bres, sizeof(double) * na * 2 * k, hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    for (int q = 0; q < na; ++q)
+        for (int i = 0; i < k; ++i) {
+            a[(int64_t)q * k + i] = c->h_bres[(int64_t)q * 2 * k + i];
+            b[(int64_t)q * k + i] = c->h_bres[(int64_t)q * 2 * k + k + i];
+        }
+    c->gs_passes++;
+}
+
+// per active sample s = alist[y]: v_j <- (v_j - V t_s) ainv_s, w <- w - V s_s - v_j sj_s;
+// nrm2[y] = new ||w_s||^2.  coef_host: ns x 2 x ldc (t then s) and sc_host: ns x 2 (sj, ainv),
+// both indexed by sample.
+void seg_update2(gplmm_ctx* c, double* V, int64_t ldv, int j, const double* coef_host, int ldc, const double* sc_host,
+                 const int32_t* alist, int na, double* w, double* nrm2) {
+    const int ns = (int)c->samples.size();
+    const int nch = seg_chunks(na, 1);
+    push_alist(c, alist, na);
+    if (j > 0) hipMemcpyAsync(c->d_bcoef, coef_host, sizeof(double) * ns * 2 * ldc, hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(c->d_bsc, sc_host, sizeof(double) * ns * 2, hipMemcpyHostToDevice, c->stream);
+    seg_update2_kernel<<<dim3(nch, na), kThreads, 0, c->stream>>>(V, ldv, j, c->d_bcoef, ldc, c->d_bsc,
+                                                                 V + (int64_t)j * ldv, w, c->d_seg, c->d_alist,
+                                                                 partials(c));
+    reduce_kernel<<<na, kThreads, 0, c->stream>>>(partials(c), nch, c->d_bres);
+    hipMemcpyAsync(c->h_bres, c->d_bres, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    for (int q = 0; q < na; ++q) nrm2[q] = c->h_bres[q];
+    c->gs_reorth++;
+}
+
+// x += Z[0..k) y_s on each sample's slots (y_host: ns x ldy)
+void seg_lincomb(gplmm_ctx* c, const double* Z, int64_t ldz, int k, const double* y_host, int ldy, double* x) {
+    const int ns = (int)c->samples.size();
+    hipMemcpyAsync(c->d_bcoef, y_host, sizeof(double) * ns * ldy, hipMemcpyHostToDevice, c->stream);
+    seg_lincomb_kernel<<<nb_for(c->N), kThreads, 0, c->stream>>>(Z, ldz, k, c->d_bcoef, ldy, c->d_csamp, c->nrec, x,
+                                                                c->N);
+    hipStreamSynchronize(c->stream);
 }
 
 }  // namespace gp

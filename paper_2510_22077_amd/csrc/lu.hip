@@ -32,7 +32,13 @@ struct Env {
     const int32_t* tlc;
     const int64_t* lrow;
     const int64_t* urow;
+    const int32_t* sub_samp;   // batch: sample of each subdomain (nullptr for one image)
+    const uint8_t* sact;       // batch: 0 for a sample whose Krylov process has finished
 };
+
+// A subdomain of a finished sample of a batch: its right-hand side is zero, so is its
+// solution; the block writes the zeros and leaves.
+__device__ __forceinline__ bool skip_solve(const Env& e, int s) { return e.sub_samp && !e.sact[e.sub_samp[s]]; }
 
 template <typename T>
 __device__ __forceinline__ T* tile_ptr(T* F, const Env& e, const Sub& sb, int I, int J) {
@@ -552,6 +558,10 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     const int nT = sb.nT;
     if (nT == 0) return;
     T* xo = out + off[s];
+    if (skip_solve(e, s)) {
+        for (int i = threadIdx.x; i < nT * kT; i += blockDim.x) xo[i] = (T)0;
+        return;
+    }
     T* x = kLds ? reinterpret_cast<T*>(dyn_lds) : xo;
     const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
     const int32_t* tfc = e.tfc + sb.env_off;
@@ -695,6 +705,10 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     const int nT = sb.nT;
     if (nT == 0) return;
     T* xo = out + off[s];
+    if (skip_solve(e, s)) {
+        for (int i = threadIdx.x; i < nT * kT; i += blockDim.x) xo[i] = (T)0;
+        return;
+    }
     T* x = reinterpret_cast<T*>(small_lds);
     const int tid = threadIdx.x, r = tid >> 3, q = tid & 7;
     const int el = r * kT + 4 * q;   // first of this thread's four elements in a tile
@@ -810,7 +824,9 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
 // ---------------------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------------------
-static Env make_env(gplmm_ctx* c) { return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_tlc, c->d_lrow, c->d_urow}; }
+static Env make_env(gplmm_ctx* c) {
+    return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_tlc, c->d_lrow, c->d_urow, c->d_sub_samp, c->d_sact};
+}
 
 template <typename T>
 int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure) {
