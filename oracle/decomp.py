@@ -29,10 +29,12 @@ paper asks only for a thinnest separating set, which it does not construct):
   The faces of such a group are marked ``free`` and keep their plain rows in
   the closure matrix (no column sums), which keeps it nonsingular;
 * an interface is degenerate when no primary cell touches it, or when every
-  primary touching it touches no other interface (a dead-end pocket that
-  reaches the rest of the void only through faces between interface cells,
-  which the coarse space leaves at zero, so its coarse pressure would be
-  undetermined); the lowest-id degenerate interface that shares a face with
+  face-connected piece of a primary touching it touches no other interface (a
+  dead-end pocket that reaches the rest of the void only through faces between
+  interface cells, which the coarse space leaves at zero, so its coarse pressure
+  would be undetermined; carving can cut a fragment off a pore, and a fragment
+  reached only through one interface is such a pocket even when the rest of its
+  pore touches other interfaces); the lowest-id degenerate interface that shares a face with
   another interface is merged into the one it shares the most faces with
   (lowest id on ties), until none is left; ids are then compacted keeping
   their order;
@@ -54,6 +56,8 @@ from dataclasses import dataclass
 from typing import List
 
 import numpy as np
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
 from scipy import ndimage as ndi
 
 from .mac import MacGrid
@@ -223,14 +227,22 @@ def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
     iface = np.full(nc, -1, dtype=np.int64)
     iface[is_if] = inv.ravel()
     # --- merge degenerate interfaces
+    # pieces of the primaries: face-connected components of the cells of one label left
+    # after carving (interface merges never change which cells are primary cells)
+    prim0 = iface < 0
+    q_idx = np.repeat(np.arange(nc), nbr.shape[1])
+    w_idx = nbr.ravel()
+    link = (w_idx >= 0) & prim0[q_idx] & prim0[np.maximum(w_idx, 0)] & (L[q_idx] == L[np.maximum(w_idx, 0)])
+    adj = sp.coo_matrix((np.ones(int(link.sum())), (q_idx[link], w_idx[link])), shape=(nc, nc))
+    _, piece = connected_components(adj, directed=False)
     while True:
         nif = upairs.shape[0]
         prim_cell = iface < 0
         a_if = iface[:, None].repeat(nbr.shape[1], 1)
         valid = (nbr >= 0) & (a_if >= 0)
         nb_prim = valid & prim_cell[np.maximum(nbr, 0)]
-        # (interface, label of the touching primary cell) pairs
-        ip = np.unique(np.stack([a_if[nb_prim], L[np.maximum(nbr, 0)][nb_prim]], 1), axis=0)
+        # (interface, primary piece of the touching primary cell) pairs
+        ip = np.unique(np.stack([a_if[nb_prim], piece[np.maximum(nbr, 0)][nb_prim]], 1), axis=0)
         # interfaces touched by each primary label
         lab_ifs = {}
         for j, l in ip:

@@ -143,14 +143,28 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
         if (is_if[q])
             c->iface[q] = (int32_t)(std::lower_bound(pairs.begin(), pairs.end(),
                                                      std::make_pair(minlow[q], L[q])) - pairs.begin());
-    // ---- degenerate interfaces: touched by no primary cell, or only by primaries that touch no
-    // other interface (a dead-end pocket seen by the rest of the void only through faces between
-    // interface cells, which the coarse space leaves at zero).  The lowest-id one that shares a
-    // face with another interface joins the interface it shares the most faces with.
+    // ---- degenerate interfaces: touched by no primary cell, or only by primary pieces that touch
+    // no other interface (a dead-end pocket seen by the rest of the void only through faces
+    // between interface cells, which the coarse space leaves at zero; a piece is a face-connected
+    // set of one label's primary cells, since carving can cut a fragment off a pore).  The
+    // lowest-id one that shares a face with another interface joins the interface it shares the
+    // most faces with.
+    std::vector<int64_t> piece(nc);
+    {
+        UF uf(nc);
+        for (int64_t q = 0; q < nc; ++q) {
+            if (is_if[q]) continue;
+            for (int e = 0; e < 2 * nd; ++e) {
+                int64_t w = c->nbr[q * 6 + e];
+                if (w >= 0 && !is_if[w] && L[w] == L[q]) uf.unite(q, w);
+            }
+        }
+        for (int64_t q = 0; q < nc; ++q) piece[q] = uf.find(q);
+    }
     for (;;) {
         int nif = (int)pairs.size();
-        std::vector<std::vector<int64_t>> if_labs(nif);                 // primary labels touching j
-        std::map<int64_t, std::vector<int32_t>> lab_ifs;                 // interfaces touched by a label
+        std::vector<std::vector<int64_t>> if_labs(nif);                 // primary pieces touching j
+        std::map<int64_t, std::vector<int32_t>> lab_ifs;                 // interfaces touched by a piece
         std::vector<uint8_t> shares(nif, 0);
         for (int64_t q = 0; q < nc; ++q) {
             int j = c->iface[q];
@@ -159,8 +173,8 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
                 int64_t w = c->nbr[q * 6 + e];
                 if (w < 0) continue;
                 if (c->iface[w] < 0) {
-                    if_labs[j].push_back(L[w]);
-                    lab_ifs[L[w]].push_back(j);
+                    if_labs[j].push_back(piece[w]);
+                    lab_ifs[piece[w]].push_back(j);
                 } else if (c->iface[w] != j) {
                     shares[j] = 1;
                 }

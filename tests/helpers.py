@@ -42,3 +42,15 @@ def rel(a, b):
 
 def workload(name, seed=0, re=None):
     return make_workload(name, seed, re=re)
+
+
+def fragment_pocket():
+    """The 12^3 fragment-pocket window (tests/golden/fragment_pocket.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fragment_pocket.txt")
+    head = [l for l in open(path) if l.startswith("#")]
+    shape = tuple(int(v) for v in head[1].split()[2:5])
+    body = tuple(float(v) for v in head[2].split()[2:5])
+    a = np.loadtxt(path, dtype=np.int64)
+    return dict(mask=a[:, 0].reshape(shape).astype(np.uint8), labels=a[:, 1].reshape(shape).astype(np.int32),
+                body=body, rho=1.0, mu=1.0)

@@ -294,3 +294,28 @@ def test_backward_euler_steps_parity(precision, tol):
         ep = rel(xg[p] - xg[p].mean(), xo[p] - xo[p].mean())
         _say("BE step", step, precision, "newton", st["newton_its"], st["lin_its"], "u err", eu, "p err", ep)
         assert eu <= tol and ep <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+def test_fragment_pocket_newton_parity(precision, tol):
+    """The 12^3 window with a pore fragment behind a one-cell interface (see the oracle
+    test of the dead-end merge): the coarse operator is regular and the solution matches
+    the oracle's."""
+    torch = _torch()
+    from paper_2510_22077_amd import Solver
+    from tests.helpers import fragment_pocket
+    w = fragment_pocket()
+    s = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"], precision=precision,
+               newton_tol=1e-13, lin_tol=1e-14)
+    g, ops, dc, ph = oracle_case(w["mask"], w["labels"], w["rho"], w["mu"], w["body"])
+    rec = record_index(g, s.maps()["cell_voxel"])
+    x, st = s.newton_solve()
+    assert st["converged"], st
+    xo, _ = newton.solve(ops, dc, ph, tol=1e-14, precond="exact")
+    xg = x.cpu().numpy()[rec]
+    u, p = slice(0, g.nu), g.p_slice
+    drive = w["rho"] * abs(w["body"][0]) * np.sqrt(g.nu)
+    eu = rel(xg[u], xo[u]) if np.linalg.norm(xo[u]) > 1e-8 * drive else np.linalg.norm(xg[u]) / drive
+    ep = rel(xg[p] - xg[p].mean(), xo[p] - xo[p].mean())
+    _say("fragment pocket", precision, st["lin_its"], "u err", eu, "p err", ep)
+    assert eu <= tol and ep <= tol

@@ -46,10 +46,14 @@ def _crop(n):
 
 @pytest.mark.parametrize("name,seed", [("disks2d_64", 0), ("disks2d_64", 3), ("disks2d_32", 1),
                                        ("spheres3d_24", 0), ("spheres3d_24", 2), ("spheres3d_48", 0),
-                                       ("crop", 48), ("crop", 64)])
+                                       ("crop", 48), ("crop", 64), ("fragment", 0)])
 def test_host_decomposition_bit_exact(name, seed):
     binding = _lib_or_skip()
-    w = _crop(seed) if name == "crop" else workload(name, seed)
+    if name == "fragment":
+        from tests.helpers import fragment_pocket
+        w = fragment_pocket()
+    else:
+        w = _crop(seed) if name == "crop" else workload(name, seed)
     s = binding.Solver(w["mask"], w["labels"], body=w["body"], host_only=True)
     g, ops, dc, ph = oracle_case(w["mask"], w["labels"], body=w["body"])
     info = s.info()

@@ -227,3 +227,19 @@ def test_slab_carving_puts_interfaces_on_the_higher_label_side():
     # touches label 1 across the periodic wrap (column 23)
     assert set(np.unique(np.nonzero(iface[0] >= 0)[1]).tolist()) == {6, 12, 18, 23}
     assert [tuple(p) for p in dc.pairs] == [(1, 2), (1, 4), (2, 3), (3, 4)]
+
+
+def test_fragment_pocket_interface_is_merged_and_coarse_operator_regular():
+    """Carving can cut a fragment off a pore; a one-cell interface whose only primary
+    neighbour is such a fragment is a dead-end pocket (reached otherwise only through
+    faces between interface cells, which the coarse space leaves at zero), so it is
+    merged, and Rhat X Phat (Section 3.2.2, Remark 1) is invertible.  Fixture: a 12^3
+    window of a seeded batch sample (tests/golden/make_fragment_fixture.py)."""
+    from tests.helpers import fragment_pocket, oracle_case
+    w = fragment_pocket()
+    g, ops, dc, ph = oracle_case(w["mask"], w["labels"], w["rho"], w["mu"], w["body"])
+    assert dc.Nc == 11 and dc.Np == 8
+    X = build_matrix(ops, ph, wind=None, tags=dc.tags)
+    M = G.build(X, dc, origin_rhs(ops, ph))
+    sv = np.linalg.svd(M.Ao, compute_uv=False)
+    assert sv[-1] / sv[0] > 1e-8
