@@ -246,6 +246,14 @@ int gplmm_precond_apply(gplmm_ctx* ctx, const double* v_dev, double* z_dev);
  * ||r|| <= newton_tol ||r(0)||, 1 when the iteration limit was reached. */
 int gplmm_newton_solve(gplmm_ctx* ctx, const double* x_prev_dev, double* x_dev, gplmm_stats* stats);
 
+/* Progress report of long solves: fn(user, k, its, rel) is called on the host after every
+ * FGMRES restart cycle of Newton step k (its = FGMRES iterations of the step so far,
+ * rel = -1) and after every Newton step (its = the step's FGMRES iterations, rel = the
+ * relative residual reached, max over the samples of a batch).  fn = NULL stops the
+ * reports.  The callback must not call back into the library. */
+typedef void (*gplmm_progress_fn)(void* user, int newton_it, int lin_its, double rel);
+int gplmm_set_progress(gplmm_ctx* ctx, gplmm_progress_fn fn, void* user);
+
 /* Record HIP events around the preconditioner application, the Jacobian
  * stencil and the Arnoldi step (on = 1) or stop recording (on = 0). */
 int gplmm_set_timing(gplmm_ctx* ctx, int on);

@@ -72,9 +72,11 @@ EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_setup_batch", "gplmm_b
            "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
            "gplmm_mlp_forward", "gplmm_mlp_grad", "gplmm_mlp_adam", "gplmm_mlp_train", "gplmm_mlp_last_error",
            "gplmm_mlp_destroy", "gplmm_set_coarse_model", "gplmm_coarse_entries",
-           "gplmm_autotune", "gplmm_set_tuning"]
+           "gplmm_autotune", "gplmm_set_tuning", "gplmm_set_progress"]
 
 _lib = None
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double)
 
 
 def load():
@@ -119,6 +121,8 @@ def load():
     lib.gplmm_precond_apply.restype = I
     lib.gplmm_newton_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
     lib.gplmm_newton_solve.restype = I
+    lib.gplmm_set_progress.argtypes = [P, PROGRESS_FN, P]
+    lib.gplmm_set_progress.restype = I
     lib.gplmm_set_timing.argtypes = [P, I]
     lib.gplmm_set_timing.restype = I
     lib.gplmm_kernel_time.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -390,6 +394,14 @@ class Solver:
         d = st.as_dict()
         d["rc"] = rc
         return x, d
+
+    def set_progress(self, fn=None):
+        """fn(newton_it, lin_its, rel) after every FGMRES cycle (rel = -1) and Newton step."""
+        if fn is None:
+            self._progress = None
+            return self._check(self.lib.gplmm_set_progress(self.ctx, PROGRESS_FN(), None), "set_progress")
+        self._progress = PROGRESS_FN(lambda user, k, its, rel: fn(k, its, rel))
+        return self._check(self.lib.gplmm_set_progress(self.ctx, self._progress, None), "set_progress")
 
     def set_timing(self, on=True):
         self.lib.gplmm_set_timing(self.ctx, 1 if on else 0)

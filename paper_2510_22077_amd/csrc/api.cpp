@@ -469,6 +469,7 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
             *ok = true;
             break;
         }
+        if (c->progress) c->progress(c->progress_user, c->progress_newton, total, -1.0);
         // restart from the true residual b - J d
         launch_jv(c, xk, d, c->d_tmp, c->stream);
         scal_copy(c, -1.0, c->d_tmp, V, N);
@@ -678,6 +679,7 @@ int fgmres_batch(gplmm_ctx* c, const double* xk, const double* b, double* d, con
         }
         if (kmax > 0) seg_lincomb(c, Z, N, kmax, y.data(), ld, d);
         if (ndone == ns) break;
+        if (c->progress) c->progress(c->progress_user, c->progress_newton, total, -1.0);
         // restart the unfinished samples from the true residual b - J d
         launch_jv(c, xk, d, c->d_tmp, c->stream);
         scal_copy(c, -1.0, c->d_tmp, V, N);
@@ -1099,6 +1101,7 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
         scal_copy(c, -1.0, c->d_r, c->d_r, N);   // b = -r (fgmres leaves d_r alone)
         auto t1 = std::chrono::steady_clock::now();
         bool ok = false;
+        c->progress_newton = k + 1;
         int its = solve_step(&ok);
         if (its < 0) return GPLMM_E_HIP;
         if (!ok && c->last_coarse_learned) {
@@ -1182,6 +1185,7 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
             S->step_length[k] = 1.0;
         }
         S->res_hist[k + 1] = rel;
+        if (c->progress) c->progress(c->progress_user, k + 1, its, rel);
     }
     if (rel <= c->opt.newton_tol) rcode = 0;
     S->converged = rcode == 0;
@@ -1208,6 +1212,13 @@ int gplmm_sample_residuals(gplmm_ctx* c, const double* x, const double* xprev, d
     norms(b);
     GP_HIP(c, hipGetLastError());
     for (int s = 0; s < ns; ++s) out[s] = a[s] > 0 ? b[s] / a[s] : b[s];
+    return GPLMM_OK;
+}
+
+int gplmm_set_progress(gplmm_ctx* c, gplmm_progress_fn fn, void* user) {
+    if (!c) return GPLMM_E_ARG;
+    c->progress = fn;
+    c->progress_user = user;
     return GPLMM_OK;
 }
 

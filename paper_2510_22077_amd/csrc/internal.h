@@ -243,6 +243,9 @@ struct gplmm_ctx {
     double apply_bytes = 0.0, jv_bytes = 0.0;
 
     std::map<std::string, gp::Timer> timers;
+    gplmm_progress_fn progress = nullptr;   // called after every Newton step and FGMRES cycle
+    void* progress_user = nullptr;
+    int progress_newton = 0;                // Newton step under way (for the FGMRES-cycle calls)
 };
 
 namespace gp {
