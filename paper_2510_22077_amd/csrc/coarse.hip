@@ -33,10 +33,17 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
     __shared__ double prow[kNB];
     __shared__ int pivot;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int m = n - k0;
-    for (int64_t x = tid; x < (int64_t)m * w; x += kPT) {
-        const int t = (int)(x / m), r = k0 + (int)(x % m);
-        P[(int64_t)t * n + r] = A[(int64_t)r * n + k0 + t];
+    // one row per thread: its w contiguous entries are read together (coalesced stores per
+    // column across the wave)
+    for (int r = k0 + tid; r < n; r += kPT) {
+        const double* a = A + (int64_t)r * n + k0;
+        double v[kNB];
+#pragma unroll
+        for (int t = 0; t < kNB; ++t)
+            if (t < w) v[t] = a[t];
+#pragma unroll
+        for (int t = 0; t < kNB; ++t)
+            if (t < w) P[(int64_t)t * n + r] = v[t];
     }
     __syncthreads();
     for (int j = 0; j < w; ++j) {
@@ -44,12 +51,20 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
         const double* pc = P + (int64_t)j * n;
         double best = -1.0;
         int bidx = n;
-        for (int r = col + tid; r < n; r += kPT) {
-            const double v = fabs(pc[r]);
-            if (v > best) {   // rows visited in increasing order: ties keep the lower index
-                best = v;
-                bidx = r;
+        // rows visited in increasing order: ties keep the lower index (four loads in flight)
+        for (int r0 = col + tid; r0 < n; r0 += 4 * kPT) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = r0 + u * kPT;
+                v[u] = r < n ? fabs(pc[r]) : -1.0;
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (v[u] > best) {
+                    best = v[u];
+                    bidx = r0 + u * kPT;
+                }
         }
         for (int off = 32; off > 0; off >>= 1) {
             const double ov = __shfl_down(best, off, 64);
@@ -97,9 +112,15 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
         }
         __syncthreads();
     }
-    for (int64_t x = tid; x < (int64_t)m * w; x += kPT) {
-        const int t = (int)(x / m), r = k0 + (int)(x % m);
-        A[(int64_t)r * n + k0 + t] = P[(int64_t)t * n + r];
+    for (int r = k0 + tid; r < n; r += kPT) {
+        double* a = A + (int64_t)r * n + k0;
+        double v[kNB];
+#pragma unroll
+        for (int t = 0; t < kNB; ++t)
+            if (t < w) v[t] = P[(int64_t)t * n + r];
+#pragma unroll
+        for (int t = 0; t < kNB; ++t)
+            if (t < w) a[t] = v[t];
     }
 }
 
@@ -271,6 +292,7 @@ static void invert_block(gplmm_ctx* c, double* A, double* X, int n) {
 int coarse_invert(gplmm_ctx* c) {
     hipStream_t s = c->stream;
     const int64_t ne = c->co_elems;
+    timer_begin(c, "coarse_inv");
     GP_HIP(c, hipMemcpyAsync(c->d_Aowork, c->d_Ao, sizeof(double) * ne, hipMemcpyDeviceToDevice, s));
     GP_HIP(c, hipMemcpyAsync(c->d_Aoasm, c->d_Ao, sizeof(double) * ne, hipMemcpyDeviceToDevice, s));
     GP_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
@@ -278,6 +300,7 @@ int coarse_invert(gplmm_ctx* c) {
         const int n = c->cblk_n[b];
         if (n > 0) invert_block(c, c->d_Aowork + c->cblk_moff[b], c->d_Ao + c->cblk_moff[b], n);
     }
+    timer_end(c, "coarse_inv", 0.0);
     int flag = 0;
     GP_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(c, hipStreamSynchronize(s));
