@@ -32,20 +32,19 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
     __shared__ int bi[kPT / 64];
     __shared__ double prow[kNB];
     __shared__ int pivot;
+    __shared__ double tile[kNB][kNB + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // one row per thread: its w contiguous entries are read together (coalesced stores per
-    // column across the wave)
-    for (int r = k0 + tid; r < n; r += kPT) {
-        const double* a = A + (int64_t)r * n + k0;
-        double v[kNB];
-#pragma unroll
-        for (int t = 0; t < kNB; ++t)
-            if (t < w) v[t] = a[t];
-#pragma unroll
-        for (int t = 0; t < kNB; ++t)
-            if (t < w) P[(int64_t)t * n + r] = v[t];
+    // 32 x 32 blocks transposed through LDS: row segments read and panel columns written
+    // with whole waves on contiguous addresses
+    const int ty = tid >> 5, tx = tid & 31;
+    for (int rb = k0; rb < n; rb += kNB) {
+        const int r = rb + ty;
+        tile[ty][tx] = (r < n && tx < w) ? A[(int64_t)r * n + k0 + tx] : 0.0;
+        __syncthreads();
+        const int rr = rb + tx;
+        if (rr < n && ty < w) P[(int64_t)ty * n + rr] = tile[tx][ty];
+        __syncthreads();
     }
-    __syncthreads();
     for (int j = 0; j < w; ++j) {
         const int col = k0 + j;
         const double* pc = P + (int64_t)j * n;
@@ -112,15 +111,14 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
         }
         __syncthreads();
     }
-    for (int r = k0 + tid; r < n; r += kPT) {
-        double* a = A + (int64_t)r * n + k0;
-        double v[kNB];
-#pragma unroll
-        for (int t = 0; t < kNB; ++t)
-            if (t < w) v[t] = P[(int64_t)t * n + r];
-#pragma unroll
-        for (int t = 0; t < kNB; ++t)
-            if (t < w) a[t] = v[t];
+    __syncthreads();
+    for (int rb = k0; rb < n; rb += kNB) {
+        const int rr = rb + tx;
+        tile[tx][ty] = (rr < n && ty < w) ? P[(int64_t)ty * n + rr] : 0.0;
+        __syncthreads();
+        const int r = rb + ty;
+        if (r < n && tx < w) A[(int64_t)r * n + k0 + tx] = tile[ty][tx];
+        __syncthreads();
     }
 }
 
