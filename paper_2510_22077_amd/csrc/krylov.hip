@@ -116,6 +116,42 @@ __global__ void scal_copy_kernel(double alpha, const double* __restrict__ x, dou
     if (i < n) y[i] = alpha * x[i];
 }
 
+// Wave-wide sums of the 16 values a[0..8), b[0..8) of every lane, written to out[0..16)
+// (a's sums first): a butterfly reduce-scatter (each exchange halves the values a lane
+// keeps: 8 + 4 + 2 + 1 lane exchanges, then two plain ones) instead of a separate
+// six-step tree per value.
+__device__ __forceinline__ void wave_sums16(const double (&a)[kGroup], const double (&b)[kGroup], int lane,
+                                            double* out) {
+    static_assert(kGroup == 8, "the reduce-scatter is written for 16 values");
+    double u8[8];
+    const bool h32 = lane & 32;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {   // keep b (upper) on lanes with bit 5 set, a otherwise
+        const double keep = h32 ? b[i] : a[i], send = h32 ? a[i] : b[i];
+        u8[i] = keep + __shfl_xor(send, 32, 64);
+    }
+    double u4[4];
+    const bool h16 = lane & 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = h16 ? u8[4 + i] : u8[i], send = h16 ? u8[i] : u8[4 + i];
+        u4[i] = keep + __shfl_xor(send, 16, 64);
+    }
+    double u2[2];
+    const bool h8 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = h8 ? u4[2 + i] : u4[i], send = h8 ? u4[i] : u4[2 + i];
+        u2[i] = keep + __shfl_xor(send, 8, 64);
+    }
+    const bool h4 = lane & 4;
+    double v = (h4 ? u2[1] : u2[0]) + __shfl_xor(h4 ? u2[0] : u2[1], 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    // value index held: 8 h32 + 4 h16 + 2 h8 + h4 (a: 0..7, b: 8..15)
+    if ((lane & 3) == 0) out[((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1)] = v;
+}
+
 // Delayed classical Gram-Schmidt (the reorthogonalisation of v_j is carried out in the
 // step that projects w, so each Arnoldi step reads the basis twice): partial sums of
 // V_i . x and V_i . y for i < k in one pass; partial[i * nblk + b] and
@@ -144,18 +180,7 @@ __global__ void __launch_bounds__(kThreads) multidot2_kernel(const double* __res
                     ay[q] += v * yr;
                 }
         }
-#pragma unroll
-        for (int q = 0; q < kGroup; ++q) {
-            double a = ax[q], b = ay[q];
-            for (int off = 32; off > 0; off >>= 1) {
-                a += __shfl_down(a, off, 64);
-                b += __shfl_down(b, off, 64);
-            }
-            if (lane == 0) {
-                sh[wv][q] = a;
-                sh[wv][kGroup + q] = b;
-            }
-        }
+        wave_sums16(ax, ay, lane, sh[wv]);
         __syncthreads();
         if ((int)threadIdx.x < 2 * kk) {
             const int q = threadIdx.x < kk ? threadIdx.x : threadIdx.x - kk;
@@ -245,18 +270,7 @@ __global__ void __launch_bounds__(kThreads) seg_multidot2_kernel(const double* _
                     ay[q] += v * yr;
                 }
         }
-#pragma unroll
-        for (int q = 0; q < kGroup; ++q) {
-            double a = ax[q], b = ay[q];
-            for (int off = 32; off > 0; off >>= 1) {
-                a += __shfl_down(a, off, 64);
-                b += __shfl_down(b, off, 64);
-            }
-            if (lane == 0) {
-                sh[wv][q] = a;
-                sh[wv][kGroup + q] = b;
-            }
-        }
+        wave_sums16(ax, ay, lane, sh[wv]);
         __syncthreads();
         if ((int)threadIdx.x < 2 * kk) {
             const int q = threadIdx.x < kk ? threadIdx.x : threadIdx.x - kk;
