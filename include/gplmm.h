@@ -276,7 +276,9 @@ void gplmm_destroy(gplmm_ctx* ctx);
 typedef struct {
     int red_blocks;          /* blocks of the Krylov dot-product / update kernels */
     int stencil_block;       /* threads per block of the stencil kernels */
-    int trsv_mode;           /* 0: subdomain solution kept in LDS during the solves, 1: in HBM */
+    int trsv_mode;           /* primary-grid solves: 0 subdomain solution kept in LDS, one element
+                                of each tile per thread; 1 solution in HBM; 2 in LDS, four groups
+                                of 256 threads on interleaved tiles, 16-byte loads */
     int from_cache;          /* 1 when read from the cache file instead of measured */
     double t_reduction_ms;   /* best measured Gram-Schmidt step (half a restart cycle of vectors) */
     double t_stencil_ms;     /* best measured X v + J v */
@@ -292,7 +294,7 @@ typedef struct {
 int gplmm_autotune(gplmm_ctx* ctx, const char* cache_path, gplmm_tuning* out);
 
 /* Set the launch parameters directly (red_blocks 64..2048, stencil_block 128/256/512,
- * trsv_mode 0/1; the timing fields are ignored).  Errors: GPLMM_E_ARG. */
+ * trsv_mode 0/1/2; the timing fields are ignored).  Errors: GPLMM_E_ARG. */
 int gplmm_set_tuning(gplmm_ctx* ctx, const gplmm_tuning* t);
 
 /* ---------------------------------------------------------------------------

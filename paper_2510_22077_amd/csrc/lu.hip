@@ -822,6 +822,157 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
 }
 
 // ---------------------------------------------------------------------------------------
+// The primary-grid substitutions with 16-byte loads: the 1024 threads form four groups
+// of 256; group g takes the tiles t = g, g + 4, ... of every tile row, and thread (r, q)
+// of a group owns the four elements (r, 4q .. 4q + 3) of each of its tiles, as in
+// trsv_small_kernel.  A row's sums are reduced over the 8 lanes of a row, then over the
+// four groups through LDS, and group 0 applies the diagonal block.  Same bytes as
+// trsv_sub_kernel with a quarter of the load instructions.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restrict__ F,
+                                                         const int32_t* __restrict__ order,
+                                                         const int32_t* __restrict__ slots,
+                                                         const T* __restrict__ vin, T* __restrict__ out,
+                                                         const int64_t* __restrict__ off) {
+    // tiles per group held per register buffer (FP32: rows of up to 32 tiles, FP64: 16)
+    constexpr int kPF = sizeof(T) == 4 ? 8 : 4;
+    extern __shared__ double2 quad_lds[];
+    __shared__ T part4[4][kT];
+    const int s = order[blockIdx.x];
+    const Sub sb = e.subs[s];
+    const int nT = sb.nT;
+    if (nT == 0) return;
+    T* xo = out + off[s];
+    if (skip_solve(e, s)) {
+        for (int i = threadIdx.x; i < nT * kT; i += blockDim.x) xo[i] = (T)0;
+        return;
+    }
+    T* x = reinterpret_cast<T*>(quad_lds);
+    const int tid = threadIdx.x, g = tid >> 8, r = (tid & 255) >> 3, q = tid & 7;
+    const int el = r * kT + 4 * q;
+    const int32_t* tfc = e.tfc + sb.env_off;
+    const int32_t* tlc = e.tlc + sb.env_off;
+    const int64_t* lrow = e.lrow + sb.env_off;
+    const int64_t* urow = e.urow + sb.env_off;
+    const int32_t* sl = slots + sb.slot_off;
+    const T* D = F + sb.diag_off + el;
+    const int len = nT * kT;
+    for (int i = tid; i < len; i += 1024) x[i] = i < sb.n ? vin[sl[i]] : (T)0;
+    Quad<T> bufA[kPF], bufB[kPF];
+    int nA = 0, nB = 0;
+    Quad<T> dA, dB;
+    // this group's tiles of a row of nt tiles: g, g + 4, ... (a count uniform over each wave)
+    auto mine = [&](int nt) { return nt > g ? min((nt - g + 3) >> 2, kPF) : 0; };
+    auto load = [&](Quad<T>(&buf)[kPF], const T* src, int n) {
+#pragma unroll
+        for (int u = 0; u < kPF; ++u)
+            if (u < n) buf[u] = ld4(src + (int64_t)(g + 4 * u) * kTT);
+    };
+    auto dot = [&](const Quad<T>(&buf)[kPF], const T* y, int n) {
+        T acc = 0;
+#pragma unroll
+        for (int u = 0; u < kPF; ++u) {
+            if (u >= n) break;
+            acc += dot4(buf[u], ld4(y + (g + 4 * u) * kT));
+        }
+        return acc;
+    };
+    auto tail = [&](const T* src, const T* y, int nt) {
+        T acc = 0;
+        for (int t = g + 4 * kPF; t < nt; t += 4) acc += dot4(ld4(src + (int64_t)t * kTT), ld4(y + t * kT));
+        return acc;
+    };
+    auto fetch_l = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
+        const int Ic = min(I, nT - 1);
+        nb = mine(Ic - tfc[Ic]);
+        load(buf, F + lrow[Ic] + el, nb);
+    };
+    auto fetch_u = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
+        const int Ic = max(I, 0);
+        nb = mine(tlc[Ic] - Ic);
+        load(buf, F + urow[Ic] + el, nb);
+    };
+    fetch_l(0, bufA, nA);
+    fetch_l(1, bufB, nB);
+    dA = ld4(D);
+    dB = ld4(D + (int64_t)min(1, nT - 1) * kTT);
+    __syncthreads();
+    // b_c - (the row sums of the four groups) for this thread's four columns; group 0 folds
+    // -b_r into its sum before the barrier, so nothing reads x[I kT ..] after it (group 0
+    // overwrites that row with the solution)
+    auto rhs4 = [&](int I) {
+        Quad<T> p;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int col = 4 * q + m;
+            p.v[m] = -(part4[0][col] + part4[1][col] + part4[2][col] + part4[3][col]);
+        }
+        return p;
+    };
+    // ---- forward: L y = b (inv(L_II) strictly lower, unit diagonal implied)
+    auto fwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
+        const int j0 = tfc[I], nt = I - j0;
+        const T* y = x + j0 * kT + 4 * q;
+        T acc = dot(buf, y, nb);
+        if (nt > 4 * kPF) acc += tail(F + lrow[I] + el, y, nt);
+        fetch_l(I + 2, buf, nb);
+        acc = sum8(acc);
+        if (q == 0) part4[g][r] = g == 0 ? acc - x[I * kT + r] : acc;
+        __syncthreads();
+        if (g == 0) {
+            const Quad<T> p4 = rhs4(I);
+            T v = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int col = 4 * q + m;
+                v += (col < r ? db.v[m] : (col == r ? (T)1 : (T)0)) * p4.v[m];
+            }
+            v = sum8(v);
+            if (q == 0) x[I * kT + r] = v;
+            db = ld4(D + (int64_t)min(I + 2, nT - 1) * kTT);
+        }
+        __syncthreads();
+    };
+    for (int I = 0; I < nT; I += 2) {
+        fwd_row(I, bufA, nA, dA);
+        if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
+    }
+    // ---- backward: U x = y (inv(U_II) on and above the diagonal)
+    auto bwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
+        const int nt = tlc[I] - I;
+        const T* y = x + (I + 1) * kT + 4 * q;
+        T acc = dot(buf, y, nb);
+        if (nt > 4 * kPF) acc += tail(F + urow[I] + el, y, nt);
+        fetch_u(I - 2, buf, nb);
+        acc = sum8(acc);
+        if (q == 0) part4[g][r] = g == 0 ? acc - x[I * kT + r] : acc;
+        __syncthreads();
+        if (g == 0) {
+            const Quad<T> p4 = rhs4(I);
+            T v = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v += (4 * q + m >= r ? db.v[m] : (T)0) * p4.v[m];
+            v = sum8(v);
+            if (q == 0) x[I * kT + r] = v;
+            db = ld4(D + (int64_t)max(I - 2, 0) * kTT);
+        }
+        __syncthreads();
+    };
+    if (g == 0) {
+        dA = ld4(D + (int64_t)(nT - 1) * kTT);
+        dB = ld4(D + (int64_t)max(nT - 2, 0) * kTT);
+    }
+    fetch_u(nT - 1, bufA, nA);
+    fetch_u(nT - 2, bufB, nB);
+    for (int I = nT - 1; I >= 0; I -= 2) {
+        bwd_row(I, bufA, nA, dA);
+        if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+    }
+    for (int i = tid; i < len; i += 1024) xo[i] = x[i];
+}
+
+// ---------------------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------------------
 static Env make_env(gplmm_ctx* c) {
@@ -884,6 +1035,9 @@ void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vi
     if (duals && lds_set <= kTrsvLdsMax)
         trsv_small_kernel<T><<<nsub, 256, lds_set, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
                                                                c->d_sub_slots, vin, out_local, c->d_local_off);
+    else if (lds <= kTrsvLdsMax && c->trsv_mode == 2)
+        trsv_quad_kernel<T><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
+                                                           c->d_sub_slots, vin, out_local, c->d_local_off);
     else if (lds <= kTrsvLdsMax && c->trsv_mode == 0)
         trsv_sub_kernel<T, true><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
                                                                 c->d_sub_slots, vin, out_local, c->d_local_off);

@@ -98,7 +98,7 @@ extern "C" int gplmm_autotune(gplmm_ctx* c, const char* cache_path, gplmm_tuning
             std::istringstream ls(line.substr(key.size()));
             int rb = 0, sb = 0, tm = 0;
             if (ls >> rb >> sb >> tm && rb >= 64 && rb <= 2048 && (sb == 128 || sb == 256 || sb == 512) &&
-                (tm == 0 || tm == 1)) {
+                tm >= 0 && tm <= 2) {
                 c->red_blocks = rb;
                 c->stencil_block = sb;
                 c->trsv_mode = tm;
@@ -144,7 +144,7 @@ extern "C" int gplmm_autotune(gplmm_ctx* c, const char* cache_path, gplmm_tuning
         if (c->built) {
             best = 1e300;
             int best_tm = 0;
-            for (int tm : {0, 1}) {
+            for (int tm : {0, 1, 2}) {
                 c->trsv_mode = tm;
                 const double ms = c->opt.precision == GPLMM_FP32 ? time_trsv<float>(c) : time_trsv<double>(c);
                 if (ms < best) {
@@ -173,7 +173,7 @@ extern "C" int gplmm_set_tuning(gplmm_ctx* c, const gplmm_tuning* t) {
     if (!c || !t) return GPLMM_E_ARG;
     if (t->red_blocks < 64 || t->red_blocks > 2048 ||
         (t->stencil_block != 128 && t->stencil_block != 256 && t->stencil_block != 512) ||
-        (t->trsv_mode != 0 && t->trsv_mode != 1))
+        t->trsv_mode < 0 || t->trsv_mode > 2)
         return gp::fail(c, GPLMM_E_ARG, "tuning values out of range");
     c->red_blocks = t->red_blocks;
     c->stencil_block = t->stencil_block;

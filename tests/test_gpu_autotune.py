@@ -31,12 +31,21 @@ def test_every_variant_gives_the_same_preconditioner(precision):
     s.build()
     v = s.residual(torch.randn(s.N, dtype=torch.float64, device="cuda"))
     ref = s.precond_apply(v).clone()
+    # variants 0 and 1 run the same arithmetic in the same order (bit-identical); variant 2
+    # sums each row's tiles in four interleaved groups, a different rounding order: its
+    # difference is bounded by a few units of rounding of the local solves' precision
+    tol = 1e-11 if precision == "fp64" else 1e-4
     for rb in (256, 2048):
         for sb in (128, 512):
-            for tm in (0, 1):
+            for tm in (0, 1, 2):
                 s.set_tuning(red_blocks=rb, stencil_block=sb, trsv_mode=tm)
                 z = s.precond_apply(v)
-                assert torch.equal(z, ref), (rb, sb, tm)
+                if tm < 2:
+                    assert torch.equal(z, ref), (rb, sb, tm)
+                else:
+                    d = float(torch.linalg.norm(z - ref) / torch.linalg.norm(ref))
+                    print("variant 2 rel diff", precision, d)
+                    assert d <= tol, (rb, sb, tm, d)
     s.close()
 
 
@@ -49,7 +58,7 @@ def test_autotune_choice_cache_and_solution(tmp_path):
     print("tuning", t)
     assert t["from_cache"] == 0
     assert t["red_blocks"] in (256, 512, 1024, 2048)
-    assert t["stencil_block"] in (128, 256, 512) and t["trsv_mode"] in (0, 1)
+    assert t["stencil_block"] in (128, 256, 512) and t["trsv_mode"] in (0, 1, 2)
     assert t["t_trsv_ms"] > 0 and t["t_reduction_ms"] > 0 and t["t_stencil_ms"] > 0
     assert os.path.getsize(cache) > 0
     x1, st1 = s.newton_solve()
