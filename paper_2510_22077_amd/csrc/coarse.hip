@@ -5,10 +5,11 @@
 // directly at every application, Section 8's complexity discussion).
 //
 // Blocked right-looking LU with panels of 32 columns: the panel is factorised by
-// one workgroup (pivot search, row interchange and rank-1 updates inside the
-// panel), the interchanges are applied to the other columns, the block row of U
-// is a unit-lower triangular solve, and the trailing matrix takes a rank-32 update
-// (a tiled FP64 product).  The inverse U^-1 L^-1 P is formed by the same two
+// one workgroup (pivot search, row interchange, rank-1 updates inside sub-panels of
+// 8 columns and a rank-8 update of the rest of the panel after each), the
+// interchanges are applied to the other columns, the block row of U is a
+// unit-lower triangular solve, and the trailing matrix takes a rank-32 update (a
+// tiled FP64 product).  The inverse U^-1 L^-1 P is formed by the same two
 // kernels: a forward sweep (triangular solve of a block row, rank-32 update of the
 // rows below) and a backward sweep with U.
 #include "internal.h"
@@ -19,6 +20,7 @@ namespace {
 
 constexpr int kNB = 32;        // panel width
 constexpr int kPT = 1024;      // panel workgroup
+constexpr int kS = 8;          // sub-panel width inside a panel
 constexpr int kGT = 64;        // update tile (kGT x kGT outputs, 256 threads, 4 x 4 each)
 
 // Factor columns [k0, k0 + w) of rows [k0, n) (row-major A, leading dimension n) through
@@ -33,6 +35,7 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
     __shared__ double prow[kNB];
     __shared__ int pivot;
     __shared__ double tile[kNB][kNB + 1];
+    __shared__ double Ub[kS][kNB];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // 32 x 32 blocks transposed through LDS: row segments read and panel columns written
     // with whole waves on contiguous addresses
@@ -45,71 +48,120 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
         if (rr < n && ty < w) P[(int64_t)ty * n + rr] = tile[tx][ty];
         __syncthreads();
     }
-    for (int j = 0; j < w; ++j) {
-        const int col = k0 + j;
-        const double* pc = P + (int64_t)j * n;
-        double best = -1.0;
-        int bidx = n;
-        // rows visited in increasing order: ties keep the lower index (four loads in flight)
-        for (int r0 = col + tid; r0 < n; r0 += 4 * kPT) {
-            double v[4];
+    // sub-panels of kS columns: the rank-1 updates of a pivot step touch only the columns
+    // of its sub-panel; then the sub-panel's rows of the remaining panel columns are
+    // finished by forward substitution (a block of U) and every row below takes one
+    // rank-kS update of those columns.  Each entry sees its updates in the same order as
+    // with whole-panel rank-1 updates, at a fraction of the passes over the panel.
+    for (int sb = 0; sb < w; sb += kS) {
+        const int se = min(sb + kS, w);   // sub-panel columns [sb, se)
+        for (int j = sb; j < se; ++j) {
+            const int col = k0 + j;
+            const double* pc = P + (int64_t)j * n;
+            double best = -1.0;
+            int bidx = n;
+            // rows visited in increasing order: ties keep the lower index (four loads in flight)
+            for (int r0 = col + tid; r0 < n; r0 += 4 * kPT) {
+                double v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int r = r0 + u * kPT;
-                v[u] = r < n ? fabs(pc[r]) : -1.0;
-            }
+                for (int u = 0; u < 4; ++u) {
+                    const int r = r0 + u * kPT;
+                    v[u] = r < n ? fabs(pc[r]) : -1.0;
+                }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (v[u] > best) {
-                    best = v[u];
-                    bidx = r0 + u * kPT;
-                }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_down(best, off, 64);
-            const int oi = __shfl_down(bidx, off, 64);
-            if (ov > best || (ov == best && oi < bidx)) {
-                best = ov;
-                bidx = oi;
+                for (int u = 0; u < 4; ++u)
+                    if (v[u] > best) {
+                        best = v[u];
+                        bidx = r0 + u * kPT;
+                    }
             }
-        }
-        if (lane == 0) {
-            bv[wv] = best;
-            bi[wv] = bidx;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double b = bv[0];
-            int p = bi[0];
-            for (int u = 1; u < kPT / 64; ++u)
-                if (bv[u] > b || (bv[u] == b && bi[u] < p)) {
-                    b = bv[u];
-                    p = bi[u];
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_down(best, off, 64);
+                const int oi = __shfl_down(bidx, off, 64);
+                if (ov > best || (ov == best && oi < bidx)) {
+                    best = ov;
+                    bidx = oi;
                 }
-            if (!(b > 0.0) || !isfinite(b) || p >= n) {
-                atomicOr(flag, 2);
-                p = col;
             }
-            pivot = p;
-            piv[col] = p;
+            if (lane == 0) {
+                bv[wv] = best;
+                bi[wv] = bidx;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double b = bv[0];
+                int p = bi[0];
+                for (int u = 1; u < kPT / 64; ++u)
+                    if (bv[u] > b || (bv[u] == b && bi[u] < p)) {
+                        b = bv[u];
+                        p = bi[u];
+                    }
+                if (!(b > 0.0) || !isfinite(b) || p >= n) {
+                    atomicOr(flag, 2);
+                    p = col;
+                }
+                pivot = p;
+                piv[col] = p;
+            }
+            __syncthreads();
+            const int p = pivot;
+            if (tid < w) {   // interchange across the whole panel; keep the pivot row
+                double* q = P + (int64_t)tid * n;
+                const double a = q[col], b = q[p];
+                q[col] = b;
+                q[p] = a;
+                prow[tid] = b;
+            }
+            __syncthreads();
+            const double d = prow[j];
+            for (int r = col + 1 + tid; r < n; r += kPT) {
+                const double l = P[(int64_t)j * n + r] / d;
+                P[(int64_t)j * n + r] = l;
+                for (int t = j + 1; t < se; ++t) P[(int64_t)t * n + r] -= l * prow[t];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const int p = pivot;
-        if (tid < w) {   // interchange inside the panel; keep the pivot row
-            double* q = P + (int64_t)tid * n;
-            const double a = q[col], b = q[p];
-            q[col] = b;
-            q[p] = a;
-            prow[tid] = b;
+        if (se < w) {
+            // U block: rows k0 + [sb, se) of columns [se, w) (unit-lower forward substitution)
+            if (tid < w - se) {
+                const int c = se + tid;
+                double u[kS];
+#pragma unroll
+                for (int i = 0; i < kS; ++i) {
+                    if (sb + i >= se) break;
+                    double v = P[(int64_t)c * n + k0 + sb + i];
+                    for (int t = 0; t < i; ++t) v -= P[(int64_t)(sb + t) * n + k0 + sb + i] * u[t];
+                    u[i] = v;
+                    P[(int64_t)c * n + k0 + sb + i] = v;
+                    Ub[i][c] = v;
+                }
+            }
+            __syncthreads();
+            // rank-(se - sb) update of rows k0 + se .. n - 1 in columns [se, w), eight at a time
+            const int ks = se - sb;
+            for (int r = k0 + se + tid; r < n; r += kPT) {
+                double l[kS];
+#pragma unroll
+                for (int t = 0; t < kS; ++t) l[t] = t < ks ? P[(int64_t)(sb + t) * n + r] : 0.0;
+#pragma unroll 1
+                for (int c0 = se; c0 < w; c0 += 8) {
+                    double v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (c0 + u < w) v[u] = P[(int64_t)(c0 + u) * n + r];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (c0 + u < w) {
+                            double acc = v[u];
+#pragma unroll
+                            for (int t = 0; t < kS; ++t)
+                                if (t < ks) acc -= l[t] * Ub[t][c0 + u];
+                            P[(int64_t)(c0 + u) * n + r] = acc;
+                        }
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const double d = prow[j];
-        for (int r = col + 1 + tid; r < n; r += kPT) {
-            const double l = P[(int64_t)j * n + r] / d;
-            P[(int64_t)j * n + r] = l;
-            for (int t = j + 1; t < w; ++t) P[(int64_t)t * n + r] -= l * prow[t];
-        }
-        __syncthreads();
     }
     __syncthreads();
     for (int rb = k0; rb < n; rb += kNB) {
