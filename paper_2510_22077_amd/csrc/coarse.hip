@@ -21,6 +21,7 @@ namespace {
 constexpr int kNB = 32;        // panel width
 constexpr int kPT = 1024;      // panel workgroup
 constexpr int kS = 8;          // sub-panel width inside a panel
+constexpr int kBig = 128;      // columns (rows) per rank-kBig trailing update
 constexpr int kGT = 64;        // update tile (kGT x kGT outputs, 256 threads, 4 x 4 each)
 
 // Factor columns [k0, k0 + w) of rows [k0, n) (row-major A, leading dimension n) through
@@ -230,7 +231,8 @@ __global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restric
         if (i < w) B[(int64_t)(k0 + i) * ldb + c] = x[i];
 }
 
-// C[r0 + i][c0 + j] -= sum_{t < w} L[r0 + i][kc + t] * B[kb + t][c0 + j], i < M, j < N.
+// C[r0 + i][c0 + j] -= sum_{t < w} L[r0 + i][kc + t] * B[kb + t][c0 + j], i < M, j < N
+// (any rank w: taken kNB columns at a time, C read and written once).
 // L has leading dimension n, B and C leading dimension ldb (C aliases B).  64 x 64 output
 // tiles, 256 threads, 4 x 4 outputs per thread; operand tiles staged in LDS.
 __global__ void __launch_bounds__(256) rank_update_kernel(const double* __restrict__ L, int n, int kc,
@@ -240,29 +242,34 @@ __global__ void __launch_bounds__(256) rank_update_kernel(const double* __restri
     __shared__ double Bb[kNB][kGT + 1];
     const int ti = blockIdx.y * kGT, tj = blockIdx.x * kGT;
     const int tid = threadIdx.x;
-    for (int x = tid; x < kGT * kNB; x += 256) {
-        const int i = x / kNB, t = x % kNB;
-        La[i][t] = (ti + i < M && t < w) ? L[(int64_t)(r0 + ti + i) * n + kc + t] : 0.0;
-    }
-    for (int x = tid; x < kNB * kGT; x += 256) {
-        const int t = x / kGT, j = x % kGT;
-        Bb[t][j] = (t < w && tj + j < N) ? B[(int64_t)(kb + t) * ldb + c0 + tj + j] : 0.0;
-    }
-    __syncthreads();
     const int ty = tid / 16, tx = tid % 16;
     double acc[4][4] = {};
-#pragma unroll 8
-    for (int t = 0; t < kNB; ++t) {
-        double a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = La[ty + 16 * u][t];
-            b[u] = Bb[t][tx + 16 * u];
+    // the rank w in chunks of kNB (operands through LDS), one read-modify-write of C
+    for (int t0 = 0; t0 < w; t0 += kNB) {
+        const int wc = min(kNB, w - t0);
+        __syncthreads();
+        for (int x = tid; x < kGT * kNB; x += 256) {
+            const int i = x / kNB, t = x % kNB;
+            La[i][t] = (ti + i < M && t < wc) ? L[(int64_t)(r0 + ti + i) * n + kc + t0 + t] : 0.0;
         }
+        for (int x = tid; x < kNB * kGT; x += 256) {
+            const int t = x / kGT, j = x % kGT;
+            Bb[t][j] = (t < wc && tj + j < N) ? B[(int64_t)(kb + t0 + t) * ldb + c0 + tj + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int t = 0; t < kNB; ++t) {
+            double a[4], b[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
+                a[u] = La[ty + 16 * u][t];
+                b[u] = Bb[t][tx + 16 * u];
+            }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -305,35 +312,66 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 // X receives the inverse.
 static void invert_block(gplmm_ctx* c, double* A, double* X, int n) {
     hipStream_t s = c->stream;
-    // LU with partial pivoting, panel by panel
-    for (int k0 = 0; k0 < n; k0 += kNB) {
-        const int w = std::min(kNB, n - k0);
-        panel_kernel<<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel);
-        swap_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, c->d_piv);
-        const int r = k0 + w, m = n - r;
-        if (m > 0) {
-            block_trsm_kernel<<<blocks(m, 256), 256, 0, s>>>(A, n, k0, w, A, n, r, n, 1);
-            rank_update_kernel<<<dim3(blocks(m, kGT), blocks(m, kGT)), 256, 0, s>>>(A, n, k0, A, n, k0, A, r, m,
-                                                                                   r, m, w);
+    // LU with partial pivoting in blocks of kBig columns: the panels of a block update
+    // only the block's own columns as they go; the block's rows of the columns to its
+    // right are then solved with the block's unit-lower factor, and the trailing matrix
+    // takes one rank-kBig update
+    for (int K0 = 0; K0 < n; K0 += kBig) {
+        const int K1 = std::min(K0 + kBig, n);
+        for (int k0 = K0; k0 < K1; k0 += kNB) {
+            const int w = std::min(kNB, K1 - k0);
+            panel_kernel<<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel);
+            swap_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, c->d_piv);
+            const int r = k0 + w;
+            if (r < K1) {
+                block_trsm_kernel<<<blocks(K1 - r, 256), 256, 0, s>>>(A, n, k0, w, A, n, r, K1, 1);
+                rank_update_kernel<<<dim3(blocks(K1 - r, kGT), blocks(n - r, kGT)), 256, 0, s>>>(
+                    A, n, k0, A, n, k0, A, r, n - r, r, K1 - r, w);
+            }
+        }
+        if (K1 < n) {
+            for (int k0 = K0; k0 < K1; k0 += kNB) {
+                const int w = std::min(kNB, K1 - k0);
+                block_trsm_kernel<<<blocks(n - K1, 256), 256, 0, s>>>(A, n, k0, w, A, n, K1, n, 1);
+                const int r = k0 + w;
+                if (r < K1)
+                    rank_update_kernel<<<dim3(blocks(n - K1, kGT), blocks(K1 - r, kGT)), 256, 0, s>>>(
+                        A, n, k0, A, n, k0, A, r, K1 - r, K1, n - K1, w);
+            }
+            rank_update_kernel<<<dim3(blocks(n - K1, kGT), blocks(n - K1, kGT)), 256, 0, s>>>(
+                A, n, K0, A, n, K0, A, K1, n - K1, K1, n - K1, K1 - K0);
         }
     }
-    // inverse: X = P I, then L^-1 (forward sweep), then U^-1 (backward sweep)
+    // inverse: X = P I, then L^-1 (forward sweep), then U^-1 (backward sweep), both in
+    // blocks of kBig rows with one rank-kBig update of the rows beyond each block
     perm_pos_kernel<<<blocks(n, 256), 256, 0, s>>>(c->d_piv, n, c->d_piv + n);
     perm_matrix_kernel<<<blocks((int64_t)n * n, 256), 256, 0, s>>>(c->d_piv + n, n, X);
-    for (int k0 = 0; k0 < n; k0 += kNB) {
-        const int w = std::min(kNB, n - k0);
-        block_trsm_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, X, n, 0, n, 1);
-        const int r = k0 + w, m = n - r;
-        if (m > 0)
-            rank_update_kernel<<<dim3(blocks(n, kGT), blocks(m, kGT)), 256, 0, s>>>(A, n, k0, X, n, k0, X, r, m, 0,
-                                                                                   n, w);
+    for (int K0 = 0; K0 < n; K0 += kBig) {
+        const int K1 = std::min(K0 + kBig, n);
+        for (int k0 = K0; k0 < K1; k0 += kNB) {
+            const int w = std::min(kNB, K1 - k0);
+            block_trsm_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, X, n, 0, n, 1);
+            const int r = k0 + w;
+            if (r < K1)
+                rank_update_kernel<<<dim3(blocks(n, kGT), blocks(K1 - r, kGT)), 256, 0, s>>>(A, n, k0, X, n, k0, X, r,
+                                                                                          K1 - r, 0, n, w);
+        }
+        if (K1 < n)
+            rank_update_kernel<<<dim3(blocks(n, kGT), blocks(n - K1, kGT)), 256, 0, s>>>(A, n, K0, X, n, K0, X, K1,
+                                                                                      n - K1, 0, n, K1 - K0);
     }
-    for (int k0 = ((n - 1) / kNB) * kNB; k0 >= 0; k0 -= kNB) {
-        const int w = std::min(kNB, n - k0);
-        block_trsm_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, X, n, 0, n, 0);
-        if (k0 > 0)
-            rank_update_kernel<<<dim3(blocks(n, kGT), blocks(k0, kGT)), 256, 0, s>>>(A, n, k0, X, n, k0, X, 0, k0,
-                                                                                    0, n, w);
+    for (int K0 = ((n - 1) / kBig) * kBig; K0 >= 0; K0 -= kBig) {
+        const int K1 = std::min(K0 + kBig, n);
+        for (int k0 = K0 + ((K1 - 1 - K0) / kNB) * kNB; k0 >= K0; k0 -= kNB) {
+            const int w = std::min(kNB, K1 - k0);
+            block_trsm_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, X, n, 0, n, 0);
+            if (k0 > K0)
+                rank_update_kernel<<<dim3(blocks(n, kGT), blocks(k0 - K0, kGT)), 256, 0, s>>>(A, n, k0, X, n, k0, X, K0,
+                                                                                           k0 - K0, 0, n, w);
+        }
+        if (K0 > 0)
+            rank_update_kernel<<<dim3(blocks(n, kGT), blocks(K0, kGT)), 256, 0, s>>>(A, n, K0, X, n, K0, X, 0, K0, 0,
+                                                                                  n, K1 - K0);
     }
 }
 
