@@ -99,8 +99,9 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this solver has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: this solver has no multi-GPU path (it would shard "
+              "by subdomain: whole pores per GPU, one halo exchange per stencil application)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
