@@ -65,11 +65,23 @@ __global__ void prolong_prim_kernel(const T* __restrict__ phi, const int64_t* __
     const int64_t c0 = pcol_off[i], c1 = pcol_off[i + 1];
     const T* ph = phi + phi_off[i] + r;
     double acc = 0.0;
-    for (int64_t k = c0; k < c1; ++k) {
-        const int32_t col = pcols[k];
-        if (col < 0) continue;
-        const double a = coef[col];
-        if (a != 0.0) acc += a * (double)ph[(k - c0) * ld];
+    // eight columns at a time: their indices, then their coefficients, then the shape
+    // vector entries of the nonzero ones are each issued together (three dependent
+    // loads per group instead of per column); the sum keeps the column order
+    for (int64_t k = c0; k < c1; k += 8) {
+        const int m = (int)min((int64_t)8, c1 - k);
+        int32_t cl[8];
+        double a[8];
+        T p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cl[u] = u < m ? pcols[k + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = cl[u] >= 0 ? coef[cl[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = a[u] != 0.0 ? ph[(k + u - c0) * ld] : (T)0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (a[u] != 0.0) acc += a[u] * (double)p[u];
     }
     z[slots[t]] = (O)acc;
 }
