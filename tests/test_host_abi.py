@@ -99,3 +99,19 @@ def test_setup_rejects_bad_labels_and_sizes():
         binding.Solver(w["mask"], lab, host_only=True)
     with pytest.raises(binding.GplmmError):
         binding.Solver(np.zeros((1, 8, 8), np.uint8), np.zeros((1, 8, 8), np.int32), host_only=True)
+
+
+def test_set_tuning_accepts_the_documented_range_only():
+    """gplmm_set_tuning: red_blocks 64..2048, stencil_block 128/256/512, trsv_mode 0..2;
+    anything else is GPLMM_E_ARG and leaves the context usable (host-only context)."""
+    binding = _lib_or_skip()
+    from paper_2510_22077_amd import Solver
+    w = workload("disks2d_32", 0)
+    s = Solver(w["mask"], w["labels"], body=w["body"], host_only=True)
+    for rb, sb, tm in [(64, 128, 0), (2048, 512, 1), (1024, 256, 2)]:
+        s.set_tuning(red_blocks=rb, stencil_block=sb, trsv_mode=tm)
+    for rb, sb, tm in [(32, 256, 0), (4096, 256, 0), (1024, 100, 0), (1024, 256, 3), (1024, 256, -1)]:
+        with pytest.raises(binding.GplmmError):
+            s.set_tuning(red_blocks=rb, stencil_block=sb, trsv_mode=tm)
+    s.set_tuning(red_blocks=512, stencil_block=128, trsv_mode=0)
+    s.close()
