@@ -173,46 +173,46 @@ __global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, 
     T* dp = F + sb.diag_off + (int64_t)K * kTT;
     for (int x = tid; x < kTT; x += blockDim.x) A[x / kT][x % kT] = (double)dp[x];
     __syncthreads();
+    // one barrier per elimination step: every thread forms the multipliers of its own
+    // rows (the same division), and the multipliers are kept in X until the end, since
+    // column k of A is still read during step k
     for (int k = 0; k < kT; ++k) {
         const double piv = A[k][k];
         if (tid == 0 && (!(piv == piv) || piv == 0.0 || fabs(piv) > 1e300)) atomicOr(flag, 1);
-        if (tid > k && tid < kT) A[tid][k] = A[tid][k] / piv;
-        __syncthreads();
         for (int x = tid; x < kTT; x += blockDim.x) {
-            int i = x / kT, j = x % kT;
-            if (i > k && j > k) A[i][j] -= A[i][k] * A[k][j];
+            const int i = x / kT, j = x % kT;
+            if (i > k && j >= k) {
+                const double l = A[i][k] / piv;
+                if (j == k) X[i][k] = l;
+                else A[i][j] -= l * A[k][j];
+            }
         }
         __syncthreads();
     }
-    // packed inverses by substitution, one column per thread (c: inv(L) e_c, 32 + c: inv(U) e_c)
+    for (int x = tid; x < kTT; x += blockDim.x) {
+        const int i = x / kT, j = x % kT;
+        if (i > j) A[i][j] = X[i][j];
+    }
+    __syncthreads();
+    // packed inverses by substitution, one column per thread (c: inv(L) e_c below the
+    // diagonal, 32 + c: inv(U) e_c on and above it), in column (axpy) form on the column's
+    // own entries of X, so that nothing is held in registers: at step k entry k is final
+    // and is subtracted, times column k of the factor, from the entries still open
     if (tid < 2 * kT) {
         const int c = tid & 31;
         if (tid < kT) {
-            double col[kT];
-#pragma unroll
-            for (int i = 0; i < kT; ++i) {
-                double v = i == c ? 1.0 : 0.0;
-#pragma unroll
-                for (int k = 0; k < i; ++k)
-                    if (k >= c) v -= A[i][k] * col[k];
-                col[i] = i < c ? 0.0 : v;
+            for (int i = c + 1; i < kT; ++i) X[i][c] = 0.0;
+            for (int k = c; k < kT - 1; ++k) {
+                const double xk = k == c ? 1.0 : X[k][c];
+                for (int i = k + 1; i < kT; ++i) X[i][c] -= A[i][k] * xk;
             }
-#pragma unroll
-            for (int i = 0; i < kT; ++i)
-                if (i > c) X[i][c] = col[i];
         } else {
-            double col[kT];
-#pragma unroll
-            for (int i = kT - 1; i >= 0; --i) {
-                double v = i == c ? 1.0 : 0.0;
-#pragma unroll
-                for (int k = i + 1; k < kT; ++k)
-                    if (k <= c) v -= A[i][k] * col[k];
-                col[i] = i > c ? 0.0 : v / A[i][i];
+            for (int i = 0; i <= c; ++i) X[i][c] = i == c ? 1.0 : 0.0;
+            for (int k = c; k >= 0; --k) {
+                const double xk = X[k][c] / A[k][k];
+                X[k][c] = xk;
+                for (int i = 0; i < k; ++i) X[i][c] -= A[i][k] * xk;
             }
-#pragma unroll
-            for (int i = 0; i < kT; ++i)
-                if (i <= c) X[i][c] = col[i];
         }
     }
     __syncthreads();
