@@ -15,7 +15,7 @@
  *   Section 4, gPLMM: A := J~_w, the Jacobian of the modified residual with
  *   the inertia linearised about a wind w and removed on faces near the
  *   contact interfaces;
- *   Section 7, right-preconditioned (flexible) GMRES with the tolerance
+ *   Section 8, right-preconditioned (flexible) GMRES with the tolerance
  *   measured against ||r(u = 0, p = 0)||.
  *
  * Conventions shared by every entry point
@@ -98,10 +98,12 @@ typedef struct {
     int host_only;           /* 1: build the decomposition and index maps on the host only
                                 (no device memory; compute calls return GPLMM_E_STATE) */
     void* stream;            /* hipStream_t, NULL = default stream */
-    int line_search;         /* 1 (default): backtracking on ||r||: the Newton update is
-                                lambda * delta with lambda = 1, 1/2, ... >= 1/64, the first
-                                lambda with ||r(x + lambda delta)|| <= (1 - 1e-4 lambda) ||r(x)||
-                                (the smallest if none); 0: full steps */
+    int line_search;         /* 0 (default): full Newton steps x + delta (Section 1); 1: backtracking
+                                on ||r||: the update is lambda * delta with lambda = 1, 1/2, ...
+                                >= 1/64, the first lambda with ||r(x + lambda delta)|| <=
+                                (1 - 1e-4 lambda) ||r(x)|| (the smallest if none).  Either way a
+                                step whose residual is not finite is refused: the solve returns
+                                GPLMM_E_BREAKDOWN with x at the last finite iterate */
     int use_graph;           /* 1 (default): the preconditioner application is captured once
                                 in a HIP graph and replayed (input and output staged through
                                 buffers owned by the context); 0: launched kernel by kernel.

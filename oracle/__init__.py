@@ -19,7 +19,7 @@ Navier-Stokes Equations in Complex Porous Microstructures":
                  (Section 3.1 two-level structure; Section 3.2.3).
 * ``literal`` -- the same preconditioner written with the paper's explicit
                  matrices W, Q, P, R and csum, dense, for tiny grids only.
-* ``krylov``  -- flexible GMRES with right preconditioning (Section 7
+* ``krylov``  -- flexible GMRES with right preconditioning (Section 8
                  stopping rule), plus textbook GMRES.
 * ``newton``  -- the Newton driver.
 * ``mlp``     -- FP64 reference of the coarse-coefficient MLP.

@@ -46,7 +46,7 @@ paper asks only for a thinnest separating set, which it does not construct):
   face neighbours through the void space (default 1 in 2D, 0 in 3D: a 3D
   interface sheet already covers a large share of the cells, and the default
   keeps the union of the dual grids near the 10-30% of the void space the
-  paper reports in its complexity discussion; wider dual grids overlap more,
+  paper reports in its complexity discussion (Section 9.3); wider dual grids overlap more,
   and the additive sum over overlapping duals then over-corrects: two
   dilations in 2D stall FGMRES on large disk packings);
 * the unknowns of a cell set: its cells plus every active face with at least

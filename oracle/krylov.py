@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper solves each Newton system with right-preconditioned GMRES and stops
-when ||A x - b|| / ||r(u=0, p=0)|| < 1e-9 (Section 7, first paragraph).  The
+when ||A x - b|| / ||r(u=0, p=0)|| < 1e-9 (Section 8, first paragraph).  The
 restart length is not given; FGMRES(m) with m = 30 is used here, with
 classical Gram-Schmidt applied twice and Givens rotations on the Hessenberg
 matrix (Saad's flexible variant: the preconditioned vectors z_j are kept, so

@@ -4,13 +4,13 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Paper, Section 1: x^{k+1} = x^k + delta^k with J^k delta^k = -r^k; each linear
 system solved by right-preconditioned Krylov iterations with the tolerance
-measured against ||r(u=0, p=0)|| (Section 7).  gPLMM is built from the
+measured against ||r(u=0, p=0)|| (Section 8).  gPLMM is built from the
 modified Jacobian J~_w once and reused for every Newton iteration (Section 4);
 with no nearby solution the Stokes velocity serves as the wind.
 
-Readings taken where the paper is silent: Newton steps globalised by
-backtracking on the residual norm (see ``solve``); stop when
-||r(x_k)|| <= tol * ||r(0)||; the first step uses w = 0 (the Stokes matrix); with ``wind="stokes"`` the preconditioner is rebuilt once with
+Readings taken where the paper is silent: full Newton steps (the update of
+Section 1), with backtracking on the residual norm as an option (see
+``solve``); stop when ||r(x_k)|| <= tol * ||r(0)||; the first step uses w = 0 (the Stokes matrix); with ``wind="stokes"`` the preconditioner is rebuilt once with
 w = the velocity after the first Newton step (the Stokes solution) and then
 kept.
 """
@@ -44,12 +44,13 @@ def build_precond(ops, dc, phys, wind):
 
 def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
           maxit=30, restart=30, lin_maxit=600, wind="stokes", wind_vec=None,
-          precond="gplmm", stats=None, line_search=True):
+          precond="gplmm", stats=None, line_search=False):
     """Newton-FGMRES with gPLMM.  ``precond``: "gplmm" or "exact" (spsolve).
 
-    ``line_search``: backtracking on ||r||, lambda = 1, 1/2, ... down to 1/64, the first
-    lambda with ||r(x + lambda d)|| <= (1 - 1e-4 lambda) ||r(x)|| (Armijo's sufficient
-    decrease), else the smallest; False takes full steps."""
+    ``line_search``: False (default) takes the full step x + d of Section 1; True
+    backtracks on ||r||, lambda = 1, 1/2, ... down to 1/64, the first lambda with
+    ||r(x + lambda d)|| <= (1 - 1e-4 lambda) ||r(x)|| (Armijo's sufficient decrease),
+    else the smallest."""
     g = ops.g
     st = stats if stats is not None else NewtonStats()
     steady0 = Phys(phys.rho, phys.mu, phys.body, phys.dt, phys.pin)

@@ -196,7 +196,7 @@ class Solver:
 
     def _prepare(self, nx, ny, nz, h=1.0, periodic=(1, 0, 0), precision="fp64", wind="stokes", tag_layers=1,
                  dual_dilations=-1, restart=30, newton_tol=1e-8, lin_tol=1e-9, newton_maxit=30, lin_maxit=600,
-                 host_only=False, stream=None, line_search=True, use_graph=True):
+                 host_only=False, stream=None, line_search=False, use_graph=True):
         lib = load()
         self.lib = lib
         self.ctx = ctypes.c_void_p()

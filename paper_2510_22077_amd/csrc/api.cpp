@@ -2,7 +2,7 @@
 //
 // Paper: Newton x^{k+1} = x^k + delta^k with J^k delta^k = -r^k (Section 1);
 // right-preconditioned GMRES stopped at ||A x - b|| / ||r(u=0,p=0)|| < tol
-// (Section 7), here in its flexible form so that an FP32 preconditioner can sit
+// (Section 8), here in its flexible form so that an FP32 preconditioner can sit
 // inside the FP64 outer iteration; gPLMM built once from J~_w and reused for all
 // Newton iterations, with the Stokes velocity as the fallback wind (Section 4).
 #include <algorithm>
@@ -404,6 +404,12 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
             const double sj = (bb[j] - tb) / alpha;
             const double wn2 = update2(c, V, N, j, a.data(), bb.data(), sj, 1.0 / alpha, w, N);
             timer_end(c, "arnoldi", 0.0);
+            if (!std::isfinite(wn2) || !std::isfinite(alpha) || !std::isfinite(sj)) {
+                // a non-finite preconditioner or Jacobian output: the step is a failure, and
+                // d keeps the finite update of the cycles before (zero in the first)
+                *ok = false;
+                return total;
+            }
             const double hn = std::sqrt(std::max(wn2, 0.0));
             if (j >= 1) {   // column j - 1 referred to the tentative v_j
                 for (int i = 0; i < j; ++i) Hx(i, j - 1) += bprev * a[i];
@@ -464,8 +470,13 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
             for (int l = i + 1; l < k; ++l) s -= Hx(i, l) * y[l];
             y[i] = s / Hx(i, i);
         }
+        for (int i = 0; i < k; ++i)
+            if (!std::isfinite(y[i])) {
+                *ok = false;
+                return total;
+            }
         if (k > 0) lincomb(c, Z, N, k, y.data(), d, N);
-        if (stop) {
+        if (stop && std::fabs(g[k]) <= tol_abs) {   // converged (the estimate met the tolerance)
             *ok = true;
             break;
         }
@@ -475,6 +486,7 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
         scal_copy(c, -1.0, c->d_tmp, V, N);
         axpy(c, 1.0, b, V, N);
         beta = nrm2(c, V, N);
+        if (!std::isfinite(beta)) return total;
         if (beta <= tol_abs) *ok = true;
     }
     return total;
@@ -596,6 +608,13 @@ int fgmres_batch(gplmm_ctx* c, const double* xk, const double* b, double* d, con
                 const double* as = a.data() + (size_t)yy * k;
                 const double* bs = bb.data() + (size_t)yy * k;
                 const double alpha = as[j];
+                if (!std::isfinite(nrm[yy]) || !std::isfinite(alpha) || !std::isfinite(sc[2 * s])) {
+                    // non-finite preconditioner or Jacobian output: the step fails
+                    std::fill(active.begin(), active.end(), 1);
+                    GP_TRY(push_active());
+                    *ok = false;
+                    return total;
+                }
                 const double hn = std::sqrt(std::max(nrm[yy], 0.0));
                 double* gs = g.data() + (size_t)s * (m + 1);
                 bool conv = false;
@@ -714,7 +733,7 @@ void gplmm_default_options(gplmm_options* o) {
     o->restart = 30;
     o->newton_tol = 1e-8;
     o->lin_tol = 1e-9;
-    o->line_search = 1;
+    o->line_search = 0;
     o->use_graph = 1;
     o->newton_maxit = 30;
     o->lin_maxit = 600;
@@ -1137,6 +1156,10 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
                 for (int s = 0; s < ns; ++s) {
                     if (acc[s]) continue;
                     const double rt = std::sqrt(rts[s]);
+                    if (last && !std::isfinite(rt))
+                        return fail(c, GPLMM_E_BREAKDOWN, "Newton step " + std::to_string(k + 1) + ": sample " +
+                                                              std::to_string(s) + " has a non-finite residual at "
+                                                              "every trial step");
                     if (rt <= (1.0 - 1e-4 * lam) * rns[s] || last) {
                         acc[s] = 1;
                         ++nacc;
@@ -1163,6 +1186,9 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
                 axpy(c, lam, c->d_dx, c->d_tmp, N);
                 launch_residual(c, c->d_tmp, xprev, c->d_r, c->stream);
                 const double rt = nrm2(c, c->d_r, N);
+                if (!std::isfinite(rt) && lam <= 1.0 / 64.0)
+                    return fail(c, GPLMM_E_BREAKDOWN, "Newton step " + std::to_string(k + 1) +
+                                                          ": non-finite residual at every trial step");
                 if (rt <= (1.0 - 1e-4 * lam) * rn || lam <= 1.0 / 64.0) {
                     GP_HIP(c, hipMemcpyAsync(x, c->d_tmp, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
                     rn = rt;
@@ -1173,9 +1199,16 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
             rel = rn / r0;
             S->step_length[k] = lam;
         } else {
-            axpy(c, 1.0, c->d_dx, x, N);
-            launch_residual(c, x, xprev, c->d_r, c->stream);
+            // full Newton step x + delta (the paper's update); the trial point is kept in d_tmp
+            // until its residual is known to be finite, so x never takes a non-finite step
+            GP_HIP(c, hipMemcpyAsync(c->d_tmp, x, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+            axpy(c, 1.0, c->d_dx, c->d_tmp, N);
+            launch_residual(c, c->d_tmp, xprev, c->d_r, c->stream);
             rn = nrm2(c, c->d_r, N);
+            if (!std::isfinite(rn))
+                return fail(c, GPLMM_E_BREAKDOWN, "Newton step " + std::to_string(k + 1) +
+                                                      ": non-finite residual; x keeps the last finite iterate");
+            GP_HIP(c, hipMemcpyAsync(x, c->d_tmp, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
             rel = rn / r0;
             if (batch) {
                 seg_sumsq(c, c->d_r, rns.data());

@@ -2,7 +2,7 @@
 // Section 3.2.2), of size Nc + Ny, factorised in FP64 with partial pivoting and
 // turned into an explicit inverse so that each application of M_G is one dense
 // GEMV (the coarse system is small and ill-conditioned; the paper solves it
-// directly at every application, Section 8's complexity discussion).
+// directly at every application, Section 9.3's complexity discussion).
 //
 // Blocked right-looking LU with panels of 32 columns: the panel is factorised by
 // one workgroup (pivot search, row interchange, rank-1 updates inside sub-panels of
