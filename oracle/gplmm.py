@@ -48,6 +48,8 @@ class GPLMM:
     lu_p: list
     lu_d: list
     Abar: list
+    t_mg: float = 0.0                 # seconds spent on M_G (closures, shape vectors, Ao)
+    t_ml: float = 0.0                 # seconds spent on the smoother's local factorisations
 
 
 def closure_matrix(X, S, cols_summed, exempt=None):
@@ -63,6 +65,8 @@ def closure_matrix(X, S, cols_summed, exempt=None):
 
 
 def build(X, dc: Decomp, bB):
+    import time
+    t0 = time.perf_counter()
     X = sp.csr_matrix(X)
     g = dc.g
     N = g.N
@@ -127,10 +131,12 @@ def build(X, dc: Decomp, bB):
                       shape=(nco, N))
     Ao = (R @ X @ P).toarray()
     Ao_lu = _dense_lu(Ao)
+    t1 = time.perf_counter()
     lu_p = [spla.splu(X[S][:, S].tocsc()) for S in dc.S]
     lu_d = [spla.splu(X[D][:, D].tocsc()) for D in dc.D]
+    t2 = time.perf_counter()
     return GPLMM(X=X, dc=dc, phi=phi, chi=chi, ycols=ycols, P=P, R=R, Ao=Ao, Ao_lu=Ao_lu,
-                 lu_p=lu_p, lu_d=lu_d, Abar=Abar)
+                 lu_p=lu_p, lu_d=lu_d, Abar=Abar, t_mg=t1 - t0, t_ml=t2 - t1)
 
 
 def _dense_lu(A):

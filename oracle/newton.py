@@ -31,15 +31,20 @@ class NewtonStats:
     lin_its: list = field(default_factory=list)
     res_hist: list = field(default_factory=list)
     step_length: list = field(default_factory=list)
-    t_mg: float = 0.0
-    t_sol: float = 0.0
+    t_mg: float = 0.0        # M_G builds: closures, shape/correction vectors, coarse operator
+    t_ml: float = 0.0        # smoother builds: LU of every primary and dual block
+    t_sol: float = 0.0       # Krylov solves (all Newton steps)
     converged: bool = False
 
 
 def build_precond(ops, dc, phys, wind):
+    t = time.perf_counter()
     X = build_matrix(ops, phys, wind=wind, tags=dc.tags)
     bB = origin_rhs(ops, phys)
-    return G.build(X, dc, bB)
+    t_asm = time.perf_counter() - t
+    M = G.build(X, dc, bB)
+    M.t_mg += t_asm            # assembling X counts with the M_G build
+    return M
 
 
 def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
@@ -61,10 +66,10 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
     x = np.zeros(g.N) if x0 is None else x0.copy()
     M = None
     if precond == "gplmm":
-        t = time.perf_counter()
         w = wind_vec if wind == "caller" else None
         M = build_precond(ops, dc, phys, w)
-        st.t_mg += time.perf_counter() - t
+        st.t_mg += M.t_mg
+        st.t_ml += M.t_ml
     r = residual(ops, x, phys, x_old=x_old)
     st.res_hist.append(np.linalg.norm(r) / r0n)
     for k in range(maxit):
@@ -72,9 +77,9 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
             st.converged = True
             break
         if k == 1 and precond == "gplmm" and wind == "stokes":
-            t = time.perf_counter()
             M = build_precond(ops, dc, phys, x)
-            st.t_mg += time.perf_counter() - t
+            st.t_mg += M.t_mg
+            st.t_ml += M.t_ml
         J = jacobian(ops, x, phys)
         t = time.perf_counter()
         if precond == "gplmm":
