@@ -248,6 +248,16 @@ int gplmm_precond_apply(gplmm_ctx* ctx, const double* v_dev, double* z_dev);
  * ||r|| <= newton_tol ||r(0)||, 1 when the iteration limit was reached. */
 int gplmm_newton_solve(gplmm_ctx* ctx, const double* x_prev_dev, double* x_dev, gplmm_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the norms of gplmm_sample_residuals,
+ * out_dev[s] = ||r_s(x)|| / ||r_s(0)|| (||r_s(x)|| when r_s(0) = 0), written to a
+ * caller-owned device array of nsamples doubles in stream order, with no allocation, no
+ * host copy and no synchronisation.  x_dev, x_prev_dev (NULL = 0): device vectors of N
+ * doubles.  The partial sums live in a static 1 MiB device array that every call on the
+ * same GPU shares (at most 65536 samples; a batch holds at most 1024): calls that overlap
+ * on one GPU race.  Errors: GPLMM_E_ARG, GPLMM_E_STATE (host-only context), GPLMM_E_HIP. */
+int gplmm_sample_residuals_noalloc(gplmm_ctx* ctx, const double* x_dev, const double* x_prev_dev, double* out_dev);
+
 /* Progress report of long solves: fn(user, k, its, rel) is called on the host after every
  * FGMRES restart cycle of Newton step k (its = FGMRES iterations of the step so far,
  * rel = -1) and after every Newton step (its = the step's FGMRES iterations, rel = the

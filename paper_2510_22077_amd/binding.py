@@ -72,7 +72,7 @@ EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_setup_batch", "gplmm_b
            "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
            "gplmm_mlp_forward", "gplmm_mlp_grad", "gplmm_mlp_adam", "gplmm_mlp_train", "gplmm_mlp_last_error",
            "gplmm_mlp_destroy", "gplmm_set_coarse_model", "gplmm_coarse_entries",
-           "gplmm_autotune", "gplmm_set_tuning", "gplmm_set_progress"]
+           "gplmm_autotune", "gplmm_set_tuning", "gplmm_set_progress", "gplmm_sample_residuals_noalloc"]
 
 _lib = None
 
@@ -262,6 +262,16 @@ class Solver:
         out = np.zeros(n)
         self._check(self.lib.gplmm_sample_residuals(self.ctx, _ptr(self._vec(x)), _ptr(self._vec(x_prev)),
                                                     out.ctypes.data), "sample_residuals")
+        return out
+
+    def sample_residuals_noalloc(self, x, out, x_prev=None):
+        """The same norms written to the caller's device FP64 tensor ``out`` (one entry per
+        sample) by the allocation-free entry point; no synchronisation."""
+        n = self.batch_info()["nsamples"]
+        if out.dtype != self.torch.float64 or not out.is_cuda or out.numel() < n or not out.is_contiguous():
+            raise ValueError("out must be a contiguous device float64 tensor of >= %d entries" % n)
+        self._check(self.lib.gplmm_sample_residuals_noalloc(self.ctx, _ptr(self._vec(x)), _ptr(self._vec(x_prev)),
+                                                            _ptr(out)), "sample_residuals_noalloc")
         return out
 
     # ---- housekeeping

@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libgplmm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GPLMM_ARCH", "gfx950")
 
-SOURCES = ["setup.cpp", "api.cpp", "coarse_learn.cpp", "stencil.hip", "krylov.hip", "lu.hip", "precond.hip", "coarse.hip", "mlp.hip", "tune.cpp"]
+SOURCES = ["setup.cpp", "api.cpp", "coarse_learn.cpp", "stencil.hip", "krylov.hip", "lu.hip", "precond.hip", "coarse.hip", "mlp.hip", "tune.cpp", "noalloc.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # packed FP32 instructions are kept out of every kernel

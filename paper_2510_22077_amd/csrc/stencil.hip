@@ -33,49 +33,10 @@ __global__ void __launch_bounds__(kBlock) residual_kernel(DevGeo g, Phys ph0, co
                                                           const double* __restrict__ xold, double* __restrict__ r) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
-    const Phys ph = cell_phys(g, ph0, c);
-    constexpr int nr = ND + 1;
-    const Nb<ND> nc = load_nb<ND>(g, c);
-    const double ih = 1.0 / g.h, vis = ph.mu * ih * ih;
+    double out[ND + 1];
+    residual_cell<ND>(g, ph0, x, xold, c, out);
 #pragma unroll
-    for (int a = 0; a < ND; ++a) {
-        double out = 0.0;
-        const int32_t L = nc.n[a][0];
-        if (L >= 0) {
-            const Nb<ND> nl = load_nb<ND>(g, L);
-            const FaceNb<ND> f = face_nb(nc, nl, a);
-            const double uF = x[nr * c + a];
-            double visc = 0.0;
-#pragma unroll
-            for (int d = 0; d < ND; ++d)
-#pragma unroll
-                for (int t = 0; t < 2; ++t) visc += uF - nb_value(f, d, t, x, nr, a, uF);
-            out = vis * visc + (x[nr * c + ND] - x[(int64_t)nr * L + ND]) * ih - ph.rho * ph.body[a];
-            if (ph.dt > 0.0) out += ph.rho * (uF - (xold ? xold[nr * c + a] : 0.0)) / ph.dt;
-            double conv = 0.0;
-#pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                const double ad = advecting(nc, nl, c, L, a, d, x, nr);
-                const double gm = nb_value(f, d, 0, x, nr, a, uF), gp_ = nb_value(f, d, 1, x, nr, a, uF);
-                conv += ad * (ad >= 0.0 ? (uF - gm) : (gp_ - uF)) * ih;
-            }
-            out += ph.rho * conv;
-        }
-        r[nr * c + a] = out;
-    }
-    double m;
-    if ((g.tag[c] & kPinBit)) {
-        m = x[nr * c + ND];
-    } else {
-        m = 0.0;
-#pragma unroll
-        for (int a = 0; a < ND; ++a) {
-            const double up = nc.n[a][1] >= 0 ? x[(int64_t)nr * nc.n[a][1] + a] : 0.0;
-            const double lo = nc.n[a][0] >= 0 ? x[nr * c + a] : 0.0;
-            m -= (up - lo) * ih;
-        }
-    }
-    r[nr * c + ND] = m;
+    for (int a = 0; a <= ND; ++a) r[(ND + 1) * c + a] = out[a];
 }
 
 // y = J(xk) v with the upwind branches frozen at xk.

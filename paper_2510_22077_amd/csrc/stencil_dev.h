@@ -131,4 +131,55 @@ __device__ __forceinline__ void x_face_coefs(const Phys& ph, double h, const Nb<
     co[0] = diag;
 }
 
+// Residual record of cell c (Section 1 momentum and mass equations on the MAC grid):
+// out[a] for the lower a-face (0 when inactive), out[ND] for the mass row (p = 0 at a
+// pinned cell).  Backward Euler against xold when dt > 0 (xold may be nullptr = 0).
+template <int ND>
+__device__ __forceinline__ void residual_cell(const DevGeo& g, const Phys& ph0, const double* __restrict__ x,
+                                              const double* __restrict__ xold, int64_t c, double* out) {
+    const Phys ph = cell_phys(g, ph0, c);
+    constexpr int nr = ND + 1;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const double ih = 1.0 / g.h, vis = ph.mu * ih * ih;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        double o = 0.0;
+        const int32_t L = nc.n[a][0];
+        if (L >= 0) {
+            const Nb<ND> nl = load_nb<ND>(g, L);
+            const FaceNb<ND> f = face_nb(nc, nl, a);
+            const double uF = x[nr * c + a];
+            double visc = 0.0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) visc += uF - nb_value(f, d, t, x, nr, a, uF);
+            o = vis * visc + (x[nr * c + ND] - x[(int64_t)nr * L + ND]) * ih - ph.rho * ph.body[a];
+            if (ph.dt > 0.0) o += ph.rho * (uF - (xold ? xold[nr * c + a] : 0.0)) / ph.dt;
+            double conv = 0.0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                const double ad = advecting(nc, nl, c, L, a, d, x, nr);
+                const double gm = nb_value(f, d, 0, x, nr, a, uF), gp_ = nb_value(f, d, 1, x, nr, a, uF);
+                conv += ad * (ad >= 0.0 ? (uF - gm) : (gp_ - uF)) * ih;
+            }
+            o += ph.rho * conv;
+        }
+        out[a] = o;
+    }
+    double m;
+    if ((g.tag[c] & kPinBit)) {
+        m = x[nr * c + ND];
+    } else {
+        m = 0.0;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            const double up = nc.n[a][1] >= 0 ? x[(int64_t)nr * nc.n[a][1] + a] : 0.0;
+            const double lo = nc.n[a][0] >= 0 ? x[nr * c + a] : 0.0;
+            m -= (up - lo) * ih;
+        }
+    }
+    out[ND] = m;
+}
+
 }  // namespace gp
