@@ -272,28 +272,32 @@ def _mass_blocks(ops, phys):
     return blocks
 
 
-def jacobian(ops, x, phys: Phys):
-    """Exact derivative of ``residual`` (full inertia, no tags) with each
-    upwind branch frozen at the state x."""
+def jacobian(ops, x, phys: Phys, tags=None):
+    """Exact derivative of ``residual`` with each upwind branch frozen at the
+    state x; ``tags`` (as in ``residual``) differentiates the residual whose
+    tagged faces carry no inertia (the modified residual of Section 4 with the
+    wind equal to the state itself, used by the coarse-scale solver)."""
     g = ops.g
     us, _ = _split(g, x)
     rho, mu, h = phys.rho, phys.mu, g.h
     blocks = _mass_blocks(ops, phys)
     for c in g.comps:
         nc = g.ncomp[c]
+        keep = sp.identity(nc) if tags is None else sp.diags((~tags[c]).astype(float))
         diag = -(mu / h ** 2) * ops.visc[c]
         if phys.dt is not None:
             diag = diag + (rho / phys.dt) * sp.identity(nc)
+        conv = sp.csr_matrix((nc, nc))
         for d in g.comps:
             a = advecting(ops, c, d, us)
             Du, fwd = _upwind(ops, c, d, a, us[c])
             Dm = _upwind_matrix(ops, c, d, fwd)
-            diag = diag + rho * (sp.diags(a) @ Dm)
+            conv = conv + sp.diags(a) @ Dm
             if d == c:
-                diag = diag + rho * sp.diags(Du)
+                conv = conv + sp.diags(Du)
             else:
-                blocks[c, d] = rho * (sp.diags(Du) @ ops.A[c, d])
-        blocks[c, c] = diag
+                blocks[c, d] = rho * (keep @ sp.diags(Du) @ ops.A[c, d])
+        blocks[c, c] = diag + rho * (keep @ conv)
         blocks[c, "p"] = ops.grad[c]
     return _assemble(g, blocks, phys.pin)
 
