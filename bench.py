@@ -20,13 +20,27 @@ METRIC = "time & iters to 1e-8 rel. residual, 128³ steady NS; precond-apply HBM
 HBM_PEAK_GBS = 8000.0
 
 
-def _cpu_baseline(workload, crop):
-    """The FP64 oracle, untuned, on a bounded sample: the full Newton-FGMRES-
-    gPLMM solve of a crop^3 corner of the same packing, one thread, scaled to
-    the full image by its number of unknowns (linear scaling, which favours
-    the CPU)."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor()
+
+
+def _cpu_baseline(workload, crop, its_full):
+    """The FP64 oracle, untuned, on a bounded sample: the full Newton-FGMRES-gPLMM solve
+    (restart 256, the bench's tolerances) of the crop^3 corner of the same packing on one
+    thread (SuperLU and the Python loops are single-threaded; BLAS is held to one thread),
+    extrapolated to the full image by the law
+        T = (T_MG + T_ML) * N_full / N_crop + (T_sol / its_crop) * (N_full / N_crop) * its_full,
+    i.e. build work linear in the unknowns and FGMRES time linear in the unknowns per
+    iteration, with its_full the FGMRES iterations the same algorithm needs on the full
+    image (measured by the plain FP64 GPU solve of this run)."""
     from threadpoolctl import threadpool_limits
-    import numpy as np
     from oracle.mac import MacGrid, Operators, Phys
     from oracle.decomp import decompose, largest_component
     from oracle import newton
@@ -39,15 +53,79 @@ def _cpu_baseline(workload, crop):
         ops = Operators(g)
         dc = decompose(g, lab)
         ph = Phys(workload["rho"], workload["mu"], workload["body"], None, dc.pin)
-        x, st = newton.solve(ops, dc, ph, tol=1e-8, lin_tol=1e-9)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        x, st = newton.solve(ops, dc, ph, tol=1e-8, lin_tol=1e-9, restart=256, lin_maxit=3000)
         el = time.perf_counter() - t0
     full = MacGrid(largest_component(workload["mask"]))
-    scale = full.N / g.N
-    return dict(value=el * scale, unit="s", cores=1, kind="oracle",
-                sample="full oracle solve (setup + Newton-FGMRES-gPLMM to 1e-8) of the %d^3 corner "
-                       "crop (N=%d, %d Newton / %d FGMRES its, %.1f s), scaled by N ratio %.1f to "
-                       "N=%d" % (crop, g.N, st.newton_its, sum(st.lin_its), el, scale, full.N),
-                converged=bool(st.converged))
+    ratio = full.N / g.N
+    its_crop = sum(st.lin_its)
+    est = (st.t_mg + st.t_ml) * ratio + (st.t_sol / max(its_crop, 1)) * ratio * its_full
+    return dict(value=est, unit="s", cores=1, kind="oracle", nproc=os.cpu_count(), cpu_model=_cpu_model(),
+                blas_threads=1,
+                sample="oracle Newton-FGMRES(256)-gPLMM to 1e-8 on the %d^3 corner crop (N=%d, %d Newton / %d "
+                       "FGMRES its, T_MG %.1f s, T_ML %.1f s, T_sol %.1f s, total %.1f s, setup %.1f s), "
+                       "extrapolated to N=%d with T = (T_MG+T_ML)*r + T_sol/its_crop*r*its_full, r = %.2f, "
+                       "its_full = %d" % (crop, g.N, st.newton_its, its_crop, st.t_mg, st.t_ml, st.t_sol, el,
+                                          t_setup, full.N, ratio, its_full),
+                crop_measured_s=el, t_mg_s=st.t_mg, t_ml_s=st.t_ml, t_sol_s=st.t_sol, newton_its=st.newton_its,
+                fgmres_its=list(st.lin_its), converged=bool(st.converged))
+
+
+def _oracle_full_record():
+    """The oracle's own full-size solve, recorded when the stored 128^3 solution was
+    written (tests/golden, another machine: the one stated): time until the Newton
+    residual first met 1e-8, and the run to 1e-12."""
+    import json as _json
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "spheres3d_128_s0_full.npz")
+    if not os.path.exists(path):
+        return None
+    meta = _json.loads(str(np.load(path, allow_pickle=False)["meta"]))
+    t8 = None
+    for r, t in zip(meta.get("res_hist", []), meta.get("t_hist", [])):
+        if r <= 1e-8:
+            t8 = t
+            break
+    return dict(s_to_1e8=t8, s_to_1e12=meta["wall_s"], newton_its=meta["newton_its"], fgmres_its=meta["fgmres_its"],
+                t_mg_s=meta["t_mg_s"], t_ml_s=meta["t_ml_s"], t_sol_s=meta["t_sol_s"], nproc=meta["nproc"],
+                cpu_model=meta["cpu_model"], blas=meta["blas"], restart=meta["restart"],
+                note="measured once by tests/golden/make_oracle_solutions.py (not on the GPU host)")
+
+
+def _paper_e2(solver, mask, xa, xt, nrec):
+    """E_2 of the paper's coarse-solver tests (root mean square over the fluid cells of
+    |xi_t - xi_a| / sup |xi_t|, percent) for xi = mean-free pressure and the velocity
+    magnitude at the cell centres (each component the mean of the cell's two faces)."""
+    import numpy as np
+    m = solver.maps()
+    cv = m["cell_voxel"]
+    nz, ny, nx = mask.shape
+    nd = nrec - 1
+    vox2cell = np.full(mask.size, -1, dtype=np.int64)
+    vox2cell[cv] = np.arange(cv.size)
+    k, j, i = np.unravel_index(cv, mask.shape)
+    up = []
+    for a, (kk, jj, ii) in enumerate([(k, j, (i + 1) % nx), (k, j + 1, i), (k + 1, j, i)][:nd]):
+        ok = (jj < ny) & (kk < nz)
+        c = np.full(cv.size, -1, dtype=np.int64)
+        c[ok] = vox2cell[(kk[ok] * ny + jj[ok]) * nx + ii[ok]]
+        up.append(c)
+
+    def fields(x):
+        X = x.reshape(-1, nrec)
+        sp2 = np.zeros(X.shape[0])
+        for a in range(nd):
+            upper = np.where(up[a] >= 0, X[np.maximum(up[a], 0), a], 0.0)
+            sp2 += (0.5 * (X[:, a] + upper)) ** 2
+        p = X[:, nd] - X[:, nd].mean()
+        return np.sqrt(sp2), p
+
+    sa, pa = fields(xa)
+    st_, pt = fields(xt)
+    e_u = 100.0 * float(np.sqrt(np.mean(((st_ - sa) / np.abs(st_).max()) ** 2)))
+    e_p = 100.0 * float(np.sqrt(np.mean(((pt - pa) / np.abs(pt).max()) ** 2)))
+    return e_p, e_u
 
 
 def _measured_traffic(workload, precision):
@@ -79,11 +157,15 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--restart", type=int, default=256)
-    ap.add_argument("--cpu-crop", type=int, default=32)
+    ap.add_argument("--cpu-crop", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true",
                     help="skip the comparison solve with the plain FP64 preconditioner")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-scale solver leg")
+    ap.add_argument("--coarse-increments", type=int, default=1)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the extra solve on the finer pore split (about 1.5k pores)")
     ap.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, five times (the reference "
                          "point for scaling hardware byte counters)")
@@ -165,7 +247,17 @@ def main():
     l = (nvox - mask.sum()) / aw
     re = w["rho"] * (ud / phi) * l / w["mu"]
 
-    kt = {k: s.kernel_time(k) for k in ("trsv_p", "trsv_d", "precond_apply", "jv", "arnoldi")}
+    kt = {k: s.kernel_time(k) for k in ("trsv_p", "trsv_d", "precond_apply", "jv", "arnoldi", "lu",
+                                         "build_closure_dual_lu", "build_shape", "build_primary_lu",
+                                         "build_coarse")}
+    for k, v in kt.items():
+        if k not in ("lu", "build_closure_dual_lu", "build_primary_lu") and v["avg_ms"] > 0 and v["bytes"] > 0:
+            v["GBps"] = v["bytes"] / (v["avg_ms"] * 1e-3) / 1e9
+    lu = kt["lu"]
+    lu_tflops = lu["bytes"] / (lu["avg_ms"] * 1e-3) / 1e12 if lu["avg_ms"] > 0 else 0.0
+    nb = stt["builds"]
+    ph = {k: kt[k]["avg_ms"] * kt[k]["samples"] / max(nb, 1) for k in
+          ("build_closure_dual_lu", "build_shape", "build_primary_lu", "build_coarse")}
     tr = kt["trsv_p"]   # trsv_sub_kernel: the primary grids' solves, the dominant launch
     achieved = tr["bytes"] / (tr["avg_ms"] * 1e-3) / 1e9 if tr["avg_ms"] > 0 else 0.0
     ap_ = kt["precond_apply"]
@@ -206,8 +298,36 @@ def main():
                      "avg_launch_ms": tr["avg_ms"], "algorithmic_bytes_per_launch": tr["bytes"],
                      "launches": tr["samples"]},
         "kernel_times": kt,
+        "lu_mfma": {"kernel": "lu_diag_kernel + lu_row_kernel (tile LU: FP32 panels and trailing updates on "
+                              "v_mfma_f32_32x32x2f32, FP64 diagonal tiles)" if args.precision == "fp32" else
+                              "lu_diag_kernel + lu_row_kernel (FP64)",
+                    "flops_per_schedule_avg": lu["bytes"], "avg_ms": lu["avg_ms"], "achieved_TFLOPs": lu_tflops,
+                    "peak_TFLOPs": 157.3 if args.precision == "fp32" else 78.6,
+                    "frac": lu_tflops / (157.3 if args.precision == "fp32" else 78.6),
+                    "lu_flops_per_build": info["lu_flops"]},
+        "time_split_ms_per_solve": {
+            "T_MG": ph["build_closure_dual_lu"] + ph["build_shape"] + ph["build_coarse"],
+            "T_ML": ph["build_primary_lu"],
+            "T_sol": stt["t_solve_ms"],
+            "note": "event-timed solve; T_MG = closure LU (shared launches with the dual LU) + shape vectors + "
+                    "coarse operator, T_ML = primary-block LU; the dual-block LU is inside T_MG",
+            "phases_ms": ph, "builds": nb},
     }
     out["autotune"] = tuning
+    # coarse-scale solver (Algorithm 1) on the same context: time, coarse Newton
+    # iterations, and the paper's E2 errors against the fine solution x just computed
+    if not args.no_coarse:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xc, stc = s.coarse_solve(increments=args.coarse_increments)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0
+        e_p, e_u = _paper_e2(s, w["mask"], xc.cpu().numpy(), x.cpu().numpy(), nrec)
+        out["coarse_solver"] = {"s": tc, "increments": stc["increments"], "coarse_newton_its": stc["newton_its"],
+                                "rc_rel": stc["rc_rel"], "converged": stc["converged"],
+                                "fine_rel_residual": stc["fine_rel_residual"], "t_build_ms": stc["t_build_ms"],
+                                "E2_p_percent": e_p, "E2_speed_percent": e_u,
+                                "speedup_vs_fine_solve": sec / tc}
     if not args.no_fp64_plain:
         log("plain FP64 preconditioner on the same workload ...")
         del s
@@ -223,9 +343,30 @@ def main():
                              "t_build_ms": st64["t_build_ms"],
                              "rel_diff_vs_fp32_solution": float(torch.linalg.norm(x64 - x) / torch.linalg.norm(x64))}
         del s64
+    if not args.no_variants:
+        from synth import make_workload as _mk
+        log("finer pore split (pores > 1000 voxels split) ...")
+        wv = _mk(args.workload, args.seed, max_size=1000)
+        sv = Solver(wv["mask"], wv["labels"], rho=wv["rho"], mu=wv["mu"], body=wv["body"],
+                    precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart)
+        if not args.no_autotune:
+            sv.build()
+            sv.autotune()
+        sv.newton_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xv_, stv = sv.newton_solve()
+        torch.cuda.synchronize()
+        out["variant_pores_split_1000"] = {"s": time.perf_counter() - t0, "pores": sv.info()["Np"],
+                                           "interfaces": sv.info()["Nc"], "newton_its": stv["newton_its"],
+                                           "fgmres_its_total": stv["lin_its_total"], "t_build_ms": stv["t_build_ms"]}
+        del sv
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a %d^3 crop) ..." % args.cpu_crop)
-        out["cpu_baseline"] = _cpu_baseline(w, args.cpu_crop)
+        its_full = out["fp64_plain"]["fgmres_its_total"] if "fp64_plain" in out else st["lin_its_total"]
+        out["cpu_baseline"] = _cpu_baseline(w, args.cpu_crop, its_full)
+        out["oracle_full_128_recorded"] = _oracle_full_record()
     print(json.dumps(out), flush=True)
 
 

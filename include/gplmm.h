@@ -120,6 +120,8 @@ typedef struct {
     int64_t local_unknowns;  /* sum of the local problem sizes (closure, primary, dual) */
     int64_t factor_bytes;    /* device bytes held by the local factors */
     int ncolors;             /* probing colours used to assemble the coarse operator */
+    double lu_flops;         /* flops of the local factorisations of one build: 2 T^3 per tile
+                                product of the closure, dual and primary LU schedules */
 } gplmm_layout;
 
 typedef struct {
@@ -258,6 +260,40 @@ int gplmm_newton_solve(gplmm_ctx* ctx, const double* x_prev_dev, double* x_dev, 
  * on one GPU race.  Errors: GPLMM_E_ARG, GPLMM_E_STATE (host-only context), GPLMM_E_HIP. */
 int gplmm_sample_residuals_noalloc(gplmm_ctx* ctx, const double* x_dev, const double* x_prev_dev, double* out_dev);
 
+/* Coarse-scale Navier-Stokes solver (Section 5, Algorithm 1): an approximate steady
+ * solution from Newton iterations on the coarse unknowns alone.  The body force is
+ * raised in `increments` equal steps to its full value (the paper raises the inlet
+ * pressure; the steps play the role of its Reynolds-number increments).  At each step
+ * Phat and Rhat are built from X = J~_w with w = the velocity of the previous step
+ * (zero at the first: the Stokes matrix), and Newton iterates
+ *   J_c delta_c = -r_c,  r_c = Rhat r~(x),  J_c = Rhat J~(x) Phat,  x <- x + Phat delta_c,
+ * r~ being the residual without inertia on tagged faces and J~ its Jacobian, until
+ * ||r_c|| < tol ||r_c^0|| (the paper's 1e-6).  x_dev (device, N doubles) receives the
+ * approximate solution (its input value is ignored: Algorithm 1 starts at rest).
+ * Single-image steady contexts with at least one tag layer and one coarse unknown.  The
+ * context's preconditioner is left unbuilt (the next solve or gplmm_build rebuilds it).
+ * Errors: GPLMM_E_ARG (batch, transient, tag_layers < 1, no coarse unknown, options),
+ * GPLMM_E_BREAKDOWN (singular local or coarse factorisation), GPLMM_E_HIP.  Returns 1
+ * when a step missed the tolerance within newton_maxit iterations. */
+typedef struct {
+    int increments;          /* body-force steps (default 1, at most 64) */
+    int newton_maxit;        /* coarse Newton iterations per step (default 50) */
+    double tol;              /* ||r_c|| < tol ||r_c^0|| ends a step (default 1e-6) */
+} gplmm_coarse_options;
+
+typedef struct {
+    int increments;
+    int newton_its[64];      /* coarse Newton iterations of each step */
+    double rc_rel[64];       /* ||r_c|| / ||r_c^0|| reached at each step */
+    double fine_rel_residual;/* ||r(x)|| / ||r(0)|| of the returned state (the true residual) */
+    double t_build_ms;       /* preconditioner builds (one per step) */
+    double t_total_ms;
+    int converged;
+} gplmm_coarse_stats;
+
+void gplmm_coarse_default_options(gplmm_coarse_options* opt);
+int gplmm_coarse_solve(gplmm_ctx* ctx, const gplmm_coarse_options* opt, double* x_dev, gplmm_coarse_stats* stats);
+
 /* Progress report of long solves: fn(user, k, its, rel) is called on the host after every
  * FGMRES restart cycle of Newton step k (its = FGMRES iterations of the step so far,
  * rel = -1) and after every Newton step (its = the step's FGMRES iterations, rel = the
@@ -270,11 +306,14 @@ int gplmm_set_progress(gplmm_ctx* ctx, gplmm_progress_fn fn, void* user);
  * stencil and the Arnoldi step (on = 1) or stop recording (on = 0). */
 int gplmm_set_timing(gplmm_ctx* ctx, int on);
 
-/* Average device time (ms) and average algorithmic bytes of the timed
- * launches of a named kernel group since the last reset, recorded with HIP
- * events on the context's stream (see gplmm_set_timing); used for roofline
- * reporting.  name: "precond_apply", "trsv", "jv", "arnoldi".  Returns the
- * number of samples. */
+/* Average device time (ms) and average algorithmic bytes (flops for "lu") of
+ * the timed launches of a named kernel group since the last reset, recorded
+ * with HIP events on the context's stream (see gplmm_set_timing); used for
+ * roofline reporting.  name: "precond_apply", "trsv" (all local solves),
+ * "trsv_p" (primary grids), "trsv_d" (dual grids), "jv", "arnoldi" (one
+ * Gram-Schmidt step), "lu" (one factorisation schedule), and the build phases
+ * "build_closure_dual_lu", "build_shape", "build_primary_lu", "build_coarse".
+ * Returns the number of samples. */
 int gplmm_kernel_time(gplmm_ctx* ctx, const char* name, double* avg_ms, double* bytes);
 
 /* Reset the kernel timers. */

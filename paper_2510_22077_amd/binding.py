@@ -40,7 +40,23 @@ class Layout(ctypes.Structure):
                 ("N", ctypes.c_int64), ("nface_active", ctypes.c_int64), ("Np", ctypes.c_int),
                 ("Nc", ctypes.c_int), ("Ny", ctypes.c_int), ("pin", ctypes.c_int64),
                 ("ndual_cells", ctypes.c_int64), ("local_unknowns", ctypes.c_int64),
-                ("factor_bytes", ctypes.c_int64), ("ncolors", ctypes.c_int)]
+                ("factor_bytes", ctypes.c_int64), ("ncolors", ctypes.c_int), ("lu_flops", ctypes.c_double)]
+
+
+class CoarseOptions(ctypes.Structure):
+    _fields_ = [("increments", ctypes.c_int), ("newton_maxit", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class CoarseStats(ctypes.Structure):
+    _fields_ = [("increments", ctypes.c_int), ("newton_its", ctypes.c_int * 64), ("rc_rel", ctypes.c_double * 64),
+                ("fine_rel_residual", ctypes.c_double), ("t_build_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double), ("converged", ctypes.c_int)]
+
+    def as_dict(self):
+        n = self.increments
+        return dict(increments=n, newton_its=[self.newton_its[k] for k in range(n)],
+                    rc_rel=[self.rc_rel[k] for k in range(n)], fine_rel_residual=self.fine_rel_residual,
+                    t_build_ms=self.t_build_ms, t_total_ms=self.t_total_ms, converged=bool(self.converged))
 
 
 class Stats(ctypes.Structure):
@@ -72,7 +88,8 @@ EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_setup_batch", "gplmm_b
            "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
            "gplmm_mlp_forward", "gplmm_mlp_grad", "gplmm_mlp_adam", "gplmm_mlp_train", "gplmm_mlp_last_error",
            "gplmm_mlp_destroy", "gplmm_set_coarse_model", "gplmm_coarse_entries",
-           "gplmm_autotune", "gplmm_set_tuning", "gplmm_set_progress", "gplmm_sample_residuals_noalloc"]
+           "gplmm_autotune", "gplmm_set_tuning", "gplmm_set_progress", "gplmm_sample_residuals_noalloc",
+           "gplmm_coarse_default_options", "gplmm_coarse_solve"]
 
 _lib = None
 
@@ -100,6 +117,12 @@ def load():
     lib.gplmm_batch_info.restype = I
     lib.gplmm_sample_residuals.argtypes = [P, P, P, P]
     lib.gplmm_sample_residuals.restype = I
+    lib.gplmm_sample_residuals_noalloc.argtypes = [P, P, P, P]
+    lib.gplmm_sample_residuals_noalloc.restype = I
+    lib.gplmm_coarse_default_options.argtypes = [ctypes.POINTER(CoarseOptions)]
+    lib.gplmm_coarse_default_options.restype = V
+    lib.gplmm_coarse_solve.argtypes = [P, ctypes.POINTER(CoarseOptions), P, ctypes.POINTER(CoarseStats)]
+    lib.gplmm_coarse_solve.restype = I
     lib.gplmm_layout_info.argtypes = [P, ctypes.POINTER(Layout)]
     lib.gplmm_layout_info.restype = I
     lib.gplmm_get_maps.argtypes = [P, P, P, P, P, P]
@@ -404,6 +427,18 @@ class Solver:
         d = st.as_dict()
         d["rc"] = rc
         return x, d
+
+    def coarse_solve(self, increments=1, newton_maxit=50, tol=1e-6):
+        """Coarse-scale solver (gplmm_coarse_solve): returns (x, stats)."""
+        o = CoarseOptions()
+        self.lib.gplmm_coarse_default_options(ctypes.byref(o))
+        o.increments, o.newton_maxit, o.tol = int(increments), int(newton_maxit), float(tol)
+        x = self.zeros()
+        st = CoarseStats()
+        rc = self.lib.gplmm_coarse_solve(self.ctx, ctypes.byref(o), _ptr(x), ctypes.byref(st))
+        if rc < 0:
+            self._check(rc, "coarse_solve")
+        return x, st.as_dict()
 
     def set_progress(self, fn=None):
         """fn(newton_it, lin_its, rel) after every FGMRES cycle (rel = -1) and Newton step."""

@@ -403,7 +403,9 @@ int fgmres(gplmm_ctx* c, const double* xk, const double* b, double* d, double to
             const double alpha = std::sqrt(std::max(a[j] - tt, 1e-300));
             const double sj = (bb[j] - tb) / alpha;
             const double wn2 = update2(c, V, N, j, a.data(), bb.data(), sj, 1.0 / alpha, w, N);
-            timer_end(c, "arnoldi", 0.0);
+            // algorithmic bytes of the step: the dots read V[0..j] and w (j + 2 vectors), the
+            // update reads V[0..j) and reads and writes v_j and w (j + 4 vectors)
+            timer_end(c, "arnoldi", 8.0 * (double)N * (double)(2 * j + 6));
             if (!std::isfinite(wn2) || !std::isfinite(alpha) || !std::isfinite(sj)) {
                 // a non-finite preconditioner or Jacobian output: the step is a failure, and
                 // d keeps the finite update of the cycles before (zero in the first)
@@ -903,6 +905,7 @@ int gplmm_layout_info(const gplmm_ctx* c, gplmm_layout* o) {
     o->local_unknowns = lu;
     o->factor_bytes = (int64_t)(c->opt.precision == GPLMM_FP32 ? 4 : 8) * c->factor_elems;
     o->ncolors = c->ncolors;
+    o->lu_flops = c->lu_flops[0] + c->lu_flops[1];
     return GPLMM_OK;
 }
 
@@ -1227,6 +1230,97 @@ int gplmm_newton_solve(gplmm_ctx* c, const double* xprev, double* x, gplmm_stats
     GP_HIP(c, hipGetLastError());
     S->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
     return rcode;
+}
+
+void gplmm_coarse_default_options(gplmm_coarse_options* o) {
+    if (!o) return;
+    o->increments = 1;
+    o->newton_maxit = 50;
+    o->tol = 1e-6;
+}
+
+int gplmm_coarse_solve(gplmm_ctx* c, const gplmm_coarse_options* opt, double* x, gplmm_coarse_stats* st) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!x || !opt) return GPLMM_E_ARG;
+    if (!c->csamp.empty()) return fail(c, GPLMM_E_ARG, "the coarse-scale solver takes a single image");
+    if (c->phys.dt > 0.0) return fail(c, GPLMM_E_ARG, "the coarse-scale solver is for the steady equations");
+    if (c->opt.tag_layers < 1) return fail(c, GPLMM_E_ARG, "the coarse-scale solver needs tag_layers >= 1");
+    if (c->nco <= 0) return fail(c, GPLMM_E_ARG, "no coarse unknowns (a single pore)");
+    if (opt->increments < 1 || opt->increments > 64 || opt->newton_maxit < 1 || !(opt->tol > 0.0))
+        return fail(c, GPLMM_E_ARG, "coarse options: 1 <= increments <= 64, newton_maxit >= 1, tol > 0");
+    gplmm_coarse_stats loc;
+    gplmm_coarse_stats* S = st ? st : &loc;
+    std::memset(S, 0, sizeof(*S));
+    auto T0 = std::chrono::steady_clock::now();
+    const int64_t N = c->N;
+    const int nco = c->nco;
+    const bool fp32 = c->opt.precision == GPLMM_FP32;
+    const Phys full = c->phys;
+    double* rc = c->d_dx;          // coarse residual (nco), then the coarse step (nco)
+    double* dc = c->d_dx + nco;
+    std::vector<double> h(nco);
+    auto coarse_norm = [&]() -> double {
+        launch_residual(c, x, nullptr, c->d_r, c->stream, true);
+        coarse_restrict(c, c->d_r, rc);
+        hipMemcpyAsync(h.data(), rc, sizeof(double) * nco, hipMemcpyDeviceToHost, c->stream);
+        hipStreamSynchronize(c->stream);
+        double s2 = 0.0;
+        for (double v : h) s2 += v * v;
+        return std::sqrt(s2);
+    };
+    int rcode = 0;
+    GP_HIP(c, hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
+    const int n = opt->increments;
+    S->converged = 1;
+    for (int m = 1; m <= n && rcode >= 0; ++m) {
+        const double f = (double)m / n;
+        for (int a = 0; a < 3; ++a) c->phys.body[a] = full.body[a] * f;
+        // wind: the velocity of the previous step (zero at the first); pressures are ignored
+        GP_HIP(c, hipMemcpyAsync(c->d_wind, x, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+        int rc_b = do_build(c);
+        S->t_build_ms += c->last_build_ms;
+        if (rc_b != GPLMM_OK) {
+            rcode = rc_b;
+            break;
+        }
+        const double r0 = coarse_norm();
+        double rel = r0 > 0.0 ? 1.0 : 0.0;
+        int its = 0;
+        while (its < opt->newton_maxit && rel >= opt->tol && r0 > 0.0) {
+            int rj = fp32 ? coarse_jacobian<float>(c, x) : coarse_jacobian<double>(c, x);
+            if (rj != GPLMM_OK) {
+                rcode = rj;
+                break;
+            }
+            if (fp32) coarse_update<float>(c, rc, dc, c->d_tmp, x);
+            else coarse_update<double>(c, rc, dc, c->d_tmp, x);
+            ++its;
+            const double rn = coarse_norm();
+            if (!std::isfinite(rn)) {
+                rcode = fail(c, GPLMM_E_BREAKDOWN, "coarse-scale solver: non-finite coarse residual");
+                break;
+            }
+            rel = rn / r0;
+        }
+        S->increments = m;
+        S->newton_its[m - 1] = its;
+        S->rc_rel[m - 1] = rel;
+        if (rel >= opt->tol) S->converged = 0;
+    }
+    c->phys = full;
+    c->built = false;            // the coarse blocks hold J_c^-1 and the factors the last step's
+    c->graph_valid = false;
+    if (rcode < 0) return rcode;
+    // true residual of the approximate solution, against r(0) of the full driving force
+    launch_residual(c, c->d_zero, c->d_zero, c->d_r, c->stream);
+    const double r0f = nrm2(c, c->d_r, N);
+    launch_residual(c, x, nullptr, c->d_r, c->stream);
+    S->fine_rel_residual = nrm2(c, c->d_r, N) / r0f;
+    GP_HIP(c, hipStreamSynchronize(c->stream));
+    GP_HIP(c, hipGetLastError());
+    S->t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - T0).count();
+    return S->converged ? GPLMM_OK : 1;
 }
 
 int gplmm_sample_residuals(gplmm_ctx* c, const double* x, const double* xprev, double* out) {

@@ -114,6 +114,7 @@ struct gplmm_ctx {
     std::vector<int32_t> lu_step_pairs[2];
     std::vector<int64_t> lu_sub_off[2];
     std::vector<int32_t> lu_sub_list[2];
+    double lu_flops[2] = {0.0, 0.0};     // flops of the tile products of each schedule (2 T^3 each)
 
     // ---- shape vectors
     std::vector<int64_t> phi_off;     // per primary: element offset of its |S| x (|Cp|+1) block
@@ -266,8 +267,9 @@ void build_coarse_blocks(gplmm_ctx* c);
 int merge_samples(gplmm_ctx* c, std::vector<gplmm_ctx*>& parts);
 
 // stencil.hip
-void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s);
-void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s);
+void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s,
+                     bool tagged = false);
+void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s, bool tagged = false);
 template <typename T>
 void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s);
 void launch_xcoef(gplmm_ctx* c, hipStream_t s);
@@ -297,6 +299,13 @@ template <typename T>
 int build_precond(gplmm_ctx* c);
 template <typename T>
 int apply_precond(gplmm_ctx* c, const double* v, double* z);
+
+// coarse-scale solver pieces (precond.hip)
+template <typename T>
+int coarse_jacobian(gplmm_ctx* c, const double* xk);
+void coarse_restrict(gplmm_ctx* c, const double* v, double* out);
+template <typename T>
+void coarse_update(gplmm_ctx* c, const double* rc, double* dc, double* tmp, double* x);
 
 // coarse.hip
 int coarse_invert(gplmm_ctx* c);

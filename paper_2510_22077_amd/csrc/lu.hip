@@ -1003,6 +1003,7 @@ int factor_set(gplmm_ctx* c, int set) {
     T* F = (T*)c->d_factor;
     const auto& soff = c->lu_sub_off[set];
     const auto& poff = c->lu_step_off[set];
+    timer_begin(c, "lu");
     for (int K = 0; K + 1 < (int)soff.size(); ++K) {
         int ns = (int)(soff[K + 1] - soff[K]);
         if (ns == 0) break;
@@ -1011,6 +1012,7 @@ int factor_set(gplmm_ctx* c, int set) {
         if (np > 0)
             lu_row_kernel<T><<<np, 256, 0, c->stream>>>(e, F, c->d_step_pairs[set] + 2 * poff[K], K, c->d_inv64);
     }
+    timer_end(c, "lu", c->lu_flops[set]);
     return GPLMM_OK;
 }
 

@@ -265,23 +265,77 @@ static int learned_coarse(gplmm_ctx* c) {
     return GPLMM_OK;
 }
 
+// The coarse blocks <- Rhat A Phat by probing: each colour's columns are prolonged together,
+// A is applied by mv(pv, xv) (FP64 vectors), the result restricted and scattered into
+// the entries of those columns.  Scratch: the first two Krylov basis vectors, which hold
+// nothing between FGMRES solves (the Newton residual and step vectors must survive a
+// rebuild).
+template <typename T, typename MV>
+static void probe_coarse(gplmm_ctx* c, MV mv) {
+    hipStream_t s = c->stream;
+    const int nco = c->nco;
+    hipMemsetAsync(c->d_Ao, 0, sizeof(double) * c->co_elems, s);
+    double* e = c->d_cv;
+    double* tco = c->d_cv + nco;
+    double* pv = c->d_V;
+    double* xv = c->d_V + c->N;
+    for (int k = 0; k < c->ncolors; ++k) {
+        int64_t c0 = c->color_col_off[k], c1 = c->color_col_off[k + 1];
+        hipMemsetAsync(e, 0, sizeof(double) * nco, s);
+        set_ones_kernel<<<nb(c1 - c0), kB, 0, s>>>(c->d_color_cols + c0, c1 - c0, e, 1.0);
+        prolong<T, double>(c, e, pv);
+        mv(pv, xv);
+        restrict_<double>(c, xv, tco);
+        int64_t p0 = c->color_off[k], p1 = c->color_off[k + 1];
+        probe_scatter_kernel<<<nb(p1 - p0), kB, 0, s>>>(c->d_probe + p0, p1 - p0, tco, c->d_Ao, coblk(c));
+    }
+}
+
+// Coarse-scale solver (Section 5): the coarse Jacobian J_c = Rhat J~(xk) Phat, J~ the
+// Jacobian of the residual without inertia on tagged faces, assembled with the probing
+// colours of the coarse operator (with at least one tag layer every coupling J~ adds to
+// X stays inside one primary, so the pattern is the same) and inverted in place.
+template <typename T>
+int coarse_jacobian(gplmm_ctx* c, const double* xk) {
+    probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_jv(c, xk, pv, xv, c->stream, true); });
+    return coarse_invert(c);
+}
+
+// out = Rhat v (FP64, nco entries).
+void coarse_restrict(gplmm_ctx* c, const double* v, double* out) { restrict_<double>(c, v, out); }
+
+// x <- x - Phat (J_c^-1 rc): the coarse Newton update with delta_c = -J_c^-1 r_c; the
+// coarse inverse is in the coarse blocks, delta at dc (nco), the prolonged step at tmp (N).
+template <typename T>
+void coarse_update(gplmm_ctx* c, const double* rc, double* dc, double* tmp, double* x) {
+    gemv_kernel<<<c->nco, kB, 0, c->stream>>>(c->d_Ao, coblk(c), rc, dc);
+    prolong<T, double>(c, dc, tmp);
+    axpy(c, -1.0, tmp, x, c->N);
+}
+
 template <typename T>
 int build_precond(gplmm_ctx* c) {
     hipStream_t s = c->stream;
     T* F = (T*)c->d_factor;
     GP_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
     // 1. closure matrices of the primaries and the dual blocks, factorised together
+    timer_begin(c, "build_closure_dual_lu");
     GP_HIP(c, hipMemsetAsync(F, 0, sizeof(T) * c->factor_elems, s));
     assemble_subs<T>(c, 0, c->Np, true);
     assemble_subs<T>(c, c->Np, c->Nc, false);
     factor_set<T>(c, 1);
+    timer_end(c, "build_closure_dual_lu", c->lu_flops[1]);
     // 2. shape and correction vectors: Abar_i^-1 [g_i1 .. g_im, b_B]
+    timer_begin(c, "build_shape");
     GP_HIP(c, hipMemcpyAsync(c->d_phi, c->d_phi_rhs, sizeof(T) * c->phi_elems, hipMemcpyDeviceToDevice, s));
     trsv_phi<T>(c, c->max_phi_cols);
+    timer_end(c, "build_shape", 0.0);
     // 3. primary Schwarz blocks X[S_i, S_i] replace the closure factors
+    timer_begin(c, "build_primary_lu");
     GP_HIP(c, hipMemsetAsync(F, 0, sizeof(T) * c->prim_factor_elems, s));
     assemble_subs<T>(c, 0, c->Np, false);
     factor_set<T>(c, 0);
+    timer_end(c, "build_primary_lu", c->lu_flops[0]);
     int flag = 0;
     GP_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(c, hipStreamSynchronize(s));
@@ -310,26 +364,13 @@ int build_precond(gplmm_ctx* c) {
         tc0 = std::chrono::steady_clock::now();
     }
     if (nco > 0) {
-        GP_HIP(c, hipMemsetAsync(c->d_Ao, 0, sizeof(double) * c->co_elems, s));
-        double* e = c->d_cv;
-        double* tco = c->d_cv + nco;
-        // FP64 scratch: the first two Krylov basis vectors, which hold nothing between
-        // FGMRES solves (the Newton residual and step vectors must survive a rebuild)
-        double* pv = c->d_V;
-        double* xv = c->d_V + c->N;
-        for (int k = 0; k < c->ncolors; ++k) {
-            int64_t c0 = c->color_col_off[k], c1 = c->color_col_off[k + 1];
-            GP_HIP(c, hipMemsetAsync(e, 0, sizeof(double) * nco, s));
-            set_ones_kernel<<<nb(c1 - c0), kB, 0, s>>>(c->d_color_cols + c0, c1 - c0, e, 1.0);
-            prolong<T, double>(c, e, pv);
-            launch_xv<double>(c, pv, xv, nullptr, s);
-            restrict_<double>(c, xv, tco);
-            int64_t p0 = c->color_off[k], p1 = c->color_off[k + 1];
-            probe_scatter_kernel<<<nb(p1 - p0), kB, 0, s>>>(c->d_probe + p0, p1 - p0, tco, c->d_Ao, coblk(c));
-        }
+        timer_begin(c, "build_coarse");
+        probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_xv<double>(c, pv, xv, nullptr, s); });
+        GP_HIP(c, hipGetLastError());
         GP_HIP(c, hipStreamSynchronize(s));
         c->last_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
         int rc = coarse_invert(c);
+        timer_end(c, "build_coarse", 0.0);
         if (rc != GPLMM_OK) return rc;
     }
     GP_HIP(c, hipStreamSynchronize(s));
@@ -382,6 +423,10 @@ int apply_precond(gplmm_ctx* c, const double* v, double* z) {
     return GPLMM_OK;
 }
 
+template int coarse_jacobian<float>(gplmm_ctx*, const double*);
+template int coarse_jacobian<double>(gplmm_ctx*, const double*);
+template void coarse_update<float>(gplmm_ctx*, const double*, double*, double*, double*);
+template void coarse_update<double>(gplmm_ctx*, const double*, double*, double*, double*);
 template int build_precond<float>(gplmm_ctx*);
 template int build_precond<double>(gplmm_ctx*);
 template int apply_precond<float>(gplmm_ctx*, const double*, double*);

@@ -576,20 +576,25 @@ int build_local_problems(gplmm_ctx* c) {
         soff.assign(1, 0);
         pr.clear();
         sl.clear();
+        double products = 0.0;   // T x T tile products of the factorisation (panels, updates)
         for (int K = 0; K < c->maxT; ++K) {
             for (int s = 0; s < ns; ++s) {
                 const Sub& sb = c->subs[s];
                 if (sb.nT <= K) continue;
                 sl.push_back(s);
                 const int* tfc = &c->env_tfc[sb.env_off];
+                const int width = c->env_tlc[sb.env_off + K] - K;   // U panel tiles of step K
+                products += width;
                 for (int I = K + 1; I < sb.nT && tfc[I] <= K; ++I) {
                     pr.push_back(s);
                     pr.push_back(I);
+                    products += 1.0 + width;                         // L panel tile, trailing row
                 }
             }
             off.push_back((int64_t)pr.size() / 2);
             soff.push_back((int64_t)sl.size());
         }
+        c->lu_flops[set] = 2.0 * (double)T * T * T * products;
     }
     // ---- shape/correction blocks: per primary |S| x (|Cp| + 1), column-major
     c->phi_off.assign(c->Np, 0);

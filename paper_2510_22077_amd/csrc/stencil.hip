@@ -28,22 +28,23 @@ namespace {
 constexpr int kBlock = 512;   // largest block size the stencil kernels are compiled for
 
 // r(x): momentum and mass residual.
-template <int ND>
+template <int ND, bool kTagged>
 __global__ void __launch_bounds__(kBlock) residual_kernel(DevGeo g, Phys ph0, const double* __restrict__ x,
                                                           const double* __restrict__ xold, double* __restrict__ r) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
     double out[ND + 1];
-    residual_cell<ND>(g, ph0, x, xold, c, out);
+    residual_cell<ND, kTagged>(g, ph0, x, xold, c, out);
 #pragma unroll
     for (int a = 0; a <= ND; ++a) r[(ND + 1) * c + a] = out[a];
 }
 
-// y = J(xk) v with the upwind branches frozen at xk.
-template <int ND>
+// y = J(xk) v with the upwind branches frozen at xk.  kTagged: the Jacobian of the
+// residual without inertia on tagged faces (coarse-scale solver).
+template <int ND, bool kTagged>
 __global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph0, const double* __restrict__ xk,
                                                     const double* __restrict__ v, double* __restrict__ y) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
     const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
@@ -64,18 +65,20 @@ __global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph0, const do
                 for (int t = 0; t < 2; ++t) visc += vF - nb_value(f, d, t, v, nr, a, vF);
             out = vis * visc + (v[nr * c + ND] - v[(int64_t)nr * L + ND]) * ih;
             if (ph.dt > 0.0) out += ph.rho * vF / ph.dt;
-            double conv = 0.0;
+            if (!kTagged || !((g.tag[c] >> a) & 1u)) {
+                double conv = 0.0;
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                const double ad = advecting(nc, nl, c, L, a, d, xk, nr);
-                const double adv = advecting(nc, nl, c, L, a, d, v, nr);
-                const int t = ad >= 0.0 ? 0 : 1;
-                const double gu = nb_value(f, d, t, xk, nr, a, uF), gv = nb_value(f, d, t, v, nr, a, vF);
-                const double Du = t == 0 ? uF - gu : gu - uF;
-                const double Dv = t == 0 ? vF - gv : gv - vF;
-                conv += (ad * Dv + adv * Du) * ih;
+                for (int d = 0; d < ND; ++d) {
+                    const double ad = advecting(nc, nl, c, L, a, d, xk, nr);
+                    const double adv = advecting(nc, nl, c, L, a, d, v, nr);
+                    const int t = ad >= 0.0 ? 0 : 1;
+                    const double gu = nb_value(f, d, t, xk, nr, a, uF), gv = nb_value(f, d, t, v, nr, a, vF);
+                    const double Du = t == 0 ? uF - gu : gu - uF;
+                    const double Dv = t == 0 ? vF - gv : gv - vF;
+                    conv += (ad * Dv + adv * Du) * ih;
+                }
+                out += ph.rho * conv;
             }
-            out += ph.rho * conv;
         }
         y[nr * c + a] = out;
     }
@@ -99,7 +102,7 @@ __global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph0, const do
 template <int ND>
 __global__ void __launch_bounds__(kBlock) xcoef_kernel(DevGeo g, Phys ph0, const double* __restrict__ wind,
                                                        double* __restrict__ cf64, float* __restrict__ cf32) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
     const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
@@ -129,7 +132,7 @@ __global__ void __launch_bounds__(kBlock) xcoef_kernel(DevGeo g, Phys ph0, const
 template <int ND, typename T>
 __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restrict__ coef, const T* __restrict__ a,
                                                     const T* __restrict__ b, T* __restrict__ y) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
     constexpr int nr = ND + 1;
     const Nb<ND> nc = load_nb<ND>(g, c);
@@ -172,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restric
 // b_B = -r(u = 0, p = 0) of the steady equations: rho * body on every active face.
 template <int ND>
 __global__ void bB_kernel(DevGeo g, Phys ph0, double* __restrict__ out) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
     const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
@@ -186,14 +189,28 @@ inline dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)
 
 }  // namespace
 
-void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s) {
-    if (c->ndim == 3) residual_kernel<3><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, x, xprev, r);
-    else residual_kernel<2><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, x, xprev, r);
+void launch_residual(gplmm_ctx* c, const double* x, const double* xprev, double* r, hipStream_t s, bool tagged) {
+    const dim3 gr = grid_for(c->ncell, c->stencil_block);
+    const int b = c->stencil_block;
+    if (c->ndim == 3) {
+        if (tagged) residual_kernel<3, true><<<gr, b, 0, s>>>(c->geo, c->phys, x, xprev, r);
+        else residual_kernel<3, false><<<gr, b, 0, s>>>(c->geo, c->phys, x, xprev, r);
+    } else {
+        if (tagged) residual_kernel<2, true><<<gr, b, 0, s>>>(c->geo, c->phys, x, xprev, r);
+        else residual_kernel<2, false><<<gr, b, 0, s>>>(c->geo, c->phys, x, xprev, r);
+    }
 }
 
-void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s) {
-    if (c->ndim == 3) jv_kernel<3><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, xk, v, y);
-    else jv_kernel<2><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, xk, v, y);
+void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipStream_t s, bool tagged) {
+    const dim3 gr = grid_for(c->ncell, c->stencil_block);
+    const int b = c->stencil_block;
+    if (c->ndim == 3) {
+        if (tagged) jv_kernel<3, true><<<gr, b, 0, s>>>(c->geo, c->phys, xk, v, y);
+        else jv_kernel<3, false><<<gr, b, 0, s>>>(c->geo, c->phys, xk, v, y);
+    } else {
+        if (tagged) jv_kernel<2, true><<<gr, b, 0, s>>>(c->geo, c->phys, xk, v, y);
+        else jv_kernel<2, false><<<gr, b, 0, s>>>(c->geo, c->phys, xk, v, y);
+    }
 }
 
 void launch_xcoef(gplmm_ctx* c, hipStream_t s) {

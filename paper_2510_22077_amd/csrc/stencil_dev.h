@@ -14,6 +14,20 @@
 namespace gp {
 
 enum : int { kActive = 0, kZero = 1, kGhost = 2 };
+
+// The chip hands workgroups to its eight XCDs round-robin (workgroup i to XCD i % 8), and
+// each XCD has its own L2.  A one-thread-per-cell stencil reads the records of the
+// neighbouring cells, which belong to neighbouring workgroups; renumbering the
+// workgroups so that XCD x works on one contiguous range of cells keeps those
+// neighbours in the same L2 (round-robin order left every neighbour row on another
+// XCD: the Jacobian stencil fetched 12x its algorithmic bytes from beyond L2).
+// A bijection of [0, n) onto itself.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t n) {
+    const int64_t q = n / kXcds, r = n % kXcds;
+    const int64_t x = i % kXcds, k = i / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
 constexpr int kNC = 7;   // coefficients per momentum row: diagonal, then (d, t) -> 1 + 2 d + t
 
 template <int ND>
@@ -134,7 +148,9 @@ __device__ __forceinline__ void x_face_coefs(const Phys& ph, double h, const Nb<
 // Residual record of cell c (Section 1 momentum and mass equations on the MAC grid):
 // out[a] for the lower a-face (0 when inactive), out[ND] for the mass row (p = 0 at a
 // pinned cell).  Backward Euler against xold when dt > 0 (xold may be nullptr = 0).
-template <int ND>
+// kTagged: the modified residual of Section 4 with the wind equal to the state, i.e.
+// no inertia on tagged faces (the residual of the coarse-scale solver, Section 5).
+template <int ND, bool kTagged = false>
 __device__ __forceinline__ void residual_cell(const DevGeo& g, const Phys& ph0, const double* __restrict__ x,
                                               const double* __restrict__ xold, int64_t c, double* out) {
     const Phys ph = cell_phys(g, ph0, c);
@@ -156,14 +172,16 @@ __device__ __forceinline__ void residual_cell(const DevGeo& g, const Phys& ph0, 
                 for (int t = 0; t < 2; ++t) visc += uF - nb_value(f, d, t, x, nr, a, uF);
             o = vis * visc + (x[nr * c + ND] - x[(int64_t)nr * L + ND]) * ih - ph.rho * ph.body[a];
             if (ph.dt > 0.0) o += ph.rho * (uF - (xold ? xold[nr * c + a] : 0.0)) / ph.dt;
-            double conv = 0.0;
+            if (!kTagged || !((g.tag[c] >> a) & 1u)) {
+                double conv = 0.0;
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                const double ad = advecting(nc, nl, c, L, a, d, x, nr);
-                const double gm = nb_value(f, d, 0, x, nr, a, uF), gp_ = nb_value(f, d, 1, x, nr, a, uF);
-                conv += ad * (ad >= 0.0 ? (uF - gm) : (gp_ - uF)) * ih;
+                for (int d = 0; d < ND; ++d) {
+                    const double ad = advecting(nc, nl, c, L, a, d, x, nr);
+                    const double gm = nb_value(f, d, 0, x, nr, a, uF), gp_ = nb_value(f, d, 1, x, nr, a, uF);
+                    conv += ad * (ad >= 0.0 ? (uF - gm) : (gp_ - uF)) * ih;
+                }
+                o += ph.rho * conv;
             }
-            o += ph.rho * conv;
         }
         out[a] = o;
     }
