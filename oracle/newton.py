@@ -34,6 +34,7 @@ class NewtonStats:
     t_mg: float = 0.0        # M_G builds: closures, shape/correction vectors, coarse operator
     t_ml: float = 0.0        # smoother builds: LU of every primary and dual block
     t_sol: float = 0.0       # Krylov solves (all Newton steps)
+    t_hist: list = field(default_factory=list)   # wall seconds from the start to each res_hist entry
     converged: bool = False
 
 
@@ -58,6 +59,7 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
     else the smallest."""
     g = ops.g
     st = stats if stats is not None else NewtonStats()
+    t_start = time.perf_counter()
     steady0 = Phys(phys.rho, phys.mu, phys.body, phys.dt, phys.pin)
     r0n = np.linalg.norm(residual(ops, np.zeros(g.N), steady0,
                                   x_old=np.zeros(g.N) if phys.dt is not None else None))
@@ -72,6 +74,7 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
         st.t_ml += M.t_ml
     r = residual(ops, x, phys, x_old=x_old)
     st.res_hist.append(np.linalg.norm(r) / r0n)
+    st.t_hist.append(time.perf_counter() - t_start)
     for k in range(maxit):
         if np.linalg.norm(r) <= tol * r0n:
             st.converged = True
@@ -101,6 +104,7 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
         st.step_length.append(lam)
         x, r = xt, rt
         st.res_hist.append(np.linalg.norm(r) / r0n)
+        st.t_hist.append(time.perf_counter() - t_start)
     else:
         st.converged = np.linalg.norm(r) <= tol * r0n
     return x, st

@@ -88,7 +88,8 @@ def solve(name, restart=256, tol=1e-12):
     meta = dict(workload="spheres3d_128", seed=0, crop=n, N=int(g.N), nu=int(g.nu), ncell=int(g.nc),
                 Np=int(dc.Np), Nc=int(dc.Nc), pin=int(dc.pin), body=list(w["body"]), tol=tol,
                 lin_tol=0.1 * tol, restart=restart, newton_its=st.newton_its, fgmres_its=list(st.lin_its),
-                step_length=list(st.step_length), res_hist=list(st.res_hist), rel_residual=rel,
+                step_length=list(st.step_length), res_hist=list(st.res_hist), t_hist=list(st.t_hist),
+                rel_residual=rel,
                 converged=bool(st.converged), wall_s=wall, setup_s=t_setup, t_mg_s=st.t_mg,
                 t_ml_s=st.t_ml, t_sol_s=st.t_sol, nproc=os.cpu_count(), cpu_model=cpu_model(), blas=blas,
                 python=platform.python_version(), numpy=np.__version__)
