@@ -163,7 +163,10 @@ def main():
                     help="skip the comparison solve with the plain FP64 preconditioner")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-scale solver leg")
-    ap.add_argument("--coarse-increments", type=int, default=1)
+    ap.add_argument("--no-aplmm", action="store_true", help="skip the aPLMM_S / aPLMM_NS comparison solves")
+    ap.add_argument("--coarse-increments", type=int, default=3,
+                    help="body-force steps of the coarse-scale solver (one step from rest stalls at "
+                         "128^3, as Algorithm 1 warns for starts far from the solution)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the extra solve on the finer pore split (about 1.5k pores)")
     ap.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
@@ -343,6 +346,24 @@ def main():
                              "t_build_ms": st64["t_build_ms"],
                              "rel_diff_vs_fp32_solution": float(torch.linalg.norm(x64 - x) / torch.linalg.norm(x64))}
         del s64
+    if not args.no_aplmm:
+        # the paper's comparison preconditioners on the same workload (Section 8):
+        # aPLMM_S = gPLMM_S (built once from the Stokes matrix) and aPLMM_NS (built from the
+        # Newton Jacobian, rebuilt once at the first Newton iterate as gPLMM is)
+        for key, kw in (("aplmm_s", dict(wind="zero")), ("aplmm_ns", dict(build_matrix="jacobian"))):
+            log("%s preconditioner on the same workload ..." % key)
+            sa = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"], precision=args.precision,
+                        newton_tol=1e-8, lin_tol=1e-9, restart=args.restart, **kw)
+            sa.newton_solve()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xa, sta = sa.newton_solve()
+            torch.cuda.synchronize()
+            out[key] = {"s": time.perf_counter() - t0, "newton_its": sta["newton_its"], "fgmres_its": sta["lin_its"],
+                        "fgmres_its_total": sta["lin_its_total"], "t_build_ms": sta["t_build_ms"],
+                        "builds": sta["builds"], "converged": sta["converged"]}
+            del sa
+            torch.cuda.empty_cache()
     if not args.no_variants:
         from synth import make_workload as _mk
         log("finer pore split (pores > 1000 voxels split) ...")

@@ -77,6 +77,16 @@ enum {
     GPLMM_WIND_CALLER = 2    /* w set by gplmm_build(ctx, w_dev) and kept */
 };
 
+/* Matrix the preconditioner is built from (the A-hat of Sections 3.1-3.2). */
+enum {
+    GPLMM_BUILD_GEOMETRIC = 0,  /* gPLMM (Section 4): X = J~_w, the Oseen operator of the wind
+                                   with no inertia on tagged faces */
+    GPLMM_BUILD_JACOBIAN = 1    /* aPLMM (Sections 3 and 8): the Newton Jacobian J(w) at the build
+                                   state w, untagged.  With GPLMM_WIND_ZERO it is the Stokes matrix
+                                   (aPLMM_S, which equals gPLMM with w = 0); with GPLMM_WIND_STOKES it
+                                   is rebuilt once from J at the first Newton iterate (aPLMM_NS) */
+};
+
 typedef struct {
     int nx, ny, nz;          /* image size; nz = 1 for 2D */
     double h;                /* voxel edge (default 1) */
@@ -108,6 +118,8 @@ typedef struct {
                                 in a HIP graph and replayed (input and output staged through
                                 buffers owned by the context); 0: launched kernel by kernel.
                                 Timed runs (gplmm_set_timing) always launch kernel by kernel */
+    int build_matrix;        /* GPLMM_BUILD_GEOMETRIC (default) or GPLMM_BUILD_JACOBIAN; the
+                                residual updates of Eqs. mono_struct_a and Mdp use the same matrix */
 } gplmm_options;
 
 typedef struct {

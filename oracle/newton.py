@@ -38,9 +38,15 @@ class NewtonStats:
     converged: bool = False
 
 
-def build_precond(ops, dc, phys, wind):
+def build_precond(ops, dc, phys, wind, build="geometric"):
+    """gPLMM from X = J~_w (Section 4), or, with build="jacobian", the algebraic aPLMM
+    from the Newton Jacobian at the state w (no tags; w = None gives the Stokes
+    matrix, i.e. aPLMM_S)."""
     t = time.perf_counter()
-    X = build_matrix(ops, phys, wind=wind, tags=dc.tags)
+    if build == "jacobian":
+        X = jacobian(ops, np.zeros(ops.g.N) if wind is None else wind, phys)
+    else:
+        X = build_matrix(ops, phys, wind=wind, tags=dc.tags)
     bB = origin_rhs(ops, phys)
     t_asm = time.perf_counter() - t
     M = G.build(X, dc, bB)
@@ -50,8 +56,12 @@ def build_precond(ops, dc, phys, wind):
 
 def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
           maxit=30, restart=30, lin_maxit=600, wind="stokes", wind_vec=None,
-          precond="gplmm", stats=None, line_search=False):
+          precond="gplmm", stats=None, line_search=False, build="geometric"):
     """Newton-FGMRES with gPLMM.  ``precond``: "gplmm" or "exact" (spsolve).
+
+    ``build``: "geometric" (gPLMM, Section 4) or "jacobian" (aPLMM from the Newton
+    Jacobian at the build state: aPLMM_S at w = 0, aPLMM_NS when rebuilt at the first
+    iterate with wind="stokes").
 
     ``line_search``: False (default) takes the full step x + d of Section 1; True
     backtracks on ||r||, lambda = 1, 1/2, ... down to 1/64, the first lambda with
@@ -69,7 +79,7 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
     M = None
     if precond == "gplmm":
         w = wind_vec if wind == "caller" else None
-        M = build_precond(ops, dc, phys, w)
+        M = build_precond(ops, dc, phys, w, build)
         st.t_mg += M.t_mg
         st.t_ml += M.t_ml
     r = residual(ops, x, phys, x_old=x_old)
@@ -80,7 +90,7 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
             st.converged = True
             break
         if k == 1 and precond == "gplmm" and wind == "stokes":
-            M = build_precond(ops, dc, phys, x)
+            M = build_precond(ops, dc, phys, x, build)
             st.t_mg += M.t_mg
             st.t_ml += M.t_ml
         J = jacobian(ops, x, phys)

@@ -26,7 +26,8 @@ class Options(ctypes.Structure):
                 ("restart", ctypes.c_int), ("newton_tol", ctypes.c_double),
                 ("lin_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int),
                 ("lin_maxit", ctypes.c_int), ("tile", ctypes.c_int), ("host_only", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("line_search", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("line_search", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("build_matrix", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -219,7 +220,7 @@ class Solver:
 
     def _prepare(self, nx, ny, nz, h=1.0, periodic=(1, 0, 0), precision="fp64", wind="stokes", tag_layers=1,
                  dual_dilations=-1, restart=30, newton_tol=1e-8, lin_tol=1e-9, newton_maxit=30, lin_maxit=600,
-                 host_only=False, stream=None, line_search=False, use_graph=True):
+                 host_only=False, stream=None, line_search=False, use_graph=True, build_matrix="geometric"):
         lib = load()
         self.lib = lib
         self.ctx = ctypes.c_void_p()
@@ -241,6 +242,7 @@ class Solver:
         o.host_only = 1 if host_only else 0
         o.line_search = 1 if line_search else 0
         o.use_graph = 1 if use_graph else 0
+        o.build_matrix = {"geometric": 0, "jacobian": 1}[build_matrix]
         self.torch = None
         if not host_only:
             import torch

@@ -260,7 +260,8 @@ int upload_all(gplmm_ctx* c) {
     // vectors
     const int m = c->opt.restart;
     GP_TRY(alloc(c, (void**)&c->d_wind, sizeof(double) * N));
-    const int64_t ncoef = (int64_t)(1 + 2 * c->ndim) * c->ndim * nc;
+    const int slots = 1 + 2 * c->ndim + (c->opt.build_matrix == GPLMM_BUILD_JACOBIAN ? 4 * (c->ndim - 1) : 0);
+    const int64_t ncoef = (int64_t)slots * c->ndim * nc;
     GP_TRY(alloc(c, (void**)&c->d_xcoef, sizeof(double) * ncoef));
     if (c->opt.precision == GPLMM_FP32) GP_TRY(alloc(c, (void**)&c->d_xcoef_f, sizeof(float) * ncoef));
     GP_TRY(alloc(c, (void**)&c->d_r, sizeof(double) * N));
@@ -749,6 +750,8 @@ static int check_options(gplmm_ctx* c, const gplmm_options* opt, double rho, dou
     if (c->opt.tile == 0) c->opt.tile = 32;
     if (c->opt.restart > kMaxRestart) return fail(c, GPLMM_E_ARG, "restart must be <= 1024");
     if (c->opt.tile != 32) return fail(c, GPLMM_E_ARG, "only tile = 32 is supported");
+    if (c->opt.build_matrix != GPLMM_BUILD_GEOMETRIC && c->opt.build_matrix != GPLMM_BUILD_JACOBIAN)
+        return fail(c, GPLMM_E_ARG, "build_matrix must be GPLMM_BUILD_GEOMETRIC or GPLMM_BUILD_JACOBIAN");
     if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return fail(c, GPLMM_E_ARG, "image dimensions must be positive");
     if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024)
         return fail(c, GPLMM_E_ARG, "image dimensions must be <= 1024");

@@ -54,7 +54,7 @@ __device__ __forceinline__ T* tile_ptr(T* F, const Env& e, const Sub& sb, int I,
 // columns of f-faces or of other primaries' unknowns are added to the diagonal
 // (Section 3.2.2, both reduction steps), except on rows of wall-free faces.
 // ---------------------------------------------------------------------------------------
-template <int ND, typename T>
+template <int ND, typename T, bool kJac>
 __global__ void assemble_kernel(DevGeo g, const double* __restrict__ coef, Env e, T* __restrict__ F,
                                 const int32_t* __restrict__ row_sub, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ sorted_slot, const int32_t* __restrict__ sorted_loc,
@@ -107,6 +107,18 @@ __global__ void assemble_kernel(DevGeo g, const double* __restrict__ coef, Env e
                     if (f.kind[d][q] == kActive) emit((int64_t)nr * f.P[d][q] + a, coef[((1 + 2 * d + q) * ND + a) * nce + c]);
             emit(nr * c + ND, ih);
             emit((int64_t)nr * L + ND, -ih);
+            if (kJac) {   // transverse couplings of the Newton Jacobian
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    if (d == a) continue;
+                    const int dd = d < a ? d : d - 1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double w = coef[((1 + 2 * ND + 4 * dd + q) * ND + a) * nce + c];
+                        if (w != 0.0) emit((int64_t)nr * jac_col_cell<ND>(nc, nl, c, L, d, q) + d, w);
+                    }
+                }
+            }
         }
     } else if ((g.tag[c] & kPinBit)) {
         emit(gs, 1.0);
@@ -985,14 +997,19 @@ int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure) {
     T* F = (T*)c->d_factor;
     const int64_t nrows = (int64_t)c->sub_slots.size();
     const unsigned nb = (unsigned)((nrows + 255) / 256);
-    if (c->ndim == 3)
-        assemble_kernel<3, T><<<nb, 256, 0, c->stream>>>(c->geo, c->d_xcoef, e, F, c->d_row_sub, c->d_sub_slots,
-                                                         c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class,
-                                                         c->d_noclose, nrows, first_sub, nsub, closure ? 1 : 0);
-    else
-        assemble_kernel<2, T><<<nb, 256, 0, c->stream>>>(c->geo, c->d_xcoef, e, F, c->d_row_sub, c->d_sub_slots,
-                                                         c->d_sorted_slot, c->d_sorted_loc, c->d_slot_class,
-                                                         c->d_noclose, nrows, first_sub, nsub, closure ? 1 : 0);
+    const bool jac = c->opt.build_matrix == GPLMM_BUILD_JACOBIAN;
+    auto launch = [&](auto kern) {
+        kern<<<nb, 256, 0, c->stream>>>(c->geo, c->d_xcoef, e, F, c->d_row_sub, c->d_sub_slots, c->d_sorted_slot,
+                                        c->d_sorted_loc, c->d_slot_class, c->d_noclose, nrows, first_sub, nsub,
+                                        closure ? 1 : 0);
+    };
+    if (c->ndim == 3) {
+        if (jac) launch(assemble_kernel<3, T, true>);
+        else launch(assemble_kernel<3, T, false>);
+    } else {
+        if (jac) launch(assemble_kernel<2, T, true>);
+        else launch(assemble_kernel<2, T, false>);
+    }
     if (nsub > 0) pad_kernel<T><<<nsub, 64, 0, c->stream>>>(e, F, first_sub, nsub);
     return GPLMM_OK;
 }

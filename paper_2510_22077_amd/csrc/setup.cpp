@@ -467,6 +467,17 @@ void row_pattern(const gplmm_ctx* c, int64_t s, std::vector<int64_t>& cols) {
             }
         cols.push_back(slot(c, q, nd));
         cols.push_back(slot(c, l0, nd));
+        if (c->opt.build_matrix == GPLMM_BUILD_JACOBIAN) {
+            // the Newton Jacobian's transverse couplings: the d-faces of the face's two cells
+            for (int d = 0; d < nd; ++d) {
+                if (d == a) continue;
+                for (int64_t cell : {l0, q}) {
+                    if (NB(cell, d, 0) >= 0) cols.push_back(slot(c, cell, d));
+                    int64_t up = NB(cell, d, 1);
+                    if (up >= 0) cols.push_back(slot(c, up, d));
+                }
+            }
+        }
     } else if (!(c->tagcell[q] & kPinBit)) {
         for (int a = 0; a < nd; ++a) {
             if (NB(q, a, 0) >= 0) cols.push_back(slot(c, q, a));
@@ -670,9 +681,17 @@ int build_probing(gplmm_ctx* c) {
                     q.push_back(g);
                 }
         };
+        const bool jac = c->opt.build_matrix == GPLMM_BUILD_JACOBIAN;
         for (int32_t x : col_cells[col]) {
             visit(x);
-            for (int e = 0; e < 2 * nd; ++e) visit(c->nbr[(int64_t)x * 6 + e]);
+            for (int e = 0; e < 2 * nd; ++e) {
+                const int64_t y = c->nbr[(int64_t)x * 6 + e];
+                visit(y);
+                // the Jacobian's transverse couplings also reach the diagonal neighbours
+                if (jac && y >= 0)
+                    for (int e2 = 0; e2 < 2 * nd; ++e2)
+                        if (e2 / 2 != e / 2) visit(c->nbr[y * 6 + e2]);
+            }
         }
         std::sort(q.begin(), q.end());
     }

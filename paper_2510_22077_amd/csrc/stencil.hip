@@ -97,39 +97,44 @@ __global__ void __launch_bounds__(kBlock) jv_kernel(DevGeo g, Phys ph0, const do
     y[nr * c + ND] = m;
 }
 
-// Momentum rows of X = J~_w: coef[(k * ND + a) * ncell + c], k = 0 diagonal, k = 1 + 2 d + t
-// neighbour face (d, t); all zero for an inactive face.  FP64 and, if cf32 != nullptr, FP32.
-template <int ND>
+// Momentum rows of the build matrix: coef[(k * ND + a) * ncell + c], k = 0 diagonal,
+// k = 1 + 2 d + t neighbour face (d, t); all zero for an inactive face.  kJac = false:
+// X = J~_w (Section 4: Oseen with wind w, no inertia on tagged faces); kJac = true: the
+// Newton Jacobian J(w) at the state w (no tags), with its transverse slots.  FP64 and,
+// if cf32 != nullptr, FP32.
+template <int ND, bool kJac>
 __global__ void __launch_bounds__(kBlock) xcoef_kernel(DevGeo g, Phys ph0, const double* __restrict__ wind,
                                                        double* __restrict__ cf64, float* __restrict__ cf32) {
     const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
     const Phys ph = cell_phys(g, ph0, c);
     constexpr int nr = ND + 1;
+    constexpr int ns = coef_slots<ND>(kJac);
     const Nb<ND> nc = load_nb<ND>(g, c);
     const int64_t nce = g.ncell;
 #pragma unroll
     for (int a = 0; a < ND; ++a) {
-        double co[kNC];
+        double co[ns > kNC ? ns : kNC];   // x_face_coefs fills kNC slots
 #pragma unroll
-        for (int k = 0; k < kNC; ++k) co[k] = 0.0;
+        for (int k = 0; k < (ns > kNC ? ns : kNC); ++k) co[k] = 0.0;
         const int32_t L = nc.n[a][0];
         if (L >= 0) {
             const Nb<ND> nl = load_nb<ND>(g, L);
             const FaceNb<ND> f = face_nb(nc, nl, a);
-            const bool tagged = (g.tag[c] >> a) & 1u;
+            const bool tagged = !kJac && ((g.tag[c] >> a) & 1u);
             x_face_coefs(ph, g.h, nc, nl, f, c, a, tagged ? (const double*)nullptr : wind, nr, co);
+            if (kJac) jac_extra<ND>(ph, g.h, nc, nl, f, c, a, wind, nr, co);
         }
 #pragma unroll
-        for (int k = 0; k < 1 + 2 * ND; ++k) {
+        for (int k = 0; k < ns; ++k) {
             cf64[(k * ND + a) * nce + c] = co[k];
             if (cf32) cf32[(k * ND + a) * nce + c] = (float)co[k];
         }
     }
 }
 
-// y = a - X b  (a == nullptr: y = X b) from the tabulated rows.
-template <int ND, typename T>
+// y = a - A b  (a == nullptr: y = A b) from the tabulated rows of the build matrix A.
+template <int ND, typename T, bool kJac>
 __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restrict__ coef, const T* __restrict__ a,
                                                     const T* __restrict__ b, T* __restrict__ y) {
     const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -154,6 +159,19 @@ __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restric
                     const int32_t P = nc.n[d][t];   // (ax, t = 0) -> L itself
                     if (w != (T)0 && P >= 0) acc += w * b[(int64_t)nr * P + ax];
                 }
+            if (kJac) {
+                const Nb<ND> nl = load_nb<ND>(g, L);
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    if (d == ax) continue;
+                    const int dd = d < ax ? d : d - 1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const T w = coef[((1 + 2 * ND + 4 * dd + q) * ND + ax) * nce + c];
+                        if (w != (T)0) acc += w * b[(int64_t)nr * jac_col_cell<ND>(nc, nl, c, L, d, q) + d];
+                    }
+                }
+            }
         }
         y[s] = a ? (T)(a[s] - acc) : acc;
     }
@@ -214,10 +232,16 @@ void launch_jv(gplmm_ctx* c, const double* xk, const double* v, double* y, hipSt
 }
 
 void launch_xcoef(gplmm_ctx* c, hipStream_t s) {
-    if (c->ndim == 3)
-        xcoef_kernel<3><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
-    else
-        xcoef_kernel<2><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+    const dim3 gr = grid_for(c->ncell, c->stencil_block);
+    const int b = c->stencil_block;
+    const bool jac = c->opt.build_matrix == GPLMM_BUILD_JACOBIAN;
+    if (c->ndim == 3) {
+        if (jac) xcoef_kernel<3, true><<<gr, b, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+        else xcoef_kernel<3, false><<<gr, b, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+    } else {
+        if (jac) xcoef_kernel<2, true><<<gr, b, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+        else xcoef_kernel<2, false><<<gr, b, 0, s>>>(c->geo, c->phys, c->d_wind, c->d_xcoef, c->d_xcoef_f);
+    }
 }
 
 template <typename T>
@@ -230,8 +254,16 @@ const float* xcoef_table<float>(gplmm_ctx* c) { return c->d_xcoef_f; }
 template <typename T>
 void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s) {
     const T* cf = xcoef_table<T>(c);
-    if (c->ndim == 3) xv_kernel<3, T><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, cf, sub_from, v, y);
-    else xv_kernel<2, T><<<grid_for(c->ncell, c->stencil_block), c->stencil_block, 0, s>>>(c->geo, cf, sub_from, v, y);
+    const dim3 gr = grid_for(c->ncell, c->stencil_block);
+    const int b = c->stencil_block;
+    const bool jac = c->opt.build_matrix == GPLMM_BUILD_JACOBIAN;
+    if (c->ndim == 3) {
+        if (jac) xv_kernel<3, T, true><<<gr, b, 0, s>>>(c->geo, cf, sub_from, v, y);
+        else xv_kernel<3, T, false><<<gr, b, 0, s>>>(c->geo, cf, sub_from, v, y);
+    } else {
+        if (jac) xv_kernel<2, T, true><<<gr, b, 0, s>>>(c->geo, cf, sub_from, v, y);
+        else xv_kernel<2, T, false><<<gr, b, 0, s>>>(c->geo, cf, sub_from, v, y);
+    }
 }
 
 void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s) {

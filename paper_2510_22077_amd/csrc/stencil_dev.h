@@ -29,6 +29,12 @@ __device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t n) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 constexpr int kNC = 7;   // coefficients per momentum row: diagonal, then (d, t) -> 1 + 2 d + t
+// With the Newton Jacobian as build matrix, each row also couples to the four d-faces of
+// its two cells on every transverse axis d (the derivative of the advecting velocity):
+// slot 1 + 2 ND + 4 dd + q, dd the rank of d among the axes other than a, q = lower and
+// upper d-face of L, lower and upper d-face of C.
+template <int ND>
+constexpr int coef_slots(bool jac) { return jac ? 1 + 2 * ND + 4 * (ND - 1) : 1 + 2 * ND; }
 
 template <int ND>
 struct Nb {
@@ -143,6 +149,45 @@ __device__ __forceinline__ void x_face_coefs(const Phys& ph, double h, const Nb<
         }
     }
     co[0] = diag;
+}
+
+// The terms by which the Newton Jacobian J(w) (Section 1) differs from the untagged Oseen
+// row of X(w): the derivative of the advecting velocity a_a = u_F adds rho D_a u(w) to the
+// diagonal; that of each transverse a_d (the mean of four d-faces) adds rho D_d u(w) / 4
+// on each of those faces that is active.  D_d u(w) is the upwind difference on the branch
+// a_d(w) selects (ties: backward), as in the Jacobian stencil.
+template <int ND, typename W>
+__device__ __forceinline__ void jac_extra(const Phys& ph, double h, const Nb<ND>& nc, const Nb<ND>& nl,
+                                          const FaceNb<ND>& f, int64_t c, int a, const W* w, int nr,
+                                          double* co) {
+    const double ih = 1.0 / h;
+    const int32_t L = nc.n[a][0];
+    const double uF = (double)w[(int64_t)nr * c + a];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const double ad = advecting(nc, nl, c, L, a, d, w, nr);
+        const int t = ad >= 0.0 ? 0 : 1;
+        const double g = nb_value(f, d, t, w, nr, a, uF);
+        const double Du = (t == 0 ? uF - g : g - uF) * ih;
+        if (d == a) {
+            co[0] += ph.rho * Du;
+        } else {
+            const int dd = d < a ? d : d - 1;
+            const double cf = 0.25 * ph.rho * Du;
+            double* tr = co + 1 + 2 * ND + 4 * dd;
+            tr[0] = nl.n[d][0] >= 0 ? cf : 0.0;
+            tr[1] = nl.n[d][1] >= 0 ? cf : 0.0;
+            tr[2] = nc.n[d][0] >= 0 ? cf : 0.0;
+            tr[3] = nc.n[d][1] >= 0 ? cf : 0.0;
+        }
+    }
+}
+
+// Record cell of transverse column q of a row (L = C - e_a): L, L + e_d, C, C + e_d.
+template <int ND>
+__device__ __forceinline__ int32_t jac_col_cell(const Nb<ND>& nc, const Nb<ND>& nl, int64_t c, int32_t L, int d,
+                                                int q) {
+    return q == 0 ? L : q == 1 ? nl.n[d][1] : q == 2 ? (int32_t)c : nc.n[d][1];
 }
 
 // Residual record of cell c (Section 1 momentum and mass equations on the MAC grid):

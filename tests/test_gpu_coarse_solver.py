@@ -93,3 +93,27 @@ def test_coarse_solver_rejects_what_it_does_not_cover():
     with pytest.raises(binding.GplmmError):
         s.coarse_solve()
     s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_coarse_solver_on_a_crop_of_the_benchmark_packing(precision, tol):
+    """The 48^3 corner of the 128^3 packing (about 110 pores, 400 interfaces): many
+    columns per probing colour."""
+    _torch()
+    from paper_2510_22077_amd import Solver
+    w = workload("spheres3d_128", 0)
+    m, lab = w["mask"][:48, :48, :48].copy(), w["labels"][:48, :48, :48].copy()
+    _say("case coarse solve crop 48", precision)
+    s = Solver(m, lab, rho=w["rho"], mu=w["mu"], body=w["body"], precision=precision)
+    g, ops, dc, ph = oracle_case(m, lab, w["rho"], w["mu"], w["body"])
+    rec = record_index(g, s.maps()["cell_voxel"])
+    x, st = s.coarse_solve(increments=1, tol=1e-10)
+    xo, sto, _ = CS.solve(ops, dc, ph, increments=1, tol=1e-10)
+    xg = x.cpu().numpy()[rec]
+    u, p = slice(0, g.nu), g.p_slice
+    eu = rel(xg[u], xo[u])
+    ep = rel(xg[p] - xg[p].mean(), xo[p] - xo[p].mean())
+    _say("  gpu its", st["newton_its"], st["rc_rel"], "oracle its", sto.newton_its, "u err %.2e p err %.2e" % (eu, ep))
+    assert st["converged"] and sto.converged
+    assert eu <= tol and ep <= tol
+    s.close()

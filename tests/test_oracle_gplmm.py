@@ -243,3 +243,38 @@ def test_fragment_pocket_interface_is_merged_and_coarse_operator_regular():
     M = G.build(X, dc, origin_rhs(ops, ph))
     sv = np.linalg.svd(M.Ao, compute_uv=False)
     assert sv[-1] / sv[0] > 1e-8
+
+
+def test_aplmm_s_is_gplmm_with_zero_wind():
+    """Section 8: gPLMM_S = aPLMM_S.  With w = 0 the build matrix X = J~_0 is the Stokes
+    matrix whatever the tags (no inertia is left to remove), and so is the Newton Jacobian
+    at rest, so the three preconditioners are the same operator."""
+    from oracle.mac import jacobian
+    m, lab = _tiny_3d()
+    g, ops, dc, ph, X, bB = _case(m, lab, dt=None)
+    Xg = build_matrix(ops, ph, wind=None, tags=dc.tags)
+    Xs = build_matrix(ops, ph, wind=None, tags=None, )
+    Js = jacobian(ops, np.zeros(g.N), ph)
+    assert abs(Xg - Xs).max() == 0.0 and abs(Js - Xs).max() == 0.0
+    v = np.random.default_rng(2).standard_normal(g.N)
+    za = G.apply(G.build(Xg, dc, bB), v)
+    zb = G.apply(G.build(Js, dc, bB), v)
+    assert np.array_equal(za, zb)
+
+
+def test_aplmm_ns_from_the_newton_jacobian_converges():
+    """aPLMM_NS (the preconditioner rebuilt from the Newton Jacobian at the first
+    iterate) drives FGMRES to the same Newton solution as gPLMM and as exact solves."""
+    from oracle import newton
+    w = make_workload("disks2d_32", 1, re=10.0)
+    g = MacGrid(largest_component(w["mask"]))
+    ops = Operators(g)
+    dc = decompose(g, w["labels"])
+    ph = Phys(w["rho"], w["mu"], w["body"], None, dc.pin)
+    xg, sg = newton.solve(ops, dc, ph, tol=1e-12, lin_tol=1e-13)
+    xa, sa = newton.solve(ops, dc, ph, tol=1e-12, lin_tol=1e-13, build="jacobian")
+    xe, se = newton.solve(ops, dc, ph, tol=1e-13, precond="exact")
+    assert sg.converged and sa.converged
+    assert np.linalg.norm(xa - xe) <= 1e-9 * np.linalg.norm(xe)
+    assert np.linalg.norm(xg - xe) <= 1e-9 * np.linalg.norm(xe)
+    print("FGMRES its gPLMM %s, aPLMM_NS %s" % (sg.lin_its, sa.lin_its))
