@@ -164,6 +164,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-scale solver leg")
     ap.add_argument("--no-aplmm", action="store_true", help="skip the aPLMM_S / aPLMM_NS comparison solves")
+    ap.add_argument("--no-pnm", action="store_true", help="skip the gPNM (pore-network decomposition) solve")
     ap.add_argument("--coarse-increments", type=int, default=3,
                     help="body-force steps of the coarse-scale solver (one step from rest stalls at "
                          "128^3, as Algorithm 1 warns for starts far from the solution)")
@@ -364,6 +365,25 @@ def main():
                         "builds": sta["builds"], "converged": sta["converged"]}
             del sa
             torch.cuda.empty_cache()
+    if not args.no_pnm:
+        # the pore-network decomposition (Section 3.3): throat regions as primary grids,
+        # one interface per pore body; same preconditioner machinery (gPNM)
+        from synth import throat_labels
+        log("gPNM (pore-network decomposition) on the same workload ...")
+        th = throat_labels(w["mask"], w["labels"])
+        sp_ = Solver(w["mask"], th, rho=w["rho"], mu=w["mu"], body=w["body"], groups=w["labels"],
+                     precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart, lin_maxit=4000)
+        sp_.newton_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xp_, stp = sp_.newton_solve()
+        torch.cuda.synchronize()
+        out["gpnm"] = {"s": time.perf_counter() - t0, "primaries_throats": sp_.info()["Np"],
+                       "interfaces_pores": sp_.info()["Nc"], "newton_its": stp["newton_its"],
+                       "fgmres_its": stp["lin_its"], "fgmres_its_total": stp["lin_its_total"],
+                       "t_build_ms": stp["t_build_ms"], "converged": stp["converged"]}
+        del sp_
+        torch.cuda.empty_cache()
     if not args.no_variants:
         from synth import make_workload as _mk
         log("finer pore split (pores > 1000 voxels split) ...")

@@ -168,6 +168,20 @@ void gplmm_default_options(gplmm_options* opt);
 int gplmm_setup(const uint8_t* mask, const int32_t* pore_labels, double rho, double mu,
                 const double body[3], double dt, const gplmm_options* opt, gplmm_ctx** out);
 
+/* The pore-network decomposition (Section 3.3, the PNM variant of the preconditioner):
+ * the primary grids are throat regions and each contact interface sits in a pore body,
+ * shared by every throat that meets there.  throat_labels[v] > 0 on the fluid voxels (the
+ * throat regions, e.g. a watershed seeded at the pores' contact pixels); pore_labels[v] > 0
+ * on the fluid voxels (the pore decomposition): a cell carved by the rule of gplmm_setup
+ * applied to throat_labels joins the interface of its pore label (one interface per pore
+ * label present among the carved cells, numbered in label order).  Every other step (tags,
+ * dual grids, closures, coarse operator, smoothers) is that of gplmm_setup, so any
+ * build_matrix or wind option gives the corresponding gPNM / aPNM preconditioner.  Single
+ * images only.  Errors as gplmm_setup, and GPLMM_E_ARG for a carved cell without a
+ * positive pore label. */
+int gplmm_setup_pnm(const uint8_t* mask, const int32_t* throat_labels, const int32_t* pore_labels, double rho,
+                    double mu, const double body[3], double dt, const gplmm_options* opt, gplmm_ctx** out);
+
 /* A batch of independent samples in one context (many samples of uneven size solved
  * together: every kernel launch covers all subdomains of all samples).  Sample s is the
  * host image masks[s] / labels[s] of dims[3s..3s+2] = (nx, ny, nz) voxels (nz = 1 for 2D;

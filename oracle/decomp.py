@@ -207,7 +207,14 @@ def free_faces(g, owner, walled):
     return out
 
 
-def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
+def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None, groups=None):
+    """Primary grids, contact interfaces, tags and dual grids from the pore labels.
+
+    ``groups`` (an image of positive labels, the pore decomposition of the same void):
+    the pore-network decomposition of Section 3.3, in which ``labels`` are the throat
+    regions and every interface cell joins the interface of the pore that contains it
+    (one contact interface per pore body, shared by all the throats that meet there),
+    instead of one interface per pair of touching labels."""
     if dual_dilations is None:
         dual_dilations = 1 if g.ndim == 2 else 0
     lab_grid = np.asarray(labels)
@@ -222,7 +229,16 @@ def decompose(g: MacGrid, labels, tag_layers=1, dual_dilations=None):
     nc = g.nc
     # --- carving
     is_if, minlow = carve(L, nbr)
-    pr = np.stack([minlow[is_if], L[is_if]], 1)
+    if groups is None:
+        pr = np.stack([minlow[is_if], L[is_if]], 1)
+    else:
+        grp = np.asarray(groups)
+        if grp.ndim == 2:
+            grp = grp[None]
+        G = grp.ravel()[cells].astype(np.int64)
+        if np.any(G[is_if] <= 0):
+            raise ValueError("every interface cell needs a positive group label")
+        pr = np.stack([G[is_if], np.zeros(int(is_if.sum()), dtype=np.int64)], 1)
     upairs, inv = np.unique(pr, axis=0, return_inverse=True)
     iface = np.full(nc, -1, dtype=np.int64)
     iface[is_if] = inv.ravel()

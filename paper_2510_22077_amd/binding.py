@@ -90,7 +90,7 @@ EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_setup_batch", "gplmm_b
            "gplmm_mlp_forward", "gplmm_mlp_grad", "gplmm_mlp_adam", "gplmm_mlp_train", "gplmm_mlp_last_error",
            "gplmm_mlp_destroy", "gplmm_set_coarse_model", "gplmm_coarse_entries",
            "gplmm_autotune", "gplmm_set_tuning", "gplmm_set_progress", "gplmm_sample_residuals_noalloc",
-           "gplmm_coarse_default_options", "gplmm_coarse_solve"]
+           "gplmm_coarse_default_options", "gplmm_coarse_solve", "gplmm_setup_pnm"]
 
 _lib = None
 
@@ -112,6 +112,9 @@ def load():
     lib.gplmm_setup.argtypes = [P, P, D, D, ctypes.POINTER(ctypes.c_double), D, ctypes.POINTER(Options),
                                 ctypes.POINTER(ctypes.c_void_p)]
     lib.gplmm_setup.restype = I
+    lib.gplmm_setup_pnm.argtypes = [P, P, P, D, D, ctypes.POINTER(ctypes.c_double), D, ctypes.POINTER(Options),
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    lib.gplmm_setup_pnm.restype = I
     lib.gplmm_setup_batch.argtypes = [I, P, P, P, P, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]
     lib.gplmm_setup_batch.restype = I
     lib.gplmm_batch_info.argtypes = [P, ctypes.POINTER(ctypes.c_int), P, P, P, P]
@@ -201,7 +204,9 @@ def _ptr(t):
 class Solver:
     """One gplmm context (one sample, one stream)."""
 
-    def __init__(self, mask, labels, rho=1.0, mu=1.0, body=(1.0, 0.0, 0.0), dt=0.0, **kw):
+    def __init__(self, mask, labels, rho=1.0, mu=1.0, body=(1.0, 0.0, 0.0), dt=0.0, groups=None, **kw):
+        """groups: pore labels for the pore-network decomposition (gplmm_setup_pnm), in which
+        ``labels`` are the throat regions; None for the pore decomposition (gplmm_setup)."""
         mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
         if mask.ndim == 2:
@@ -213,8 +218,14 @@ class Solver:
         o = self._prepare(nx, ny, nz, **kw)
         b = (ctypes.c_double * 3)(*[float(v) for v in body])
         ctx = ctypes.c_void_p()
-        rc = self.lib.gplmm_setup(mask.ctypes.data, labels.ctypes.data, float(rho), float(mu), b, float(dt),
-                                  ctypes.byref(o), ctypes.byref(ctx))
+        if groups is None:
+            rc = self.lib.gplmm_setup(mask.ctypes.data, labels.ctypes.data, float(rho), float(mu), b, float(dt),
+                                      ctypes.byref(o), ctypes.byref(ctx))
+        else:
+            grp = np.ascontiguousarray(np.asarray(groups, dtype=np.int32).reshape(mask.shape))
+            self._groups = grp
+            rc = self.lib.gplmm_setup_pnm(mask.ctypes.data, labels.ctypes.data, grp.ctypes.data, float(rho),
+                                          float(mu), b, float(dt), ctypes.byref(o), ctypes.byref(ctx))
         self._finish(ctx, rc, "gplmm_setup")
         self.shape = mask.shape
 

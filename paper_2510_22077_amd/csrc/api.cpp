@@ -817,6 +817,26 @@ int gplmm_setup(const uint8_t* mask, const int32_t* labels, double rho, double m
     return rc;
 }
 
+int gplmm_setup_pnm(const uint8_t* mask, const int32_t* throat_labels, const int32_t* pore_labels, double rho,
+                    double mu, const double body[3], double dt, const gplmm_options* opt, gplmm_ctx** out) {
+    if (!mask || !throat_labels || !pore_labels || !opt || !out || !body) return GPLMM_E_ARG;
+    *out = nullptr;
+    gplmm_ctx* c = new gplmm_ctx();
+    c->opt = *opt;
+    *out = c;
+    int rc = check_options(c, opt, rho, mu);
+    if (rc != GPLMM_OK) return rc;
+    set_dims(c, opt->nx, opt->ny, opt->nz);
+    c->phys = Phys{rho, mu, {body[0], body[1], c->ndim == 3 ? body[2] : 0.0}, dt > 0 ? dt : 0.0};
+    c->stream = (hipStream_t)opt->stream;
+    c->setup_groups = pore_labels;
+    rc = build_decomposition(c, mask, throat_labels);
+    c->setup_groups = nullptr;
+    c->samples.assign(1, SampleGeo{0, 0, c->nx, c->ny, c->nz, 0, 0});
+    if (rc == GPLMM_OK) rc = finish_setup(c);
+    return rc;
+}
+
 int gplmm_setup_batch(int nsamples, const uint8_t* const* masks, const int32_t* const* labels, const int32_t* dims,
                       const double* rho, const double* mu, const double* body, const double* dt,
                       const gplmm_options* opt, gplmm_ctx** out) {

@@ -98,6 +98,7 @@ struct gplmm_ctx {
     std::vector<std::vector<int32_t>> icells;      // cells of each interface
     std::vector<std::vector<int32_t>> dual_cells;  // cells of each dual grid
     std::vector<int32_t> ycol;        // primary -> coarse y column (or -1)
+    const int32_t* setup_groups = nullptr;   // interface groups during gplmm_setup_pnm only
 
     // ---- local problems
     int tile = 32;

@@ -132,17 +132,28 @@ int build_decomposition(gplmm_ctx* c, const uint8_t* mask, const int32_t* labels
     // an a-face "at" cell q is its lower a-face; active iff the lower neighbour is fluid
     auto face_active = [&](int64_t q, int a) { return q >= 0 && NB(q, a, 0) >= 0; };
     carve();
-    // ---- interfaces: sorted (lower label, own label) pairs
+    // ---- interfaces: sorted (lower label, own label) pairs; with interface groups (the
+    // pore-network decomposition of Section 3.3) one interface per group label instead
+    std::vector<int64_t> G;
+    if (c->setup_groups) {
+        G.assign(nc, 0);
+        for (int64_t q = 0; q < nc; ++q) {
+            G[q] = c->setup_groups[c->cell_voxel[q]];
+            if (is_if[q] && G[q] <= 0) return fail(c, GPLMM_E_ARG, "an interface cell has a non-positive group label");
+        }
+    }
+    auto key_of = [&](int64_t q) {
+        return G.empty() ? std::make_pair(minlow[q], L[q]) : std::make_pair(G[q], (int64_t)0);
+    };
     std::vector<std::pair<int64_t, int64_t>> pairs;
     for (int64_t q = 0; q < nc; ++q)
-        if (is_if[q]) pairs.push_back({minlow[q], L[q]});
+        if (is_if[q]) pairs.push_back(key_of(q));
     std::sort(pairs.begin(), pairs.end());
     pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
     c->iface.assign(nc, -1);
     for (int64_t q = 0; q < nc; ++q)
         if (is_if[q])
-            c->iface[q] = (int32_t)(std::lower_bound(pairs.begin(), pairs.end(),
-                                                     std::make_pair(minlow[q], L[q])) - pairs.begin());
+            c->iface[q] = (int32_t)(std::lower_bound(pairs.begin(), pairs.end(), key_of(q)) - pairs.begin());
     // ---- degenerate interfaces: touched by no primary cell, or only by primary pieces that touch
     // no other interface (a dead-end pocket seen by the rest of the void only through faces
     // between interface cells, which the coarse space leaves at zero; a piece is a face-connected

@@ -11,8 +11,8 @@ are not available, so random disk / sphere packings of similar structure stand
 in for them.
 """
 from .packing import disk_packing_rsa, boolean_packing, channel
-from .watershed import watershed_labels
+from .watershed import watershed_labels, throat_labels
 from .workloads import make_workload, make_batch, WORKLOADS
 
 __all__ = ["disk_packing_rsa", "boolean_packing", "channel",
-           "watershed_labels", "make_workload", "make_batch", "WORKLOADS"]
+           "watershed_labels", "throat_labels", "make_workload", "make_batch", "WORKLOADS"]

@@ -203,3 +203,58 @@ def watershed_labels(mask, footprint=5, h_min=1.0, min_size=0, periodic_x=True,
     remap = np.zeros(int(lab.max()) + 1, dtype=np.int32)
     remap[order] = np.arange(1, order.size + 1, dtype=np.int32)
     return remap[lab].astype(np.int32)
+
+
+def throat_labels(mask, pore_labels, periodic_x=True):
+    """Throat regions for the pore-network decomposition (Section 3.3 of the paper: the
+    watershed is seeded at the interface pixels of the pore decomposition, so that its
+    regions are the constrictions and their meeting places lie in the pore bodies).
+
+    Seeds: the void voxels with a face neighbour of another pore label, one marker per
+    face-connected set of such voxels on the same pair of pores; the markers are grown
+    through the void breadth-first (ties in arrival order) until they meet.  Returns
+    labels 1..Nt on the void voxels (0 on grains), numbered in raster order of first
+    appearance."""
+    mask = np.asarray(mask).astype(bool)
+    lab = np.asarray(pore_labels).astype(np.int64)
+    if mask.ndim == 2:
+        mask, lab = mask[None], lab[None]
+    vox, nb = _neighbours(mask, periodic_x)
+    lv = lab.ravel()[vox]
+    nbl = np.where(nb >= 0, lv[np.maximum(nb, 0)], 0)
+    other = (nb >= 0) & (nbl != lv[:, None]) & (nbl > 0)
+    seed = other.any(1)
+    # the pair of pores a seed voxel sits between: its own label and its smallest other
+    big = np.iinfo(np.int64).max
+    partner = np.where(other, nbl, big).min(1)
+    key = np.minimum(lv, partner) * (lab.max() + 1) + np.maximum(lv, partner)
+    # components of seed voxels with the same pair
+    sidx = np.flatnonzero(seed)
+    pos = np.full(vox.size, -1, dtype=np.int64)
+    pos[sidx] = np.arange(sidx.size)
+    rows, cols = [], []
+    for e in range(nb.shape[1]):
+        u = nb[sidx, e]
+        ok = (u >= 0) & seed[np.maximum(u, 0)]
+        ok &= key[np.maximum(u, 0)] == key[sidx]
+        rows.append(pos[sidx[ok]])
+        cols.append(pos[u[ok]])
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    n = sidx.size
+    _, comp = connected_components(csr_matrix((np.ones(r.size), (r, c)), shape=(n, n)), directed=False)
+    markers = np.zeros(mask.size, dtype=np.int64)
+    markers[vox[sidx]] = comp + 1
+    out = _flood(np.zeros(mask.shape), markers.reshape(mask.shape), mask, periodic_x)
+    orphan = mask & (out == 0)
+    if orphan.any():
+        conn = ndi.generate_binary_structure(3, 1)
+        ol, _ = ndi.label(orphan, structure=conn)
+        out = np.where(orphan, ol + out.max(), out)
+    u, first = np.unique(out.ravel(), return_index=True)
+    u, first = u[u > 0], first[u > 0]
+    order = u[np.argsort(first)]
+    remap = np.zeros(int(out.max()) + 1, dtype=np.int32)
+    remap[order] = np.arange(1, order.size + 1, dtype=np.int32)
+    return remap[out].astype(np.int32)
