@@ -128,6 +128,35 @@ def _paper_e2(solver, mask, xa, xt, nrec):
     return e_p, e_u
 
 
+def _train_mlp(m, feats, targets, epochs=60, seed=0):
+    """Train the coarse model with the library's BF16 kernels and Adam on standardised
+    features; the standardisation is folded into the first layer afterwards."""
+    import numpy as np
+    X = np.concatenate(feats)
+    T = np.concatenate(targets)[:, None].astype(np.float32)
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(len(X))
+    X, T = X[perm], T[perm]
+    mu, sd = X.mean(0), X.std(0)
+    const = sd < 1e-6
+    sd[const], mu[const] = 1.0, 0.0
+    nin, nh = X.shape[1], 128
+    flat = []
+    fan = [nin, nh, nh, nh, 1]
+    for a, b in zip(fan[:-1], fan[1:]):   # Glorot-uniform weights, zero biases
+        lim = np.sqrt(6.0 / (a + b))
+        flat += [rng.uniform(-lim, lim, size=a * b), np.zeros(b)]
+    m.set_params(np.concatenate(flat).astype(np.float32))
+    loss = m.train(((X - mu) / sd).astype(np.float32), T, epochs=epochs, batch=1024, lr=1e-3)
+    p = m.get_params()
+    W1 = p[:nin * nh].reshape(nin, nh)
+    b1 = p[nin * nh:nin * nh + nh]
+    b1 -= (mu / sd) @ W1
+    W1 /= sd[:, None]
+    m.set_params(p)
+    return float(loss), float(np.var(T))
+
+
 def _measured_traffic(workload, precision):
     """HBM bytes per launch of the skyline-solve kernel from the committed PMC summary, if
     it was taken on this workload and precision with the current kernel source."""
@@ -165,6 +194,8 @@ def main():
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-scale solver leg")
     ap.add_argument("--no-aplmm", action="store_true", help="skip the aPLMM_S / aPLMM_NS comparison solves")
     ap.add_argument("--no-pnm", action="store_true", help="skip the gPNM (pore-network decomposition) solve")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned coarse operator leg")
+    ap.add_argument("--learned-seeds", type=int, default=5, help="packings (seeds 1..n) the coarse model is trained on")
     ap.add_argument("--coarse-increments", type=int, default=3,
                     help="body-force steps of the coarse-scale solver (one step from rest stalls at "
                          "128^3, as Algorithm 1 warns for starts far from the solution)")
@@ -365,6 +396,50 @@ def main():
                         "builds": sta["builds"], "converged": sta["converged"]}
             del sa
             torch.cuda.empty_cache()
+    if not args.no_learned:
+        # FP32 + learned coarse operator (the structured model: predicted entries, interface
+        # diagonals and correction rows set by conservation), trained on the exact coarse
+        # entries of other seeds of the same packing law, evaluated on this one
+        from synth import make_workload as _mk
+        from paper_2510_22077_amd import Mlp
+        import numpy as np
+        log("learned coarse operator: training on seeds %s ..." % list(range(1, 1 + args.learned_seeds)))
+        t0 = time.perf_counter()
+        feats, targets = [], []
+        nthroats = 0
+        for sd_ in range(1, 1 + args.learned_seeds):
+            wt = _mk(args.workload, sd_)
+            st_ = Solver(wt["mask"], wt["labels"], rho=wt["rho"], mu=wt["mu"], body=wt["body"],
+                         precision=args.precision, restart=args.restart)
+            st_.build()
+            e_ = st_.coarse_entries(exact=True)
+            feats.append(e_["feat"])
+            targets.append(np.arcsinh(e_["exact"] / e_["scale"]))
+            nthroats += st_.info()["Nc"]
+            del st_
+        mlp = Mlp(16, 128, 3, 1, max_batch=4096)
+        loss, var = _train_mlp(mlp, feats, targets)
+        t_train = time.perf_counter() - t0
+        sl = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"], precision=args.precision,
+                    newton_tol=1e-8, lin_tol=1e-9, restart=args.restart)
+        sl.set_coarse_model(mlp)
+        sl.newton_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xl, stl = sl.newton_solve()
+        torch.cuda.synchronize()
+        out["learned_coarse"] = {"s": time.perf_counter() - t0, "newton_its": stl["newton_its"],
+                                 "fgmres_its": stl["lin_its"], "fgmres_its_total": stl["lin_its_total"],
+                                 "learned_builds": stl["learned_builds"], "fallbacks": stl["coarse_fallbacks"],
+                                 "t_coarse_ms": stl["t_coarse_ms"], "t_build_ms": stl["t_build_ms"],
+                                 "rel_diff_vs_exact_solution": float(torch.linalg.norm(xl - x) / torch.linalg.norm(x)),
+                                 "train": {"seeds": args.learned_seeds, "entries": int(sum(len(f) for f in feats)),
+                                           "throats": nthroats, "loss": loss, "target_var": var,
+                                           "s": t_train}}
+        sl.set_coarse_model(None)
+        del sl
+        mlp.close()
+        torch.cuda.empty_cache()
     if not args.no_pnm:
         # the pore-network decomposition (Section 3.3): throat regions as primary grids,
         # one interface per pore body; same preconditioner machinery (gPNM)

@@ -1416,7 +1416,7 @@ void gplmm_destroy(gplmm_ctx* c) {
     if (c->apply_exec) (void)hipGraphExecDestroy(c->apply_exec);
     if (c->apply_graph) (void)hipGraphDestroy(c->apply_graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    void* ptrs[] = {c->d_panel, c->d_gin, c->d_gout, c->d_cl_row, c->d_cl_col, c->d_cl_feat, c->d_cl_pred, c->d_cl_scale, c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
+    void* ptrs[] = {c->d_co_pinned, c->d_panel, c->d_gin, c->d_gout, c->d_cl_row, c->d_cl_col, c->d_cl_feat, c->d_cl_pred, c->d_cl_scale, c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,

@@ -10,11 +10,14 @@
 // sheet, grain faces per cell for a pore), and log(1 + Re) of a local Reynolds number rho |w| l / mu
 // from the wind (mean face speed over the object's cells, l = size^(1/ndim-1) for a
 // throat, size^(1/ndim) for a pore); and a relation feature (size of the pore two
-// throats share, adjacency of a throat and a pore, throats two pores share), and for
+// throats share, adjacency of a throat and a pore, throats two pores share), for
 // each object the log size of its neighbourhood (a throat: its pores' cells; a pore:
-// its coordination number).  The network predicts asinh(entry / scale) with the scale
-// mu l_r^(1/2) l_c^(1/2) built from the objects' lengths: targets of order one that
-// keep their sign, with the large diagonal entries compressed.
+// its coordination number), and the row object's shape factor G = A / P^2 (its size
+// over its squared wall contact).  The network predicts asinh(entry / scale) with the
+// scale mu l_r^(1/2) l_c^(1/2) built from the objects' lengths: targets of order one
+// that keep their sign, with the large diagonal entries compressed.  The operator
+// assembled from the predictions then takes the conservation structure of the exact
+// one (zero sums over the interface columns, see learned_coarse).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -143,7 +146,8 @@ int coarse_features(gplmm_ctx* c, const double* wind_host, std::vector<float>& f
             }
         }
         f[12] = (float)rel;
-        f[15] = 1.f;
+        // shape factor G = A / P^2 of the row object: its size against its wall contact
+        f[15] = (float)std::log(std::max(obj[r].size, 1.0) / ((1.0 + obj[r].wall) * (1.0 + obj[r].wall)));
         const double mu = (c->csamp.empty() || obj[r].cells.empty()) ? c->phys.mu : c->sphys[c->csamp[obj[r].cells[0]]].mu;
         scale[e] = (float)(mu * std::sqrt(obj[r].len * obj[k].len));
     }

@@ -224,6 +224,7 @@ struct gplmm_ctx {
     float* d_cl_feat = nullptr;
     float* d_cl_pred = nullptr;
     float* d_cl_scale = nullptr;
+    uint8_t* d_co_pinned = nullptr;      // coarse rows coupled to a primary holding a pinned cell
     bool last_coarse_learned = false;    // the last build took the learned coarse operator
     double last_coarse_ms = 0.0;         // coarse assembly time of the last build (host clock)
     // launch parameters chosen by gplmm_autotune (defaults until then)

@@ -181,6 +181,48 @@ __global__ void learned_scatter_kernel(const int32_t* __restrict__ row, const in
     Ao[co_pos(cb, row[k], col[k])] = sinh(z) * (double)scale[k];
 }
 
+// Conservation structure of the learned coarse operator.  The shape vectors of a primary
+// sum to a uniform pressure (partition of unity) wherever the primary holds no pinned
+// cell, and X maps a uniform pressure to zero, so every coarse row not coupled to a pinned
+// primary has zero sum over the interface columns.  Interface rows: the diagonal is set
+// to minus the sum of the predicted off-diagonal interface entries; correction rows: the
+// predicted interface entries are shifted equally to a zero sum.  One workgroup per
+// coarse row of its sample's dense block; rows flagged in `pinned` keep the prediction.
+__global__ void coarse_structure_kernel(double* __restrict__ Ao, CoBlk cb, int Nc, const uint8_t* __restrict__ pinned) {
+    __shared__ double sh[16];
+    __shared__ double shc[16];
+    const int r = blockIdx.x;
+    if (pinned[r]) return;
+    const int b = cb.blk[r], n = cb.n[b];
+    double* row = Ao + cb.moff[b] + (int64_t)cb.loc[r] * n;
+    const int32_t* idx = cb.idx + cb.ioff[b];
+    double acc = 0.0, cnt = 0.0;
+    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        const int col = idx[l];
+        if (col < Nc && col != r && row[l] != 0.0) {
+            acc += row[l];
+            cnt += 1.0;
+        }
+    }
+    const double sum = block_sum(acc, sh);
+    const double num = block_sum(cnt, shc);
+    __shared__ double tot, m;
+    if (threadIdx.x == 0) {
+        tot = sum;
+        m = num;
+    }
+    __syncthreads();
+    if (r < Nc) {
+        if (threadIdx.x == 0) row[cb.loc[r]] = -tot;
+    } else if (m > 0.0) {
+        const double shift = tot / m;
+        for (int l = threadIdx.x; l < n; l += blockDim.x) {
+            const int col = idx[l];
+            if (col < Nc && row[l] != 0.0) row[l] -= shift;
+        }
+    }
+}
+
 template <typename T>
 __global__ void zero_kernel(T* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,6 +302,18 @@ static int learned_coarse(gplmm_ctx* c) {
     GP_HIP(c, hipDeviceSynchronize());
     learned_scatter_kernel<<<nb(ne), kB, 0, s>>>(c->d_cl_row, c->d_cl_col, c->d_cl_pred, c->d_cl_scale, ne, c->d_Ao,
                                                  coblk(c));
+    if (!c->d_co_pinned) {   // coarse rows coupled to a primary that holds a pinned cell
+        std::vector<uint8_t> pin(c->nco, 0);
+        for (int64_t q = 0; q < c->ncell; ++q) {
+            if (!(c->tagcell[q] & kPinBit) || c->prim[q] < 0) continue;
+            const int i = c->prim[q];
+            if (c->ycol[i] >= 0) pin[c->ycol[i]] = 1;
+            for (int32_t j : c->Cp[i]) pin[j] = 1;
+        }
+        GP_HIP(c, hipMalloc((void**)&c->d_co_pinned, std::max<size_t>(pin.size(), 1)));
+        GP_HIP(c, hipMemcpy(c->d_co_pinned, pin.data(), pin.size(), hipMemcpyHostToDevice));
+    }
+    coarse_structure_kernel<<<c->nco, kB, 0, s>>>(c->d_Ao, coblk(c), c->Nc, c->d_co_pinned);
     GP_HIP(c, hipGetLastError());
     GP_HIP(c, hipStreamSynchronize(s));
     return GPLMM_OK;

@@ -64,39 +64,52 @@ def test_a_model_giving_a_singular_operator_falls_back_to_the_exact_one():
     m.close()
 
 
-def test_trained_model_gain_against_the_exact_operator():
-    torch = _torch()
-    from paper_2510_22077_amd import Mlp
+def _train(m, feats, targets, epochs=150, seed=0):
+    """Standardise the features, train with the library's Adam, fold the standardisation
+    into the first layer; returns the last mean batch loss."""
     from oracle import mlp as R
-    feats, targets = [], []
-    for seed in (0, 1, 2, 3):
-        s = _solver("spheres3d_24", seed)
-        s.newton_solve()
-        e = s.coarse_entries(exact=True)
-        feats.append(e["feat"])
-        targets.append(np.arcsinh(e["exact"] / e["scale"]))
-        s.close()
     X = np.concatenate(feats)
     T = np.concatenate(targets)[:, None].astype(np.float32)
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     perm = rng.permutation(len(X))
     X, T = X[perm], T[perm]
     mu = X.mean(0)
     sd = X.std(0)
     const = sd < 1e-6
     sd[const], mu[const] = 1.0, 0.0
-    m = Mlp(16, 128, 3, 1, max_batch=2048)
     params = R.init_params(16, 128, 3, 1, rng)
     m.set_params(np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params]).astype(np.float32))
-    loss = m.train(((X - mu) / sd).astype(np.float32), T, epochs=150, batch=512, lr=1e-3)
-    # fold the feature standardisation into the first layer
+    loss = m.train(((X - mu) / sd).astype(np.float32), T, epochs=epochs, batch=512, lr=1e-3)
     flat = m.get_params()
     W1 = flat[:16 * 128].reshape(16, 128)
     b1 = flat[16 * 128:16 * 128 + 128]
     b1 -= (mu / sd) @ W1
     W1 /= sd[:, None]
     m.set_params(flat)
-    s = _solver_tight("spheres3d_24", 5)
+    return loss, float(np.var(T))
+
+
+def test_trained_model_gain_against_the_exact_operator():
+    """Train on the exact coarse entries of six packings, evaluate on a seventh: the
+    learned operator has the exact one's conservation structure (zero sums over the
+    interface columns away from the pinned primary), the solve converges to the FP64
+    outer tolerance and matches the exact-operator solution, and the gain is measured.
+    Measured: the structured model needs more FGMRES iterations than the exact operator
+    (it replaces an assembly that costs a few ms with an approximation), so the recorded
+    outcome is a loss, and the test asserts that sign."""
+    torch = _torch()
+    from paper_2510_22077_amd import Mlp
+    feats, targets = [], []
+    for seed in range(1, 7):
+        s = _solver("spheres3d_48", seed)
+        s.newton_solve()
+        e = s.coarse_entries(exact=True)
+        feats.append(e["feat"])
+        targets.append(np.arcsinh(e["exact"] / e["scale"]))
+        s.close()
+    m = Mlp(16, 128, 3, 1, max_batch=2048)
+    loss, var = _train(m, feats, targets)
+    s = _solver_tight("spheres3d_48", 0)
     x_exact, st_exact = s.newton_solve()
     e = s.coarse_entries(exact=True)
     z = m.forward(e["feat"]).cpu().numpy()[:, 0]
@@ -104,14 +117,25 @@ def test_trained_model_gain_against_the_exact_operator():
     r2 = 1.0 - np.mean((z - zt) ** 2) / np.var(zt)
     s.set_coarse_model(m)
     x_l, st_l = s.newton_solve()
-    print("train loss %.3f (target var %.3f); unseen geometry: R2 %.3f" % (loss, float(np.var(T)), r2))
-    print("exact:   newton %d, fgmres %s, coarse assembly %.2f ms, total %.1f ms"
-          % (st_exact["newton_its"], st_exact["lin_its"], st_exact["t_coarse_ms"], st_exact["t_total_ms"]))
-    print("learned: newton %d, fgmres %s, coarse assembly %.2f ms, total %.1f ms, learned builds %d, fallbacks %d"
-          % (st_l["newton_its"], st_l["lin_its"], st_l["t_coarse_ms"], st_l["t_total_ms"], st_l["learned_builds"],
+    # the learned operator of the last learned build keeps the conservation structure
+    A = s.coarse_operator()
+    Nc = s.info()["Nc"]
+    print("train loss %.3f (target var %.3f) on %d entries; unseen geometry: R2 %.3f" % (loss, var, sum(len(f) for f in feats), r2))
+    print("exact:   newton %d, fgmres %s (%d), total %.1f ms"
+          % (st_exact["newton_its"], st_exact["lin_its"], st_exact["lin_its_total"], st_exact["t_total_ms"]))
+    print("learned: newton %d, fgmres %s (%d), total %.1f ms, learned builds %d, fallbacks %d"
+          % (st_l["newton_its"], st_l["lin_its"], st_l["lin_its_total"], st_l["t_total_ms"], st_l["learned_builds"],
              st_l["coarse_fallbacks"]))
-    assert st_l["converged"]
-    assert loss < 0.5 * float(np.var(T))
+    assert st_l["converged"] and st_l["learned_builds"] >= 1
+    assert loss < 0.5 * var
     assert _rel(x_l.cpu().numpy(), x_exact.cpu().numpy()) <= 1e-8
+    if st_l["coarse_fallbacks"] == 0:
+        rs = A[:, :Nc].sum(1)
+        scale = np.abs(A[:, :Nc]).max(1) + 1e-300
+        frac_zero = np.mean(np.abs(rs) <= 1e-9 * scale)
+        print("rows with zero interface-column sums: %.3f" % frac_zero)
+        assert frac_zero >= 0.8
+    # the measured sign: no gain in iterations over the exact operator
+    assert st_l["lin_its_total"] >= st_exact["lin_its_total"]
     s.set_coarse_model(None)
     m.close()
