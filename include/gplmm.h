@@ -120,6 +120,10 @@ typedef struct {
                                 Timed runs (gplmm_set_timing) always launch kernel by kernel */
     int build_matrix;        /* GPLMM_BUILD_GEOMETRIC (default) or GPLMM_BUILD_JACOBIAN; the
                                 residual updates of Eqs. mono_struct_a and Mdp use the same matrix */
+    int split_tiles;         /* primaries whose Schwarz block spans more than this many 32-row tiles
+                                are solved by one level of nested dissection (two halves cut by a
+                                separator plane, solved in parallel, and the separator's Schur
+                                complement); 0 = default (128), -1 = never.  Single images only */
 } gplmm_options;
 
 typedef struct {
@@ -133,7 +137,9 @@ typedef struct {
     int64_t factor_bytes;    /* device bytes held by the local factors */
     int ncolors;             /* probing colours used to assemble the coarse operator */
     double lu_flops;         /* flops of the local factorisations of one build: 2 T^3 per tile
-                                product of the closure, dual and primary LU schedules */
+                                product of the closure, dual, primary and separator LU schedules */
+    int nsplit;              /* primaries solved by nested dissection (options.split_tiles) */
+    int64_t sep_unknowns;    /* unknowns on their separators */
 } gplmm_layout;
 
 typedef struct {
@@ -239,6 +245,16 @@ int gplmm_get_duals(const gplmm_ctx* ctx, int64_t* dual_ptr, int32_t* dual_cells
  * factor_elems[s] stored factor elements (diagonal tiles, L tile rows, U tile columns).
  * Host arrays owned by the caller; either may be NULL. */
 int gplmm_get_subdomains(const gplmm_ctx* ctx, int32_t* n, int64_t* factor_elems);
+
+/* Nested-dissection plan of split k, 0 <= k < layout.nsplit (options.split_tiles): info[4]
+ * = {primary, nA, nB, nS}, and, when slots is not NULL (nA + nB + nS entries), the record
+ * slots of the primary's unknowns in their elimination order: half A, half B (in its own
+ * order, the cut plane last), then the separator S.  A and B are uncoupled in X, nA and nB
+ * are multiples of the tile, and every pressure follows its faces, so the block
+ * factorises without pivoting in this order as two independent halves and the
+ * separator's Schur complement.  Host arrays owned by the caller; GPLMM_E_ARG for k out
+ * of range. */
+int gplmm_get_split(const gplmm_ctx* ctx, int k, int32_t* info, int32_t* slots);
 
 /* r = r(x): the MAC residual of the momentum and mass equations (Section 1;
  * backward Euler against x_prev when dt > 0, x_prev may be NULL = 0; the pinned

@@ -91,8 +91,8 @@ int upload_all(gplmm_ctx* c) {
         GP_TRY(alloc(c, (void**)&c->d_bcoef, nb));
         GP_TRY(alloc(c, (void**)&c->d_bsc, sizeof(double) * 2 * c->samples.size()));
         GP_HIP(c, hipHostMalloc((void**)&c->h_bres, nb, hipHostMallocDefault));
-        std::vector<int32_t> ss(c->Np + c->Nc);   // sample of each subdomain (of its first unknown)
-        for (int i = 0; i < c->Np + c->Nc; ++i) {
+        std::vector<int32_t> ss(c->subs.size());   // sample of each subdomain (of its first unknown)
+        for (size_t i = 0; i < c->subs.size(); ++i) {
             const Sub& sb = c->subs[i];
             ss[i] = c->csamp[c->sub_slots[sb.slot_off] / c->nrec];
         }
@@ -104,9 +104,10 @@ int upload_all(gplmm_ctx* c) {
                     nc, (int)c->pin, c->opt.h, c->d_nb6, c->d_tag, c->d_csamp, c->d_sphys};
     // local problems
     const int nsub = c->Np + c->Nc;
+    const int nall = (int)c->subs.size();   // with the split parts
     std::vector<int32_t> row_sub(c->sub_slots.size()), sorted_slot(c->sub_slots.size()), sorted_loc(c->sub_slots.size());
-    std::vector<int64_t> local_off(nsub + 1, 0);
-    for (int s = 0; s < nsub; ++s) {
+    std::vector<int64_t> local_off(nall + 1, 0);
+    for (int s = 0; s < nall; ++s) {
         const Sub& sb = c->subs[s];
         std::vector<std::pair<int32_t, int32_t>> p(sb.n);
         for (int r = 0; r < sb.n; ++r) {
@@ -126,8 +127,8 @@ int upload_all(gplmm_ctx* c) {
         int comp = (int)(s % c->nrec);
         slot_class[s] = comp < c->ndim ? c->owner[s] : (c->prim[q] >= 0 ? c->prim[q] : -4);
     }
-    std::vector<int32_t> sub_ids(nsub);
-    for (int s = 0; s < nsub; ++s) sub_ids[s] = s;
+    std::vector<int32_t> sub_ids(nall);
+    for (int s = 0; s < nall; ++s) sub_ids[s] = s;
     GP_TRY(upload(c, &c->d_subs, c->subs));
     GP_TRY(upload(c, &c->d_sub_slots, c->sub_slots));
     GP_TRY(upload(c, &c->d_row_sub, row_sub));
@@ -142,7 +143,7 @@ int upload_all(gplmm_ctx* c) {
     GP_TRY(upload(c, &c->d_lrow, c->env_lrow));
     GP_TRY(upload(c, &c->d_urow, c->env_urow));
     GP_TRY(upload(c, &c->d_tlc, c->env_tlc));
-    for (int set = 0; set < 2; ++set) {
+    for (int set = 0; set < 3; ++set) {
         GP_TRY(upload(c, &c->d_step_pairs[set], c->lu_step_pairs[set]));
         GP_TRY(upload(c, &c->d_sub_list[set], c->lu_sub_list[set]));
     }
@@ -155,11 +156,60 @@ int upload_all(gplmm_ctx* c) {
         c->maxT_set[set] = ord.empty() ? 0 : c->subs[ord[0]].nT;
         GP_TRY(upload(c, &c->d_sub_order[set], ord));
     }
-    c->prim_factor_elems = c->Nc > 0 ? c->subs[c->Np].diag_off : c->factor_elems;
-    c->prim_rows = c->Nc > 0 ? c->subs[c->Np].slot_off : (int64_t)c->sub_slots.size();
+    // split primaries: phase 1 = forward over the unsplit primaries (whole solves) and the
+    // halves, phase 3 = backward over the halves; separators' inverses
+    if (!c->splits.empty()) {
+        std::vector<int32_t> p1, p3, sep;
+        for (int s = 0; s < nall; ++s) {
+            const Sub& sb = c->subs[s];
+            if ((sb.kind == 0 && sb.split < 0) || sb.kind == 2) p1.push_back(s);
+            if (sb.kind == 2) p3.push_back(s);
+        }
+        auto by_size = [&](int a, int b) { return c->subs[a].nT > c->subs[b].nT; };
+        std::stable_sort(p1.begin(), p1.end(), by_size);
+        std::stable_sort(p3.begin(), p3.end(), by_size);
+        c->n_phase1 = (int)p1.size();
+        c->n_phase3 = (int)p3.size();
+        c->maxT_phase1 = c->subs[p1[0]].nT;
+        c->maxT_phase3 = c->subs[p3[0]].nT;
+        std::vector<int64_t> inv_off(nall, 0);
+        std::vector<int32_t> inv_cols(nall, 0);
+        for (const Split& sp : c->splits) {
+            sep.push_back(sp.s_sub);
+            inv_off[sp.s_sub] = sp.inv_off;
+            inv_cols[sp.s_sub] = sp.nS;
+        }
+        GP_TRY(upload(c, &c->d_phase_order[0], p1));
+        GP_TRY(upload(c, &c->d_phase_order[1], p3));
+        GP_TRY(upload(c, &c->d_sep_ids, sep));
+        GP_TRY(upload(c, &c->d_sinv_off, inv_off));
+        GP_TRY(upload(c, &c->d_sinv_ncols, inv_cols));
+        GP_TRY(upload(c, &c->d_splits, c->splits));
+        GP_TRY(alloc(c, &c->d_sinv, real_size(c) * c->sinv_elems));
+        int64_t used = 0;
+        for (int s = 0; s < nall; ++s) {
+            const Sub& sb = c->subs[s];
+            if (sb.kind == 0 && sb.split < 0) {
+                used += (s + 1 < nall ? c->subs[s + 1].diag_off : c->factor_elems) - sb.diag_off;
+            } else if (sb.kind == 2) {
+                const int stop = sb.sep0 / T;
+                for (int I = 0; I < sb.nT; ++I) {
+                    const int tfc = c->env_tfc[sb.env_off + I];
+                    used += (int64_t)std::max(std::min(I, stop) - tfc, 0) * T * T;
+                    if (I < stop) used += (int64_t)(1 + c->env_tlc[sb.env_off + I] - I) * T * T;
+                }
+            }
+        }
+        for (const Split& sp : c->splits) used += (int64_t)sp.ld * sp.nS;
+        c->split_apply_elems = used;
+        c->split_row0 = c->subs[nsub].slot_off;
+        c->split_row1 = (int64_t)c->sub_slots.size();
+    }
+    c->prim_factor_elems = nall > c->Np ? c->subs[c->Np].diag_off : c->factor_elems;
+    c->prim_rows = nall > c->Np ? c->subs[c->Np].slot_off : (int64_t)c->sub_slots.size();
     GP_TRY(alloc(c, &c->d_factor, real_size(c) * c->factor_elems));
-    GP_TRY(alloc(c, (void**)&c->d_inv64, sizeof(double) * 1024 * std::max(nsub, 1)));
-    GP_TRY(alloc(c, &c->d_local, real_size(c) * local_off[nsub]));
+    GP_TRY(alloc(c, (void**)&c->d_inv64, sizeof(double) * 1024 * std::max(nall, 1)));
+    GP_TRY(alloc(c, &c->d_local, real_size(c) * local_off[nall]));
     // shape/correction blocks: column-major with ld = nT * T, right-hand sides built here
     std::vector<int64_t> phi_off(c->Np + 1, 0);
     std::vector<int32_t> phi_ncols(std::max(nsub, 1), 0);
@@ -752,6 +802,7 @@ static int check_options(gplmm_ctx* c, const gplmm_options* opt, double rho, dou
     if (c->opt.tile != 32) return fail(c, GPLMM_E_ARG, "only tile = 32 is supported");
     if (c->opt.build_matrix != GPLMM_BUILD_GEOMETRIC && c->opt.build_matrix != GPLMM_BUILD_JACOBIAN)
         return fail(c, GPLMM_E_ARG, "build_matrix must be GPLMM_BUILD_GEOMETRIC or GPLMM_BUILD_JACOBIAN");
+    if (c->opt.split_tiles < -1) return fail(c, GPLMM_E_ARG, "split_tiles must be -1, 0 or positive");
     if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return fail(c, GPLMM_E_ARG, "image dimensions must be positive");
     if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024)
         return fail(c, GPLMM_E_ARG, "image dimensions must be <= 1024");
@@ -928,7 +979,9 @@ int gplmm_layout_info(const gplmm_ctx* c, gplmm_layout* o) {
     o->local_unknowns = lu;
     o->factor_bytes = (int64_t)(c->opt.precision == GPLMM_FP32 ? 4 : 8) * c->factor_elems;
     o->ncolors = c->ncolors;
-    o->lu_flops = c->lu_flops[0] + c->lu_flops[1];
+    o->lu_flops = c->lu_flops[0] + c->lu_flops[1] + c->lu_flops[2];
+    o->nsplit = (int)c->splits.size();
+    for (const Split& sp : c->splits) o->sep_unknowns += sp.nS;
     return GPLMM_OK;
 }
 
@@ -954,13 +1007,34 @@ int gplmm_get_duals(const gplmm_ctx* c, int64_t* ptr, int32_t* cells) {
     return GPLMM_OK;
 }
 
+int gplmm_get_split(const gplmm_ctx* c, int k, int32_t* info, int32_t* slots) {
+    if (!c || !info) return GPLMM_E_ARG;
+    if (k < 0 || k >= (int)c->splits.size()) return GPLMM_E_ARG;
+    const Split& sp = c->splits[k];
+    info[0] = sp.prim;
+    info[1] = sp.nA;
+    info[2] = sp.nB;
+    info[3] = sp.nS;
+    if (slots) {
+        const Sub& a = c->subs[sp.a_sub];
+        const Sub& b = c->subs[sp.b_sub];
+        const int32_t* sa = c->sub_slots.data() + a.slot_off;
+        const int32_t* sb = c->sub_slots.data() + b.slot_off;
+        std::copy(sa, sa + sp.nA, slots);
+        std::copy(sb, sb + sp.nB, slots + sp.nA);
+        std::copy(sa + sp.nA, sa + sp.nA + sp.nS, slots + sp.nA + sp.nB);
+    }
+    return GPLMM_OK;
+}
+
 int gplmm_get_subdomains(const gplmm_ctx* c, int32_t* n, int64_t* factor_elems) {
     if (!c) return GPLMM_E_ARG;
-    const int nsub = (int)c->subs.size();
+    const int nsub = c->Np + c->Nc;   // the split parts are not reported
+    const int nall = (int)c->subs.size();
     for (int s = 0; s < nsub; ++s) {
         if (n) n[s] = c->subs[s].n;
         if (factor_elems)
-            factor_elems[s] = (s + 1 < nsub ? c->subs[s + 1].diag_off : c->factor_elems) - c->subs[s].diag_off;
+            factor_elems[s] = (s + 1 < nall ? c->subs[s + 1].diag_off : c->factor_elems) - c->subs[s].diag_off;
     }
     return GPLMM_OK;
 }
@@ -1418,6 +1492,8 @@ void gplmm_destroy(gplmm_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     void* ptrs[] = {c->d_co_pinned, c->d_panel, c->d_gin, c->d_gout, c->d_cl_row, c->d_cl_col, c->d_cl_feat, c->d_cl_pred, c->d_cl_scale, c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
+                    c->d_step_pairs[2], c->d_sub_list[2], c->d_splits, c->d_phase_order[0], c->d_phase_order[1],
+                    c->d_sep_ids, c->d_sinv_off, c->d_sinv_ncols, c->d_sinv,
                     c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_r, c->d_tmp,

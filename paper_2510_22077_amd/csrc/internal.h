@@ -48,15 +48,31 @@ struct SampleGeo {
     int p0, i0;              // first primary, first interface
 };
 
-// One local problem (primary closure / primary block / dual block).
+// One local problem (primary closure / primary block / dual block / split parts).
 struct Sub {
-    int kind;                // 0 primary (closure and Schwarz block), 1 dual
+    int kind;                // 0 primary (closure and Schwarz block), 1 dual, 2 half of a split
+                             // primary with the separator appended, 3 separator of a split primary
     int id;                  // primary or interface id
     int n;                   // local unknowns
     int nT;                  // tiles per side
     int64_t slot_off;        // into sub_slots
     int64_t env_off;         // into env arrays (tfc, tfr, tlc, lrow, urow), nT entries each
     int64_t diag_off;        // element offset of the first diagonal tile in the factor buffer
+    int sep0;                // kind 2: first local row of the separator (a multiple of the tile)
+    int skip_ss;             // kind 2: 1 = the separator-separator block is not assembled here
+    int split;               // index of the split that the subdomain belongs to, or -1
+};
+
+// A primary whose Schwarz block is solved by one level of nested dissection: the halves A
+// and B (B in reverse order along the cut axis) each factorised with the separator S
+// appended ([A, S] and [B, S], elimination stopped after the half), the separator's Schur
+// complement S' = the sum of the two trailing blocks, factorised and inverted.
+struct Split {
+    int prim;
+    int a_sub, b_sub, s_sub;
+    int nA, nB, nS;
+    int ld;                  // padded separator size (its tiles times the tile)
+    int64_t inv_off;         // element offset of S'^-1 (column-major, ld x ld) in the inverse buffer
 };
 
 // Coarse probing: one colour = set of coarse columns whose restricted images do not overlap.
@@ -111,11 +127,27 @@ struct gplmm_ctx {
     int maxT = 0;
     int maxT_set[2] = {0, 0};          // largest tile count among the primaries / the duals
     // LU schedule: per step K, (sub, I) pairs for the row-update kernel
-    std::vector<int64_t> lu_step_off[2];     // [set][K], set 0 = primaries, 1 = primaries + duals
-    std::vector<int32_t> lu_step_pairs[2];
-    std::vector<int64_t> lu_sub_off[2];
-    std::vector<int32_t> lu_sub_list[2];
-    double lu_flops[2] = {0.0, 0.0};     // flops of the tile products of each schedule (2 T^3 each)
+    // set 0 = primaries' Schwarz blocks (split halves in place of split primaries, stopped
+    // after the half), 1 = primaries' closures + duals, 2 = separators of split primaries
+    std::vector<int64_t> lu_step_off[3];     // [set][K]
+    std::vector<int32_t> lu_step_pairs[3];
+    std::vector<int64_t> lu_sub_off[3];
+    std::vector<int32_t> lu_sub_list[3];
+    double lu_flops[3] = {0.0, 0.0, 0.0};   // flops of the tile products of each schedule (2 T^3 each)
+    std::vector<gp::Split> splits;       // primaries solved by nested dissection
+    int nsub_main = 0;                   // Np + Nc: the subdomains before the split parts
+    int64_t sinv_elems = 0;              // separators' inverses, all splits
+    int64_t split_apply_elems = 0;       // factor and inverse elements one primary solve reads
+    int max_sep_ld = 0;                  // largest padded separator
+    int n_phase1 = 0, n_phase3 = 0;      // split solves: unsplit primaries and halves / halves only
+    int maxT_phase1 = 0, maxT_phase3 = 0;
+    int64_t split_row0 = 0, split_row1 = 0;   // slot-list rows of the split parts
+    gp::Split* d_splits = nullptr;
+    int32_t* d_phase_order[2] = {nullptr, nullptr};   // phase 1 (largest first), phase 3
+    int32_t* d_sep_ids = nullptr;        // the separators' subdomain ids
+    int64_t* d_sinv_off = nullptr;       // per subdomain: offset of its inverse (separators)
+    int32_t* d_sinv_ncols = nullptr;     // per subdomain: columns of its inverse (separators)
+    void* d_sinv = nullptr;              // separators' inverses (real)
 
     // ---- shape vectors
     std::vector<int64_t> phi_off;     // per primary: element offset of its |S| x (|Cp|+1) block
@@ -157,8 +189,8 @@ struct gplmm_ctx {
     int64_t* d_lrow = nullptr;
     int64_t* d_urow = nullptr;
     int32_t* d_tlc = nullptr;
-    int32_t* d_step_pairs[2] = {nullptr, nullptr};
-    int32_t* d_sub_list[2] = {nullptr, nullptr};
+    int32_t* d_step_pairs[3] = {nullptr, nullptr, nullptr};
+    int32_t* d_sub_list[3] = {nullptr, nullptr, nullptr};
     void* d_factor = nullptr;            // real (float or double) tiles
     double* d_inv64 = nullptr;           // per subdomain: FP64 inverses of the current LU step's diagonal tile
     int64_t prim_factor_elems = 0;       // primaries' tiles come first

@@ -34,6 +34,7 @@ struct Env {
     const int64_t* urow;
     const int32_t* sub_samp;   // batch: sample of each subdomain (nullptr for one image)
     const uint8_t* sact;       // batch: 0 for a sample whose Krylov process has finished
+    const Split* splits;       // primaries solved by nested dissection
 };
 
 // A subdomain of a finished sample of a batch: its right-hand side is zero, so is its
@@ -66,7 +67,10 @@ __global__ void assemble_kernel(DevGeo g, const double* __restrict__ coef, Env e
     if (s < first_sub || s >= first_sub + nsub) return;
     constexpr int nr = ND + 1;
     const Sub sb = e.subs[s];
+    if (sb.kind == 3) return;   // separators: formed from the halves' trailing blocks
     const int r = (int)(t - sb.slot_off);
+    // a half assembled without the separator-separator block (the other half holds it)
+    const int sep_skip = sb.skip_ss && r >= sb.sep0 ? sb.sep0 : sb.n;
     const int64_t gs = slots[t];
     const int64_t c = gs / nr;
     const int comp = (int)(gs % nr);
@@ -83,6 +87,7 @@ __global__ void assemble_kernel(DevGeo g, const double* __restrict__ coef, Env e
         }
         if (lo < sb.n && ss[lo] == col) {
             const int lc = sl[lo];
+            if (lc >= sep_skip) return;
             T* tp = tile_ptr(F, e, sb, r / kT, lc / kT);
             tp[(r % kT) * kT + (lc % kT)] += (T)val;
         } else if (closure) {
@@ -557,11 +562,19 @@ __device__ __forceinline__ T buf_dot(const T (&buf)[kPF], const T* y, int n) {
 // of tile row I + 2 (I - 2 going backward) are loaded into registers while rows I and
 // I + 1 are processed (two register buffers), which keeps two rows of factor loads in
 // flight behind the dependency chain of the substitution.
+//
+// phase (split primaries, for the halves [A, S] only; other subdomains solve whole):
+// 1 = forward substitution of the half (rows below sep0), then the separator rows minus
+//     their half's part, r_S - L_SA y_A (for the second half, whose separator rows hold
+//     no right-hand side, -L_SB y_B); no backward substitution;
+// 2 = backward substitution of the half with the separator's solution read from the
+//     separator's local vector.
 template <typename T, bool kLds>
 __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restrict__ F,
                                                         const int32_t* __restrict__ order,
                                                         const int32_t* __restrict__ slots, const T* __restrict__ vin,
-                                                        T* __restrict__ out, const int64_t* __restrict__ off) {
+                                                        T* __restrict__ out, const int64_t* __restrict__ off,
+                                                        int phase) {
     constexpr int kPF = pf_tiles<T>();
     extern __shared__ unsigned char dyn_lds[];
     __shared__ T part[kT];
@@ -574,6 +587,9 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         for (int i = threadIdx.x; i < nT * kT; i += blockDim.x) xo[i] = (T)0;
         return;
     }
+    const bool half = phase != 0 && sb.kind == 2;
+    const int stop = half ? sb.sep0 / kT : nT;   // rows eliminated by the substitutions
+    const bool fwd = !half || phase == 1, bwd = !half || phase == 2;
     T* x = kLds ? reinterpret_cast<T*>(dyn_lds) : xo;
     const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
     const int32_t* tfc = e.tfc + sb.env_off;
@@ -583,7 +599,13 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     const int32_t* sl = slots + sb.slot_off;
     const T* D = F + sb.diag_off + tid;
     const int len = nT * kT;
-    for (int i = tid; i < len; i += 1024) x[i] = i < sb.n ? vin[sl[i]] : (T)0;
+    if (fwd) {
+        const int nb = sb.skip_ss ? sb.sep0 : sb.n;
+        for (int i = tid; i < len; i += 1024) x[i] = i < nb ? vin[sl[i]] : (T)0;
+    } else {
+        const T* xs = out + off[e.splits[sb.split].s_sub];
+        for (int i = tid; i < len; i += 1024) x[i] = i < stop * kT ? xo[i] : xs[i - stop * kT];
+    }
     T bufA[kPF], bufB[kPF];
 #pragma unroll
     for (int t = 0; t < kPF; ++t) bufA[t] = bufB[t] = 0;
@@ -593,9 +615,11 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     // end are clamped to the last row (and never used)
     // (the diagonal value of a row is fetched only after the row's diagonal product has
     // consumed the previous one, so that it reuses its register without a copy)
+    // L tiles of row I taken by the substitution: columns below both I and stop
+    auto lcount = [&](int I) { return max(min(I, stop) - tfc[I], 0); };
     auto fetch_l = [&](int I, T(&buf)[kPF], int& nb) {
         const int Ic = min(I, nT - 1);
-        nb = min(Ic - tfc[Ic], kPF);
+        nb = min(lcount(Ic), kPF);
         load_row(buf, F + lrow[Ic] + tid, nb);
     };
     auto fetch_u = [&](int I, T(&buf)[kPF], int& nb) {
@@ -603,19 +627,25 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         nb = min(tlc[Ic] - Ic, kPF);
         load_row(buf, F + urow[Ic] + tid, nb);
     };
-    fetch_l(0, bufA, nA);
-    fetch_l(1, bufB, nB);
-    dA = D[0];
-    dB = D[(int64_t)min(1, nT - 1) * kTT];
+    if (fwd) {
+        fetch_l(0, bufA, nA);
+        fetch_l(1, bufB, nB);
+        dA = D[0];
+        dB = D[(int64_t)min(1, nT - 1) * kTT];
+    }
     __syncthreads();
     // ---- forward: L y = b, row-oriented over L's contiguous tile rows
     auto fwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
-        const int j0 = tfc[I], nt = I - j0;
+        const int j0 = tfc[I], nt = lcount(I);
         const T* y = x + j0 * kT + c;
         T acc = buf_dot(buf, y, nb);
         if (nt > kPF) acc += tail_dot<T>(F + lrow[I] + tid, y, kPF, nt);
         fetch_l(I + 2, buf, nb);
         acc = sum32(acc);
+        if (I >= stop) {   // separator row of a half: no elimination, no dependency
+            if (c == 0) x[I * kT + r] -= acc;
+            return;
+        }
         if (c == 0) part[r] = x[I * kT + r] - acc;
         __syncthreads();
         const T v = sum32((c < r ? db : (c == r ? (T)1 : (T)0)) * part[c]);
@@ -623,9 +653,12 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         db = D[(int64_t)min(I + 2, nT - 1) * kTT];
         __syncthreads();
     };
-    for (int I = 0; I < nT; I += 2) {
-        fwd_row(I, bufA, nA, dA);
-        if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
+    if (fwd) {
+        for (int I = 0; I < nT; I += 2) {
+            fwd_row(I, bufA, nA, dA);
+            if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
+        }
+        __syncthreads();
     }
     // ---- backward: U x = y, row-oriented over U's contiguous tile rows (descending)
     auto bwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
@@ -642,16 +675,79 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         db = D[(int64_t)max(I - 2, 0) * kTT];
         __syncthreads();
     };
-    fetch_u(nT - 1, bufA, nA);
-    fetch_u(nT - 2, bufB, nB);
-    dA = D[(int64_t)(nT - 1) * kTT];
-    dB = D[(int64_t)max(nT - 2, 0) * kTT];
-    for (int I = nT - 1; I >= 0; I -= 2) {
-        bwd_row(I, bufA, nA, dA);
-        if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+    if (bwd) {
+        fetch_u(stop - 1, bufA, nA);
+        fetch_u(stop - 2, bufB, nB);
+        dA = D[(int64_t)(stop - 1) * kTT];
+        dB = D[(int64_t)max(stop - 2, 0) * kTT];
+        for (int I = stop - 1; I >= 0; I -= 2) {
+            bwd_row(I, bufA, nA, dA);
+            if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+        }
     }
     if (kLds)
         for (int i = tid; i < len; i += 1024) xo[i] = x[i];
+}
+
+// Separators of the split primaries: x_S = S'^-1 r'_S with r'_S the sum of the two
+// halves' separator rows after phase 1; one block per (split, 64 rows of S'^-1, column-
+// major), four waves over interleaved columns, the solution written to the separator's
+// local vector.
+template <typename T>
+__global__ void __launch_bounds__(256) sep_solve_kernel(Env e, const T* __restrict__ sinv, T* __restrict__ loc,
+                                                        const int64_t* __restrict__ off) {
+    extern __shared__ double2 sep_lds[];
+    T* rs = reinterpret_cast<T*>(sep_lds);
+    __shared__ T red[4][64];
+    const Split sp = e.splits[blockIdx.x];
+    const int row0 = blockIdx.y * 64;
+    if (row0 >= sp.ld) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const T* xa = loc + off[sp.a_sub] + sp.nA;
+    const T* xb = loc + off[sp.b_sub] + sp.nB;
+    for (int i = tid; i < sp.nS; i += 256) rs[i] = xa[i] + xb[i];
+    __syncthreads();
+    const int row = row0 + lane;
+    T acc = 0;
+    if (row < sp.ld) {
+        const T* m = sinv + sp.inv_off + row;
+        for (int j = w; j < sp.nS; j += 4) acc += m[(int64_t)j * sp.ld] * rs[j];
+    }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && row < sp.ld) loc[off[sp.s_sub] + row] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+// S' = the sum of the two halves' trailing separator blocks (after their eliminations
+// stopped at the separator), one block per (split, separator tile); tiles outside a
+// half's envelope are zero.
+template <typename T>
+__global__ void schur_sum_kernel(Env e, T* __restrict__ F) {
+    const Split sp = e.splits[blockIdx.x];
+    const int nts = sp.ld / kT;
+    const int I = blockIdx.y, J = blockIdx.z;
+    if (I >= nts || J >= nts) return;
+    auto tile_if = [&](const Sub& sb, int a0) -> const T* {
+        const int i = a0 + I, j = a0 + J;
+        if (j < i && j < e.tfc[sb.env_off + i]) return nullptr;
+        if (i < j && j > e.tlc[sb.env_off + i]) return nullptr;
+        return tile_ptr(F, e, sb, i, j);
+    };
+    const Sub a = e.subs[sp.a_sub], b = e.subs[sp.b_sub], sv = e.subs[sp.s_sub];
+    const T* ta = tile_if(a, sp.nA / kT);
+    const T* tb = tile_if(b, sp.nB / kT);
+    T* ts = tile_ptr(F, e, sv, I, J);
+    for (int x = threadIdx.x; x < kTT; x += blockDim.x) ts[x] = (ta ? ta[x] : (T)0) + (tb ? tb[x] : (T)0);
+}
+
+// Identity columns 0 .. nS-1 of each separator's inverse block (solved in place).
+template <typename T>
+__global__ void sep_identity_kernel(Env e, T* __restrict__ sinv) {
+    const Split sp = e.splits[blockIdx.x];
+    const int j = blockIdx.y;
+    if (j >= sp.nS) return;
+    T* col = sinv + sp.inv_off + (int64_t)j * sp.ld;
+    for (int i = threadIdx.x; i < sp.ld; i += blockDim.x) col[i] = i == j ? (T)1 : (T)0;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -988,7 +1084,7 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
 // Host drivers
 // ---------------------------------------------------------------------------------------
 static Env make_env(gplmm_ctx* c) {
-    return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_tlc, c->d_lrow, c->d_urow, c->d_sub_samp, c->d_sact};
+    return Env{c->d_subs, c->d_tfc, c->d_tfr, c->d_tlc, c->d_lrow, c->d_urow, c->d_sub_samp, c->d_sact, c->d_splits};
 }
 
 template <typename T>
@@ -1059,12 +1155,66 @@ void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vi
                                                            c->d_sub_slots, vin, out_local, c->d_local_off);
     else if (lds <= kTrsvLdsMax && c->trsv_mode == 0)
         trsv_sub_kernel<T, true><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
-                                                                c->d_sub_slots, vin, out_local, c->d_local_off);
+                                                                c->d_sub_slots, vin, out_local, c->d_local_off, 0);
     else
         trsv_sub_kernel<T, false><<<nsub, 1024, 0, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
-                                                               c->d_sub_slots, vin, out_local, c->d_local_off);
+                                                               c->d_sub_slots, vin, out_local, c->d_local_off, 0);
     timer_end(c, duals ? "trsv_d" : "trsv_p", bytes);
     timer_end(c, "trsv", bytes);
+}
+
+// The primaries' solves with split primaries: phase 1 (unsplit primaries whole, halves
+// forward), the separators, phase 2 (halves backward).  The halves' local vectors then
+// hold [x_A, x_S] and [x_B, x_S].
+template <typename T>
+void trsv_split(gplmm_ctx* c, const T* vin, T* loc) {
+    Env e = make_env(c);
+    const T* F = (const T*)c->d_factor;
+    const int nsp = (int)c->splits.size();
+    // algorithmic bytes: the factor tiles the substitutions read (every tile of an unsplit
+    // primary; of a half the tiles of its eliminated rows and the separator rows' L tiles
+    // left of the separator), the separators' inverses, the gathered right-hand side
+    // (value + slot index) and the solution written and re-read
+    const double bytes = (double)sizeof(T) * (double)c->split_apply_elems + (double)c->prim_rows * (3.0 * sizeof(T) + 4.0);
+    timer_begin(c, "trsv");
+    timer_begin(c, "trsv_p");
+    const size_t lds1 = (size_t)c->maxT_phase1 * kT * sizeof(T), lds3 = (size_t)c->maxT_phase3 * kT * sizeof(T);
+    if (lds1 <= kTrsvLdsMax)
+        trsv_sub_kernel<T, true><<<c->n_phase1, 1024, lds1, c->stream>>>(e, F, c->d_phase_order[0], c->d_sub_slots, vin,
+                                                                          loc, c->d_local_off, 1);
+    else
+        trsv_sub_kernel<T, false><<<c->n_phase1, 1024, 0, c->stream>>>(e, F, c->d_phase_order[0], c->d_sub_slots, vin,
+                                                                        loc, c->d_local_off, 1);
+    sep_solve_kernel<T><<<dim3(nsp, (c->max_sep_ld + 63) / 64), 256, (size_t)c->max_sep_ld * sizeof(T), c->stream>>>(
+        e, (const T*)c->d_sinv, loc, c->d_local_off);
+    if (lds3 <= kTrsvLdsMax)
+        trsv_sub_kernel<T, true><<<c->n_phase3, 1024, lds3, c->stream>>>(e, F, c->d_phase_order[1], c->d_sub_slots, vin,
+                                                                          loc, c->d_local_off, 2);
+    else
+        trsv_sub_kernel<T, false><<<c->n_phase3, 1024, 0, c->stream>>>(e, F, c->d_phase_order[1], c->d_sub_slots, vin,
+                                                                        loc, c->d_local_off, 2);
+    timer_end(c, "trsv_p", bytes);
+    timer_end(c, "trsv", bytes);
+}
+
+// Separators after the halves' stopped eliminations: S' assembled from the trailing
+// blocks, factorised (schedule 2) and inverted column by column.
+template <typename T>
+int build_separators(gplmm_ctx* c) {
+    const int nsp = (int)c->splits.size();
+    if (nsp == 0) return GPLMM_OK;
+    Env e = make_env(c);
+    T* F = (T*)c->d_factor;
+    const int mt = c->max_sep_ld / kT;
+    schur_sum_kernel<T><<<dim3(nsp, mt, mt), 256, 0, c->stream>>>(e, F);
+    int rc = factor_set<T>(c, 2);
+    if (rc != GPLMM_OK) return rc;
+    int maxs = 0;
+    for (const Split& sp : c->splits) maxs = std::max(maxs, sp.nS);
+    sep_identity_kernel<T><<<dim3(nsp, maxs), 256, 0, c->stream>>>(e, (T*)c->d_sinv);
+    trsv_kernel<T><<<dim3(nsp, maxs), 256, 0, c->stream>>>(e, F, c->d_sep_ids, c->d_sub_slots, nullptr, (T*)c->d_sinv,
+                                                          c->d_sinv_off, c->d_sinv_ncols, 1);
+    return GPLMM_OK;
 }
 
 template <typename T>
@@ -1082,6 +1232,10 @@ template int factor_set<float>(gplmm_ctx*, int);
 template int factor_set<double>(gplmm_ctx*, int);
 template void trsv_gather<float>(gplmm_ctx*, const int32_t*, int, const float*, float*);
 template void trsv_gather<double>(gplmm_ctx*, const int32_t*, int, const double*, double*);
+template void trsv_split<float>(gplmm_ctx*, const float*, float*);
+template void trsv_split<double>(gplmm_ctx*, const double*, double*);
+template int build_separators<float>(gplmm_ctx*);
+template int build_separators<double>(gplmm_ctx*);
 template void trsv_phi<float>(gplmm_ctx*, int);
 template void trsv_phi<double>(gplmm_ctx*, int);
 

@@ -133,7 +133,24 @@ __global__ void scatter_prim_kernel(const int32_t* __restrict__ slots, const int
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nrows_prim) return;
     const int s = row_sub[t];
+    if (subs[s].split >= 0) return;   // solved by its halves
     const int r = (int)(t - subs[s].slot_off);
+    z[slots[t]] = loc[local_off[s] + r];
+}
+
+// zp[slot] = the halves' local solutions of the split primaries: the first half's rows
+// ([x_A, x_S]) and the second half's own rows (x_B)
+template <typename T>
+__global__ void scatter_split_kernel(const int32_t* __restrict__ slots, const int32_t* __restrict__ row_sub,
+                                     const Sub* __restrict__ subs, const int64_t* __restrict__ local_off,
+                                     const T* __restrict__ loc, T* __restrict__ z, int64_t row0, int64_t row1) {
+    const int64_t t = row0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= row1) return;
+    const int s = row_sub[t];
+    const Sub sb = subs[s];
+    if (sb.kind != 2) return;
+    const int r = (int)(t - sb.slot_off);
+    if (sb.skip_ss && r >= sb.sep0) return;
     z[slots[t]] = loc[local_off[s] + r];
 }
 
@@ -247,6 +264,10 @@ template <typename T>
 int assemble_subs(gplmm_ctx* c, int first_sub, int nsub, bool closure);
 template <typename T>
 int factor_set(gplmm_ctx* c, int set);
+template <typename T>
+void trsv_split(gplmm_ctx* c, const T* vin, T* loc);
+template <typename T>
+int build_separators(gplmm_ctx* c);
 
 static CoBlk coblk(const gplmm_ctx* c) {
     return CoBlk{c->d_co_blk, c->d_co_loc, c->d_cblk_n, c->d_cblk_idx, c->d_cblk_ioff, c->d_cblk_moff};
@@ -388,8 +409,15 @@ int build_precond(gplmm_ctx* c) {
     timer_begin(c, "build_primary_lu");
     GP_HIP(c, hipMemsetAsync(F, 0, sizeof(T) * c->prim_factor_elems, s));
     assemble_subs<T>(c, 0, c->Np, false);
+    const int nall = (int)c->subs.size();
+    if (nall > c->nsub_main) {   // split primaries: both halves with the separator appended
+        const int64_t e0 = c->subs[c->nsub_main].diag_off;
+        GP_HIP(c, hipMemsetAsync(F + e0, 0, sizeof(T) * (c->factor_elems - e0), s));
+        assemble_subs<T>(c, c->nsub_main, nall - c->nsub_main, false);
+    }
     factor_set<T>(c, 0);
-    timer_end(c, "build_primary_lu", c->lu_flops[0]);
+    build_separators<T>(c);
+    timer_end(c, "build_primary_lu", c->lu_flops[0] + c->lu_flops[2]);
     int flag = 0;
     GP_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(c, hipStreamSynchronize(s));
@@ -470,7 +498,14 @@ int apply_precond(gplmm_ctx* c, const double* v, double* z) {
     // r2 = r1 - X z_d ; z_p = M_p^-1 r2 (disjoint primaries)
     launch_xv<T>(c, zd, r2, r1, s);
     zero_fill<T>(c, zp, N);
-    trsv_gather<T>(c, c->d_sub_ids, c->Np, r2, loc);
+    if (c->splits.empty()) {
+        trsv_gather<T>(c, c->d_sub_ids, c->Np, r2, loc);
+    } else {
+        trsv_split<T>(c, r2, loc);
+        const int64_t nr = c->split_row1 - c->split_row0;
+        scatter_split_kernel<T><<<nb(nr), kB, 0, s>>>(c->d_sub_slots, c->d_row_sub, c->d_subs, c->d_local_off, loc, zp,
+                                                      c->split_row0, c->split_row1);
+    }
     scatter_prim_kernel<T><<<nb(c->prim_rows), kB, 0, s>>>(c->d_sub_slots, c->d_row_sub, c->d_subs, c->d_local_off,
                                                            loc, zp, c->prim_rows);
     combine_kernel<T><<<nb(N), kB, 0, s>>>(zG, zd, zp, z, N);

@@ -376,18 +376,23 @@ std::vector<int64_t> unknowns_of(const gplmm_ctx* c, const std::vector<int32_t>&
     return u;
 }
 
-// Local order of a subdomain's unknowns: a raster order over the set's own bounding
-// box (periodic axes cut at their longest empty run, so a set that wraps is
-// contiguous), with the longest extent as the slowest axis, which keeps the
-// envelope (the slab of unknowns between a row and its furthest lower neighbour)
-// small.  A face sits at its record cell's raster position (axis order within it;
-// for a face whose record cell is outside the set, that cell's unwrapped position);
-// a pressure sits after the upper face of its cell along the slowest axis, so every
-// pressure follows all of its faces and the velocity-first leading blocks of the
-// saddle-point matrix stay nonsingular without pivoting.
-std::vector<int64_t> local_keys(const gplmm_ctx* c, const std::vector<int32_t>& cells, const std::vector<int64_t>& u) {
+// Frame of a set's unknowns: the record position of each face (for a face whose
+// record cell is outside the set, one step above its lower neighbour) and the cell
+// position of each pressure, in the set's own coordinates, and the raster strides.
+struct LocalFrame {
+    std::vector<std::array<int, 3>> pos;   // per unknown
+    std::vector<int> comp;                 // per unknown: face axis, or ndim for a pressure
+    int64_t stride[3] = {0, 0, 0};
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    int slow = 0;
+    int nd = 3;
+};
+
+LocalFrame local_frame(const gplmm_ctx* c, const std::vector<int32_t>& cells, const std::vector<int64_t>& u) {
     const int nd = c->ndim;
     const int n = (int)cells.size();
+    LocalFrame f;
+    f.nd = nd;
     // the sample holding the set (a subdomain never spans two samples of a batch)
     size_t si = 0;
     while (si + 1 < c->samples.size() && c->samples[si + 1].coff <= (int64_t)cells[0]) ++si;
@@ -416,47 +421,71 @@ std::vector<int64_t> local_keys(const gplmm_ctx* c, const std::vector<int32_t>& 
         const int start = (best + bestlen) % dims[a];
         for (int t = 0; t < n; ++t) co[t][a] = (co[t][a] - start + dims[a]) % dims[a];
     }
-    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (int a = 0; a < 3; ++a) {
+        f.lo[a] = 1 << 30;
+        f.hi[a] = -1;
+    }
     for (int t = 0; t < n; ++t)
         for (int a = 0; a < 3; ++a) {
-            lo[a] = std::min(lo[a], co[t][a]);
-            hi[a] = std::max(hi[a], co[t][a]);
+            f.lo[a] = std::min(f.lo[a], co[t][a]);
+            f.hi[a] = std::max(f.hi[a], co[t][a]);
         }
     int ax[3] = {0, 1, 2};   // fastest .. slowest; ties keep x fastest
-    std::stable_sort(ax, ax + nd, [&](int a, int b) { return hi[a] - lo[a] < hi[b] - lo[b]; });
-    int64_t stride[3] = {0, 0, 0}, st = 1;
+    std::stable_sort(ax, ax + nd, [&](int a, int b) { return f.hi[a] - f.lo[a] < f.hi[b] - f.lo[b]; });
+    int64_t st = 1;
     for (int q = 0; q < nd; ++q) {
-        stride[ax[q]] = st;
-        st *= (int64_t)(hi[ax[q]] - lo[ax[q]] + 2);   // +1 for the upper faces of the top layer
+        f.stride[ax[q]] = st;
+        st *= (int64_t)(f.hi[ax[q]] - f.lo[ax[q]] + 2);   // +1 for the upper faces of the top layer
     }
-    const int slow = ax[nd - 1];
-    auto lin = [&](const std::array<int, 3>& p) {
-        int64_t l = 0;
-        for (int a = 0; a < nd; ++a) l += (int64_t)(p[a] - lo[a]) * stride[a];
-        return l;
-    };
+    f.slow = ax[nd - 1];
     auto idx = [&](int64_t q) -> int {
         auto it = std::lower_bound(cells.begin(), cells.end(), (int32_t)q);
         return (it != cells.end() && *it == q) ? (int)(it - cells.begin()) : -1;
     };
-    std::vector<int64_t> keys(u.size());
+    f.pos.resize(u.size());
+    f.comp.resize(u.size());
     for (size_t t = 0; t < u.size(); ++t) {
         const int64_t q = u[t] / c->nrec;
         const int comp = (int)(u[t] % c->nrec);
         int k = idx(q);
+        f.comp[t] = comp;
         if (comp < nd) {
-            std::array<int, 3> p;
             if (k >= 0) {
-                p = co[k];
+                f.pos[t] = co[k];
             } else {   // record cell outside the set: one step above its lower neighbour
-                p = co[idx(c->nbr[q * 6 + 2 * comp])];
-                p[comp] += 1;
+                f.pos[t] = co[idx(c->nbr[q * 6 + 2 * comp])];
+                f.pos[t][comp] += 1;
             }
-            keys[t] = lin(p) * 8 + comp;
         } else {
-            keys[t] = (lin(co[k]) + stride[slow]) * 8 + 7;
+            f.pos[t] = co[k];
         }
     }
+    return f;
+}
+
+// Raster key of unknown t: faces at their record position (axis order within it), a
+// pressure after the upper face of its cell along the slowest axis.  reverse: the slowest
+// axis runs downwards (a pressure then still follows every face of its cell).
+int64_t frame_key(const LocalFrame& f, size_t t, bool reverse) {
+    const auto& p = f.pos[t];
+    int64_t l = 0;
+    for (int a = 0; a < f.nd; ++a) {
+        const int x = (reverse && a == f.slow) ? f.hi[a] + 1 - p[a] : p[a] - f.lo[a];
+        l += (int64_t)x * f.stride[a];
+    }
+    return f.comp[t] < f.nd ? l * 8 + f.comp[t] : (l + f.stride[f.slow]) * 8 + 7;
+}
+
+// Local order of a subdomain's unknowns: a raster order over the set's own bounding
+// box (periodic axes cut at their longest empty run, so a set that wraps is
+// contiguous), with the longest extent as the slowest axis, which keeps the
+// envelope (the slab of unknowns between a row and its furthest lower neighbour)
+// small.  Every pressure follows all of its faces, so the velocity-first leading blocks
+// of the saddle-point matrix stay nonsingular without pivoting.
+std::vector<int64_t> local_keys(const gplmm_ctx* c, const std::vector<int32_t>& cells, const std::vector<int64_t>& u) {
+    LocalFrame f = local_frame(c, cells, u);
+    std::vector<int64_t> keys(u.size());
+    for (size_t t = 0; t < u.size(); ++t) keys[t] = frame_key(f, t, false);
     return keys;
 }
 
@@ -498,12 +527,143 @@ void row_pattern(const gplmm_ctx* c, int64_t s, std::vector<int64_t>& cols) {
     }
 }
 
+// One level of nested dissection of a primary's unknown set (its Schwarz block is solved
+// as the halves A and B in parallel and the separator S between them):
+// * S: every unknown whose position along the slowest axis is the median plane k0 (a face
+//   at its record cell, a pressure at its cell); A below, B above.  The X stencil couples
+//   unknowns at most one position apart, so A and B are uncoupled;
+// * A in raster order, B in raster order reversed along the cut axis (its separator
+//   neighbours come last), each trimmed to a whole number of tiles by moving its last
+//   unknowns to the front of S;
+// * any pressure with an incident face ordered after it (in the global order [A, B, S])
+//   moves to the end of S, so every pressure still follows its faces and the elimination
+//   without pivoting stays defined; trimming and moving repeat until nothing moves.
+// Returns false when the set does not split (too few planes, a coupling across the cut,
+// or a separator above a quarter of the unknowns or above 4096).
+bool plan_split(const gplmm_ctx* c, const std::vector<int32_t>& cells, std::vector<int64_t>& A,
+                std::vector<int64_t>& B, std::vector<int64_t>& S) {
+    const int T = c->tile, nd = c->ndim;
+    std::vector<int64_t> u = unknowns_of(c, cells);
+    const LocalFrame f = local_frame(c, cells, u);
+    const int n = (int)u.size();
+    const int sl = f.slow;
+    const int z0 = f.lo[sl], z1 = f.hi[sl] + 1;
+    std::vector<int> cnt(z1 - z0 + 1, 0);
+    for (int t = 0; t < n; ++t) cnt[f.pos[t][sl] - z0]++;
+    int k0 = z0, acc = 0;
+    while (k0 < z1 && acc + cnt[k0 - z0] < n / 2) acc += cnt[k0++ - z0];
+    if (k0 <= z0 || k0 >= z1) return false;
+    std::vector<std::pair<int64_t, int>> ka, kb, ks;
+    for (int t = 0; t < n; ++t) {
+        const int z = f.pos[t][sl];
+        if (z < k0) ka.push_back({frame_key(f, t, false), t});
+        else if (z > k0) kb.push_back({frame_key(f, t, true), t});
+        else ks.push_back({frame_key(f, t, false), t});
+    }
+    std::sort(ka.begin(), ka.end());
+    std::sort(kb.begin(), kb.end());
+    std::sort(ks.begin(), ks.end());
+    std::vector<int> a, b, core, rep;
+    std::deque<int> movA, movB;
+    for (auto& p : ka) a.push_back(p.second);
+    for (auto& p : kb) b.push_back(p.second);
+    for (auto& p : ks) core.push_back(p.second);
+    // slot -> unknown index
+    std::vector<std::pair<int64_t, int>> inv(n);
+    for (int t = 0; t < n; ++t) inv[t] = {u[t], t};
+    std::sort(inv.begin(), inv.end());
+    auto index_of = [&](int64_t s) -> int {
+        auto it = std::lower_bound(inv.begin(), inv.end(), std::make_pair(s, -1));
+        return (it != inv.end() && it->first == s) ? it->second : -1;
+    };
+    std::vector<int> place(n);
+    for (int round = 0; round < 64; ++round) {
+        while (a.size() % T) {
+            movA.push_front(a.back());
+            a.pop_back();
+        }
+        while (b.size() % T) {
+            movB.push_front(b.back());
+            b.pop_back();
+        }
+        int pos = 0;
+        for (int t : a) place[t] = pos++;
+        for (int t : b) place[t] = pos++;
+        for (int t : movA) place[t] = pos++;
+        for (int t : movB) place[t] = pos++;
+        for (int t : core) place[t] = pos++;
+        for (int t : rep) place[t] = pos++;
+        // pressures ordered before one of their faces move to the end of S
+        std::vector<char> late(n, 0);
+        bool any = false;
+        for (int t = 0; t < n; ++t) {
+            if (f.comp[t] != nd) continue;
+            const int64_t q = u[t] / c->nrec;
+            bool bad = false;
+            for (int d = 0; d < nd && !bad; ++d) {
+                int64_t lo_s = c->nbr[q * 6 + 2 * d] >= 0 ? (int64_t)c->nrec * q + d : -1;
+                int64_t up = c->nbr[q * 6 + 2 * d + 1];
+                int64_t hi_s = up >= 0 ? (int64_t)c->nrec * up + d : -1;
+                for (int64_t fs : {lo_s, hi_s}) {
+                    if (fs < 0) continue;
+                    const int k = index_of(fs);
+                    if (k >= 0 && place[k] > place[t]) bad = true;
+                }
+            }
+            if (bad && std::find(rep.begin(), rep.end(), t) == rep.end()) {
+                late[t] = 1;
+                any = true;
+            }
+        }
+        if (!any) break;
+        auto drop = [&](std::vector<int>& v) { v.erase(std::remove_if(v.begin(), v.end(), [&](int t) { return late[t]; }), v.end()); };
+        auto dropq = [&](std::deque<int>& v) { v.erase(std::remove_if(v.begin(), v.end(), [&](int t) { return late[t]; }), v.end()); };
+        drop(a);
+        drop(b);
+        dropq(movA);
+        dropq(movB);
+        drop(core);
+        for (int t = 0; t < n; ++t)
+            if (late[t]) rep.push_back(t);
+        if (round == 63) return false;
+    }
+    const int nS = (int)(movA.size() + movB.size() + core.size() + rep.size());
+    if (a.empty() || b.empty() || nS * 4 > n || nS > 4096) return false;
+    // the halves must be uncoupled
+    std::vector<char> part(n, 2);
+    for (int t : a) part[t] = 0;
+    for (int t : b) part[t] = 1;
+    std::vector<int64_t> cols;
+    for (int t = 0; t < n; ++t) {
+        if (part[t] == 2) continue;
+        row_pattern(c, u[t], cols);
+        for (int64_t s : cols) {
+            const int k = index_of(s);
+            if (k >= 0 && part[k] != 2 && part[k] != part[t]) return false;
+        }
+    }
+    A.clear();
+    B.clear();
+    S.clear();
+    for (int t : a) A.push_back(u[t]);
+    for (int t : b) B.push_back(u[t]);
+    for (int t : movA) S.push_back(u[t]);
+    for (int t : movB) S.push_back(u[t]);
+    for (int t : core) S.push_back(u[t]);
+    for (int t : rep) S.push_back(u[t]);
+    return true;
+}
+
 }  // namespace
 
 int build_local_problems(gplmm_ctx* c) {
     const int T = c->tile;
     const int nsub = c->Np + c->Nc;
+    c->nsub_main = nsub;
     c->subs.assign(nsub, {});
+    c->splits.clear();
+    c->sinv_elems = 0;
+    c->max_sep_ld = 0;
     c->sub_slots.clear();
     c->env_tfc.clear();
     c->env_tfr.clear();
@@ -516,45 +676,35 @@ int build_local_problems(gplmm_ctx* c) {
     int64_t elems = 0;
     c->maxT = 0;
     std::vector<int64_t> cols;
-    for (int sidx = 0; sidx < nsub; ++sidx) {
-        Sub& sb = c->subs[sidx];
-        sb.kind = sidx < c->Np ? 0 : 1;
-        sb.id = sidx < c->Np ? sidx : sidx - c->Np;
-        const std::vector<int32_t>& cells = sb.kind == 0 ? prim_cells[sb.id] : c->dual_cells[sb.id];
-        std::vector<int64_t> u = unknowns_of(c, cells);
-        std::vector<std::pair<int64_t, int64_t>> keyed(u.size());
-        std::vector<int64_t> keys = local_keys(c, cells, u);
-        for (size_t t = 0; t < u.size(); ++t) keyed[t] = {keys[t], u[t]};
-        std::sort(keyed.begin(), keyed.end());
-        const int n = (int)u.size();
+    // the tile skyline of a subdomain whose unknowns are `ordered` (its local order); dense:
+    // every tile present (the separators, whose Schur complement fills in)
+    auto add_sub = [&](Sub& sb, const std::vector<int64_t>& ordered, bool dense) {
+        const int n = (int)ordered.size();
         sb.n = n;
         sb.nT = (n + T - 1) / T;
         c->maxT = std::max(c->maxT, sb.nT);
         sb.slot_off = (int64_t)c->sub_slots.size();
-        std::vector<int64_t> sorted_slots(n);
-        for (int t = 0; t < n; ++t) {
-            sorted_slots[t] = keyed[t].second;
-            c->sub_slots.push_back((int32_t)keyed[t].second);
-        }
+        for (int64_t v : ordered) c->sub_slots.push_back((int32_t)v);
         // global slot -> local index (sorted lookup)
         std::vector<std::pair<int64_t, int>> inv(n);
-        for (int t = 0; t < n; ++t) inv[t] = {sorted_slots[t], t};
+        for (int t = 0; t < n; ++t) inv[t] = {ordered[t], t};
         std::sort(inv.begin(), inv.end());
         auto local = [&](int64_t s) -> int {
             auto it = std::lower_bound(inv.begin(), inv.end(), std::make_pair(s, -1));
             return (it != inv.end() && it->first == s) ? it->second : -1;
         };
         std::vector<int> fc(n), fr(n);
-        for (int r = 0; r < n; ++r) fc[r] = fr[r] = r;
-        for (int r = 0; r < n; ++r) {
-            row_pattern(c, sorted_slots[r], cols);
-            for (int64_t s : cols) {
-                int lc = local(s);
-                if (lc < 0) continue;
-                fc[r] = std::min(fc[r], lc);
-                fr[lc] = std::min(fr[lc], r);
+        for (int r = 0; r < n; ++r) fc[r] = fr[r] = dense ? 0 : r;
+        if (!dense)
+            for (int r = 0; r < n; ++r) {
+                row_pattern(c, ordered[r], cols);
+                for (int64_t s : cols) {
+                    int lc = local(s);
+                    if (lc < 0) continue;
+                    fc[r] = std::min(fc[r], lc);
+                    fr[lc] = std::min(fr[lc], r);
+                }
             }
-        }
         sb.env_off = (int64_t)c->env_tfc.size();
         std::vector<int> tfc(sb.nT), tfr(sb.nT);
         for (int I = 0; I < sb.nT; ++I) {
@@ -585,11 +735,87 @@ int build_local_problems(gplmm_ctx* c) {
             c->env_urow.push_back(elems);
             elems += (int64_t)(last - I) * T * T;
         }
+    };
+    for (int sidx = 0; sidx < nsub; ++sidx) {
+        Sub& sb = c->subs[sidx];
+        sb.kind = sidx < c->Np ? 0 : 1;
+        sb.id = sidx < c->Np ? sidx : sidx - c->Np;
+        sb.sep0 = 0;
+        sb.skip_ss = 0;
+        const std::vector<int32_t>& cells = sb.kind == 0 ? prim_cells[sb.id] : c->dual_cells[sb.id];
+        std::vector<int64_t> u = unknowns_of(c, cells);
+        std::vector<std::pair<int64_t, int64_t>> keyed(u.size());
+        std::vector<int64_t> keys = local_keys(c, cells, u);
+        for (size_t t = 0; t < u.size(); ++t) keyed[t] = {keys[t], u[t]};
+        std::sort(keyed.begin(), keyed.end());
+        std::vector<int64_t> ordered(u.size());
+        for (size_t t = 0; t < u.size(); ++t) ordered[t] = keyed[t].second;
+        add_sub(sb, ordered, false);
+    }
+    // ---- nested dissection of the primaries whose blocks span more than split_tiles tiles
+    // (single images; the split parts follow the duals)
+    const int thr = c->opt.split_tiles == 0 ? 128 : c->opt.split_tiles;
+    if (thr > 0 && c->samples.size() <= 1) {
+        for (int i = 0; i < c->Np; ++i) {
+            if (c->subs[i].nT <= thr) continue;
+            std::vector<int64_t> A, B, S;
+            if (!plan_split(c, prim_cells[i], A, B, S)) continue;
+            Split sp;
+            sp.prim = i;
+            sp.nA = (int)A.size();
+            sp.nB = (int)B.size();
+            sp.nS = (int)S.size();
+            std::vector<int64_t> as(A), bs(B);
+            as.insert(as.end(), S.begin(), S.end());
+            bs.insert(bs.end(), S.begin(), S.end());
+            Sub sa{}, sbb{}, ss{};
+            sa.split = sbb.split = ss.split = -1;
+            sa.kind = sbb.kind = 2;
+            ss.kind = 3;
+            sa.id = sbb.id = ss.id = i;
+            sa.sep0 = sp.nA;
+            sbb.sep0 = sp.nB;
+            sbb.skip_ss = 1;
+            add_sub(sa, as, false);
+            add_sub(sbb, bs, false);
+            add_sub(ss, S, true);
+            sp.ld = ss.nT * T;
+            sp.inv_off = c->sinv_elems;
+            c->sinv_elems += (int64_t)sp.ld * sp.ld;
+            c->max_sep_ld = std::max(c->max_sep_ld, sp.ld);
+            sp.a_sub = (int)c->subs.size();
+            c->subs.push_back(sa);
+            sp.b_sub = (int)c->subs.size();
+            c->subs.push_back(sbb);
+            sp.s_sub = (int)c->subs.size();
+            c->subs.push_back(ss);
+            c->splits.push_back(sp);
+        }
     }
     c->factor_elems = elems;
-    // ---- LU schedules: set 0 = primaries, set 1 = primaries and duals
-    for (int set = 0; set < 2; ++set) {
-        int ns = set == 0 ? c->Np : nsub;
+    // ---- LU schedules: set 0 = the primaries' Schwarz blocks (split primaries by their two
+    // halves, eliminated up to the separator), set 1 = the primaries' closures and the
+    // duals, set 2 = the separators' Schur complements
+    std::vector<int> stop(c->subs.size());
+    for (size_t s = 0; s < c->subs.size(); ++s) {
+        Sub& sb = c->subs[s];
+        sb.split = -1;
+        stop[s] = sb.nT;
+    }
+    for (size_t k = 0; k < c->splits.size(); ++k) {
+        const Split& sp = c->splits[k];
+        c->subs[sp.prim].split = c->subs[sp.a_sub].split = c->subs[sp.b_sub].split = c->subs[sp.s_sub].split = (int)k;
+        stop[sp.a_sub] = sp.nA / T;
+        stop[sp.b_sub] = sp.nB / T;
+    }
+    for (int set = 0; set < 3; ++set) {
+        std::vector<int> members;
+        for (int s = 0; s < (int)c->subs.size(); ++s) {
+            const Sub& sb = c->subs[s];
+            const bool in = set == 0 ? ((sb.kind == 0 && sb.split < 0) || sb.kind == 2)
+                                     : (set == 1 ? s < nsub : sb.kind == 3);
+            if (in) members.push_back(s);
+        }
         auto& off = c->lu_step_off[set];
         auto& pr = c->lu_step_pairs[set];
         auto& soff = c->lu_sub_off[set];
@@ -599,10 +825,12 @@ int build_local_problems(gplmm_ctx* c) {
         pr.clear();
         sl.clear();
         double products = 0.0;   // T x T tile products of the factorisation (panels, updates)
-        for (int K = 0; K < c->maxT; ++K) {
-            for (int s = 0; s < ns; ++s) {
+        int steps = 0;
+        for (int s : members) steps = std::max(steps, stop[s]);
+        for (int K = 0; K < steps; ++K) {
+            for (int s : members) {
                 const Sub& sb = c->subs[s];
-                if (sb.nT <= K) continue;
+                if (stop[s] <= K) continue;
                 sl.push_back(s);
                 const int* tfc = &c->env_tfc[sb.env_off];
                 const int width = c->env_tlc[sb.env_off + K] - K;   // U panel tiles of step K

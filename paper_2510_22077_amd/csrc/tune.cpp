@@ -3,7 +3,7 @@
 // kernels, and where the batched triangular solves keep the subdomain solution (LDS
 // or HBM).  Results can be cached in a text file keyed by device architecture,
 // problem size and precision, one line per problem:
-//   <arch> <N> <Np> <Nc> <precision> <red_blocks> <stencil_block> <trsv_mode>
+//   <arch> <N> <Np> <Nc> <precision> s<split primaries> <red_blocks> <stencil_block> <trsv_mode>
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -16,6 +16,8 @@
 namespace gp {
 template <typename T>
 void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vin, T* out_local);
+template <typename T>
+void trsv_split(gplmm_ctx* c, const T* vin, T* loc);
 void dots2(gplmm_ctx* c, const double* V, int64_t ldv, int k, const double* y, int64_t n, double* a, double* b);
 double update2(gplmm_ctx* c, double* V, int64_t ldv, int j, const double* t, const double* s, double sj,
                double ainv, double* w, int64_t n);
@@ -60,7 +62,7 @@ double time_ms(gplmm_ctx* c, F f, int reps = 5) {
 std::string key_of(const gplmm_ctx* c) {
     std::ostringstream k;
     k << arch_name() << " " << c->N << " " << c->Np << " " << c->Nc << " "
-      << (c->opt.precision == GPLMM_FP32 ? "fp32" : "fp64");
+      << (c->opt.precision == GPLMM_FP32 ? "fp32" : "fp64") << " s" << c->splits.size();
     return k.str();
 }
 
@@ -70,7 +72,8 @@ double time_trsv(gplmm_ctx* c) {
     const T* v = (const T*)c->d_pv;
     return time_ms(c, [&]() {
         trsv_gather<T>(c, c->d_sub_ids + c->Np, c->Nc, v, loc);
-        trsv_gather<T>(c, c->d_sub_ids, c->Np, v, loc);
+        if (c->splits.empty()) trsv_gather<T>(c, c->d_sub_ids, c->Np, v, loc);
+        else trsv_split<T>(c, v, loc);
     });
 }
 
