@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--no-fp64-plain", action="store_true",
                     help="skip the comparison solve with the plain FP64 preconditioner")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--split-tiles", type=int, default=0,
+                    help="primaries spanning more tiles are solved by nested dissection (0, the library "
+                         "default, and -1: never)")
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-scale solver leg")
     ap.add_argument("--no-aplmm", action="store_true", help="skip the aPLMM_S / aPLMM_NS comparison solves")
     ap.add_argument("--no-pnm", action="store_true", help="skip the gPNM (pore-network decomposition) solve")
@@ -234,7 +237,8 @@ def main():
     log("workload %s generated in %.1f s" % (args.workload, time.perf_counter() - t0))
     t0 = time.perf_counter()
     s = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"],
-               precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart)
+               precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart,
+               split_tiles=args.split_tiles)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = s.info()
@@ -282,7 +286,8 @@ def main():
     l = (nvox - mask.sum()) / aw
     re = w["rho"] * (ud / phi) * l / w["mu"]
 
-    kt = {k: s.kernel_time(k) for k in ("trsv_p", "trsv_d", "precond_apply", "jv", "arnoldi", "lu",
+    kt = {k: s.kernel_time(k) for k in ("trsv_p", "trsv_p_fwd", "trsv_sep", "trsv_p_bwd", "trsv_d",
+                                         "precond_apply", "jv", "arnoldi", "lu",
                                          "build_closure_dual_lu", "build_shape", "build_primary_lu",
                                          "build_coarse")}
     for k, v in kt.items():
@@ -313,6 +318,7 @@ def main():
         "config": {"workload": "%s: 128^3 lognormal sphere packing (mean r 8, sigma 0.3), porosity %.3f, "
                                "seed %d, body force for Re~1, periodic x, steady NS" % (args.workload, phi, args.seed),
                    "unknowns": info["N"], "pores": info["Np"], "interfaces": info["Nc"],
+                   "split_pores": info["nsplit"], "separator_unknowns": info["sep_unknowns"],
                    "precision": args.precision, "restart": args.restart},
         "newton_its": st["newton_its"],
         "fgmres_its": st["lin_its"],

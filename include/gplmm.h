@@ -123,7 +123,9 @@ typedef struct {
     int split_tiles;         /* primaries whose Schwarz block spans more than this many 32-row tiles
                                 are solved by one level of nested dissection (two halves cut by a
                                 separator plane, solved in parallel, and the separator's Schur
-                                complement); 0 = default (128), -1 = never.  Single images only */
+                                complement); 0 (default) or -1 = never.  Single images only.  It
+                                shortens the longest substitution chain but adds the separator
+                                rows and a second launch: slower on the 128^3 packing */
 } gplmm_options;
 
 typedef struct {
@@ -352,7 +354,8 @@ int gplmm_set_timing(gplmm_ctx* ctx, int on);
  * the timed launches of a named kernel group since the last reset, recorded
  * with HIP events on the context's stream (see gplmm_set_timing); used for
  * roofline reporting.  name: "precond_apply", "trsv" (all local solves),
- * "trsv_p" (primary grids), "trsv_d" (dual grids), "jv", "arnoldi" (one
+ * "trsv_p" (primary grids; with split primaries its three phases "trsv_p_fwd",
+ * "trsv_sep" and "trsv_p_bwd" also, bytes 0), "trsv_d" (dual grids), "jv", "arnoldi" (one
  * Gram-Schmidt step), "lu" (one factorisation schedule), and the build phases
  * "build_closure_dual_lu", "build_shape", "build_primary_lu", "build_coarse".
  * Returns the number of samples. */

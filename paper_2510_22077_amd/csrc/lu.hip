@@ -534,24 +534,68 @@ __device__ __forceinline__ T tail_dot(const T* __restrict__ src, const T* y, int
 
 // buf[t] = tile t of a tile row for t < n (entries past the row keep stale values,
 // which buf_dot drops)
-template <typename T, int kPF>
-__device__ __forceinline__ void load_row(T (&buf)[kPF], const T* __restrict__ src, int n) {
-#pragma unroll
-    for (int t = 0; t < kPF; ++t)
-        if (t < n) buf[t] = src[(int64_t)t * kTT];
+// Buffer resource over the n tiles of a tile row (raw, bounds-checked: a load past the
+// range returns zero without a memory access).  Flags: the data-format word of CDNA3/4.
+constexpr int kBufFlags = 0x00020000;
+// (the row pointer and count are the same in every lane: taken from the first lane, so the
+// descriptor lives in scalar registers)
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T* row, int n) {
+    const uint64_t a = reinterpret_cast<uint64_t>(row);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    T* base = reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, __builtin_amdgcn_readfirstlane(n) * kTT * (int)sizeof(T),
+                                             kBufFlags);
 }
 
-// sum_{t < n} buf[t] y[t kT]; n is the same for the whole workgroup, so the loop leaves
-// at the end of the row with a uniform branch (no LDS read or product past the row)
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, byte_off, 0, 0));
+}
+
+// buf[t] = element `el` of tile t of a tile row of n tiles, t < kPF.  Every call issues
+// the same kPF loads (those past the row return zero and touch no memory): with a fixed
+// count the waits on a buffer can count exactly, whereas loads skipped by branches make
+// every later wait drain all loads in flight, including the rows prefetched ahead.
+template <typename T, int kPF>
+__device__ __forceinline__ void load_row(T (&buf)[kPF], const T* __restrict__ row, int n, int el) {
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, n);
+#pragma unroll
+    for (int t = 0; t < kPF; ++t) buf[t] = buf_ld<T>(rs, (t * kTT + el) * (int)sizeof(T));
+}
+
+// sum_{t < n} buf[t] y[t kT]; n is the same for the whole workgroup, so each term sits
+// behind a uniform branch (no LDS read or product past the row)
 template <typename T, int kPF>
 __device__ __forceinline__ T buf_dot(const T (&buf)[kPF], const T* y, int n) {
     T acc = 0;
 #pragma unroll
-    for (int t = 0; t < kPF; ++t) {
-        if (t >= n) break;
-        acc += buf[t] * y[t * kT];
-    }
+    for (int t = 0; t < kPF; ++t)
+        if (t < n) acc += buf[t] * y[t * kT];
     return acc;
+}
+
+// The per-row envelope of a subdomain (first L tile column, last U tile column, and the
+// offsets of the L and U tile rows from its first diagonal tile) staged in LDS, 4 nT ints
+// at m.  The substitutions read them from LDS: global loads complete in order, so waiting
+// for a global load of them would also wait for every factor load issued before it (the
+// tile rows prefetched ahead of the substitution).
+// An entry of the staged envelope, the same in every lane (read from LDS, made scalar so
+// that row pointers, counts and buffer ranges live in scalar registers)
+__device__ __forceinline__ int row_u(const int32_t* m, int i) { return __builtin_amdgcn_readfirstlane(m[i]); }
+
+__device__ __forceinline__ void stage_rows(const Env& e, const Sub& sb, int32_t* m, int tid, int nthr) {
+    for (int I = tid; I < sb.nT; I += nthr) {
+        const int64_t k = sb.env_off + I;
+        m[I] = e.tfc[k];
+        m[sb.nT + I] = e.tlc[k];
+        m[2 * sb.nT + I] = (int32_t)(e.lrow[k] - sb.diag_off);
+        m[3 * sb.nT + I] = (int32_t)(e.urow[k] - sb.diag_off);
+    }
 }
 
 // kLds: the subdomain's solution vector lives in LDS (dynamic, nT * T entries) during
@@ -574,9 +618,10 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
                                                         const int32_t* __restrict__ order,
                                                         const int32_t* __restrict__ slots, const T* __restrict__ vin,
                                                         T* __restrict__ out, const int64_t* __restrict__ off,
-                                                        int phase) {
+                                                        int phase, int mrows) {
     constexpr int kPF = pf_tiles<T>();
-    extern __shared__ unsigned char dyn_lds[];
+    extern __shared__ double2 sub_lds[];
+    unsigned char* dyn_lds = reinterpret_cast<unsigned char*>(sub_lds);
     __shared__ T part[kT];
     const int s = order[blockIdx.x];
     const Sub sb = e.subs[s];
@@ -590,14 +635,17 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     const bool half = phase != 0 && sb.kind == 2;
     const int stop = half ? sb.sep0 / kT : nT;   // rows eliminated by the substitutions
     const bool fwd = !half || phase == 1, bwd = !half || phase == 2;
-    T* x = kLds ? reinterpret_cast<T*>(dyn_lds) : xo;
+    T* x = kLds ? reinterpret_cast<T*>(dyn_lds + 16 * mrows) : xo;
     const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
-    const int32_t* tfc = e.tfc + sb.env_off;
-    const int32_t* tlc = e.tlc + sb.env_off;
-    const int64_t* lrow = e.lrow + sb.env_off;
-    const int64_t* urow = e.urow + sb.env_off;
+    int32_t* meta = reinterpret_cast<int32_t*>(dyn_lds);
+    stage_rows(e, sb, meta, tid, 1024);
+    const int32_t* tfc = meta;
+    const int32_t* tlc = meta + nT;
+    const int32_t* lrow = meta + 2 * nT;
+    const int32_t* urow = meta + 3 * nT;
     const int32_t* sl = slots + sb.slot_off;
-    const T* D = F + sb.diag_off + tid;
+    const T* Fd = F + sb.diag_off;
+    const T* D = Fd + tid;
     const int len = nT * kT;
     if (fwd) {
         const int nb = sb.skip_ss ? sb.sep0 : sb.n;
@@ -606,6 +654,7 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         const T* xs = out + off[e.splits[sb.split].s_sub];
         for (int i = tid; i < len; i += 1024) x[i] = i < stop * kT ? xo[i] : xs[i - stop * kT];
     }
+    __syncthreads();
     T bufA[kPF], bufB[kPF];
 #pragma unroll
     for (int t = 0; t < kPF; ++t) bufA[t] = bufB[t] = 0;
@@ -616,16 +665,16 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     // (the diagonal value of a row is fetched only after the row's diagonal product has
     // consumed the previous one, so that it reuses its register without a copy)
     // L tiles of row I taken by the substitution: columns below both I and stop
-    auto lcount = [&](int I) { return max(min(I, stop) - tfc[I], 0); };
+    auto lcount = [&](int I) { return max(min(I, stop) - row_u(tfc, I), 0); };
     auto fetch_l = [&](int I, T(&buf)[kPF], int& nb) {
         const int Ic = min(I, nT - 1);
         nb = min(lcount(Ic), kPF);
-        load_row(buf, F + lrow[Ic] + tid, nb);
+        load_row(buf, Fd + row_u(lrow, Ic), nb, tid);
     };
     auto fetch_u = [&](int I, T(&buf)[kPF], int& nb) {
         const int Ic = max(I, 0);
-        nb = min(tlc[Ic] - Ic, kPF);
-        load_row(buf, F + urow[Ic] + tid, nb);
+        nb = min(row_u(tlc, Ic) - Ic, kPF);
+        load_row(buf, Fd + row_u(urow, Ic), nb, tid);
     };
     if (fwd) {
         fetch_l(0, bufA, nA);
@@ -636,10 +685,10 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
     __syncthreads();
     // ---- forward: L y = b, row-oriented over L's contiguous tile rows
     auto fwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
-        const int j0 = tfc[I], nt = lcount(I);
+        const int j0 = row_u(tfc, I), nt = lcount(I);
         const T* y = x + j0 * kT + c;
         T acc = buf_dot(buf, y, nb);
-        if (nt > kPF) acc += tail_dot<T>(F + lrow[I] + tid, y, kPF, nt);
+        if (nt > kPF) acc += tail_dot<T>(Fd + row_u(lrow, I) + tid, y, kPF, nt);
         fetch_l(I + 2, buf, nb);
         acc = sum32(acc);
         if (I >= stop) {   // separator row of a half: no elimination, no dependency
@@ -653,19 +702,23 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         db = D[(int64_t)min(I + 2, nT - 1) * kTT];
         __syncthreads();
     };
+    // (every path back to the top of the loops runs both halves of the body, so the
+    // compiler's count of the loads in flight at the top stays exact)
     if (fwd) {
-        for (int I = 0; I < nT; I += 2) {
+        for (int I = 0;; I += 2) {
             fwd_row(I, bufA, nA, dA);
-            if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
+            if (I + 1 >= nT) break;
+            fwd_row(I + 1, bufB, nB, dB);
+            if (I + 2 >= nT) break;
         }
         __syncthreads();
     }
     // ---- backward: U x = y, row-oriented over U's contiguous tile rows (descending)
     auto bwd_row = [&](int I, T(&buf)[kPF], int& nb, T& db) {
-        const int nt = tlc[I] - I;
+        const int nt = row_u(tlc, I) - I;
         const T* y = x + (I + 1) * kT + c;
         T acc = buf_dot(buf, y, nb);
-        if (nt > kPF) acc += tail_dot<T>(F + urow[I] + tid, y, kPF, nt);
+        if (nt > kPF) acc += tail_dot<T>(Fd + row_u(urow, I) + tid, y, kPF, nt);
         fetch_u(I - 2, buf, nb);
         acc = sum32(acc);
         if (c == 0) part[r] = x[I * kT + r] - acc;
@@ -680,9 +733,11 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         fetch_u(stop - 2, bufB, nB);
         dA = D[(int64_t)(stop - 1) * kTT];
         dB = D[(int64_t)max(stop - 2, 0) * kTT];
-        for (int I = stop - 1; I >= 0; I -= 2) {
+        for (int I = stop - 1;; I -= 2) {
             bwd_row(I, bufA, nA, dA);
-            if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+            if (I < 1) break;
+            bwd_row(I - 1, bufB, nB, dB);
+            if (I < 2) break;
         }
     }
     if (kLds)
@@ -804,7 +859,7 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
                                                          const int32_t* __restrict__ order,
                                                          const int32_t* __restrict__ slots,
                                                          const T* __restrict__ vin, T* __restrict__ out,
-                                                         const int64_t* __restrict__ off) {
+                                                         const int64_t* __restrict__ off, int mrows) {
     constexpr int kPF = pf_small<T>();
     extern __shared__ double2 small_lds[];
     __shared__ __align__(16) T part[kT];
@@ -817,17 +872,21 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
         for (int i = threadIdx.x; i < nT * kT; i += blockDim.x) xo[i] = (T)0;
         return;
     }
-    T* x = reinterpret_cast<T*>(small_lds);
+    T* x = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(small_lds) + 16 * mrows);
     const int tid = threadIdx.x, r = tid >> 3, q = tid & 7;
     const int el = r * kT + 4 * q;   // first of this thread's four elements in a tile
-    const int32_t* tfc = e.tfc + sb.env_off;
-    const int32_t* tlc = e.tlc + sb.env_off;
-    const int64_t* lrow = e.lrow + sb.env_off;
-    const int64_t* urow = e.urow + sb.env_off;
+    int32_t* meta = reinterpret_cast<int32_t*>(small_lds);
+    stage_rows(e, sb, meta, tid, 256);
+    const int32_t* tfc = meta;
+    const int32_t* tlc = meta + nT;
+    const int32_t* lrow = meta + 2 * nT;
+    const int32_t* urow = meta + 3 * nT;
     const int32_t* sl = slots + sb.slot_off;
-    const T* D = F + sb.diag_off + el;
+    const T* Fd = F + sb.diag_off;
+    const T* D = Fd + el;
     const int len = nT * kT;
     for (int i = tid; i < len; i += 256) x[i] = i < sb.n ? vin[sl[i]] : (T)0;
+    __syncthreads();
     Quad<T> bufA[kPF], bufB[kPF];
     int nA = 0, nB = 0;
     Quad<T> dA, dB;
@@ -860,13 +919,13 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     };
     auto fetch_l = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = min(I, nT - 1);
-        nb = min(Ic - tfc[Ic], kPF);
-        load(buf, F + lrow[Ic] + el, nb);
+        nb = min(Ic - row_u(tfc, Ic), kPF);
+        load(buf, Fd + row_u(lrow, Ic) + el, nb);
     };
     auto fetch_u = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = max(I, 0);
-        nb = min(tlc[Ic] - Ic, kPF);
-        load(buf, F + urow[Ic] + el, nb);
+        nb = min(row_u(tlc, Ic) - Ic, kPF);
+        load(buf, Fd + row_u(urow, Ic) + el, nb);
     };
     fetch_l(0, bufA, nA);
     fetch_l(1, bufB, nB);
@@ -875,10 +934,10 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     __syncthreads();
     // ---- forward: L y = b (inv(L_II) strictly lower, unit diagonal implied)
     auto fwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
-        const int j0 = tfc[I], nt = I - j0;
+        const int j0 = row_u(tfc, I), nt = I - j0;
         const T* y = x + j0 * kT + 4 * q;
         T acc = dot(buf, y, nb);
-        if (nt > kPF) acc += tail(F + lrow[I] + el, y, kPF, nt);
+        if (nt > kPF) acc += tail(Fd + row_u(lrow, I) + el, y, kPF, nt);
         fetch_l(I + 2, buf, nb);
         acc = sum8(acc);
         if (q == 0) part[r] = x[I * kT + r] - acc;
@@ -901,10 +960,10 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     }
     // ---- backward: U x = y (inv(U_II) on and above the diagonal)
     auto bwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
-        const int nt = tlc[I] - I;
+        const int nt = row_u(tlc, I) - I;
         const T* y = x + (I + 1) * kT + 4 * q;
         T acc = dot(buf, y, nb);
-        if (nt > kPF) acc += tail(F + urow[I] + el, y, kPF, nt);
+        if (nt > kPF) acc += tail(Fd + row_u(urow, I) + el, y, kPF, nt);
         fetch_u(I - 2, buf, nb);
         acc = sum8(acc);
         if (q == 0) part[r] = x[I * kT + r] - acc;
@@ -942,7 +1001,7 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
                                                          const int32_t* __restrict__ order,
                                                          const int32_t* __restrict__ slots,
                                                          const T* __restrict__ vin, T* __restrict__ out,
-                                                         const int64_t* __restrict__ off) {
+                                                         const int64_t* __restrict__ off, int mrows) {
     // tiles per group held per register buffer (FP32: rows of up to 32 tiles, FP64: 16)
     constexpr int kPF = sizeof(T) == 4 ? 8 : 4;
     extern __shared__ double2 quad_lds[];
@@ -956,17 +1015,21 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
         for (int i = threadIdx.x; i < nT * kT; i += blockDim.x) xo[i] = (T)0;
         return;
     }
-    T* x = reinterpret_cast<T*>(quad_lds);
+    T* x = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(quad_lds) + 16 * mrows);
     const int tid = threadIdx.x, g = tid >> 8, r = (tid & 255) >> 3, q = tid & 7;
     const int el = r * kT + 4 * q;
-    const int32_t* tfc = e.tfc + sb.env_off;
-    const int32_t* tlc = e.tlc + sb.env_off;
-    const int64_t* lrow = e.lrow + sb.env_off;
-    const int64_t* urow = e.urow + sb.env_off;
+    int32_t* meta = reinterpret_cast<int32_t*>(quad_lds);
+    stage_rows(e, sb, meta, tid, 1024);
+    const int32_t* tfc = meta;
+    const int32_t* tlc = meta + nT;
+    const int32_t* lrow = meta + 2 * nT;
+    const int32_t* urow = meta + 3 * nT;
     const int32_t* sl = slots + sb.slot_off;
-    const T* D = F + sb.diag_off + el;
+    const T* Fd = F + sb.diag_off;
+    const T* D = Fd + el;
     const int len = nT * kT;
     for (int i = tid; i < len; i += 1024) x[i] = i < sb.n ? vin[sl[i]] : (T)0;
+    __syncthreads();
     Quad<T> bufA[kPF], bufB[kPF];
     int nA = 0, nB = 0;
     Quad<T> dA, dB;
@@ -993,13 +1056,13 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
     };
     auto fetch_l = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = min(I, nT - 1);
-        nb = mine(Ic - tfc[Ic]);
-        load(buf, F + lrow[Ic] + el, nb);
+        nb = mine(Ic - row_u(tfc, Ic));
+        load(buf, Fd + row_u(lrow, Ic) + el, nb);
     };
     auto fetch_u = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = max(I, 0);
-        nb = mine(tlc[Ic] - Ic);
-        load(buf, F + urow[Ic] + el, nb);
+        nb = mine(row_u(tlc, Ic) - Ic);
+        load(buf, Fd + row_u(urow, Ic) + el, nb);
     };
     fetch_l(0, bufA, nA);
     fetch_l(1, bufB, nB);
@@ -1020,10 +1083,10 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
     };
     // ---- forward: L y = b (inv(L_II) strictly lower, unit diagonal implied)
     auto fwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
-        const int j0 = tfc[I], nt = I - j0;
+        const int j0 = row_u(tfc, I), nt = I - j0;
         const T* y = x + j0 * kT + 4 * q;
         T acc = dot(buf, y, nb);
-        if (nt > 4 * kPF) acc += tail(F + lrow[I] + el, y, nt);
+        if (nt > 4 * kPF) acc += tail(Fd + row_u(lrow, I) + el, y, nt);
         fetch_l(I + 2, buf, nb);
         acc = sum8(acc);
         if (q == 0) part4[g][r] = g == 0 ? acc - x[I * kT + r] : acc;
@@ -1048,10 +1111,10 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
     }
     // ---- backward: U x = y (inv(U_II) on and above the diagonal)
     auto bwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
-        const int nt = tlc[I] - I;
+        const int nt = row_u(tlc, I) - I;
         const T* y = x + (I + 1) * kT + 4 * q;
         T acc = dot(buf, y, nb);
-        if (nt > 4 * kPF) acc += tail(F + urow[I] + el, y, nt);
+        if (nt > 4 * kPF) acc += tail(Fd + row_u(urow, I) + el, y, nt);
         fetch_u(I - 2, buf, nb);
         acc = sum8(acc);
         if (q == 0) part4[g][r] = g == 0 ? acc - x[I * kT + r] : acc;
@@ -1145,20 +1208,22 @@ void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vi
     const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)rows * (3.0 * sizeof(T) + 4.0);
     timer_begin(c, "trsv");
     timer_begin(c, duals ? "trsv_d" : "trsv_p");
-    const size_t lds = (size_t)c->maxT * kT * sizeof(T);
-    const size_t lds_set = (size_t)c->maxT_set[set] * kT * sizeof(T);
-    if (duals && lds_set <= kTrsvLdsMax)
-        trsv_small_kernel<T><<<nsub, 256, lds_set, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
-                                                               c->d_sub_slots, vin, out_local, c->d_local_off);
+    // dynamic LDS: the staged row envelopes (16 bytes per tile row), then the solution
+    const int mt = c->maxT_set[set];
+    const size_t meta = (size_t)16 * mt;
+    const size_t lds = meta + (size_t)mt * kT * sizeof(T);
+    const T* F = (const T*)c->d_factor;
+    const int32_t* ord = c->d_sub_order[set];
+    if (duals && lds <= kTrsvLdsMax)
+        trsv_small_kernel<T><<<nsub, 256, lds, c->stream>>>(e, F, ord, c->d_sub_slots, vin, out_local, c->d_local_off, mt);
     else if (lds <= kTrsvLdsMax && c->trsv_mode == 2)
-        trsv_quad_kernel<T><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
-                                                           c->d_sub_slots, vin, out_local, c->d_local_off);
+        trsv_quad_kernel<T><<<nsub, 1024, lds, c->stream>>>(e, F, ord, c->d_sub_slots, vin, out_local, c->d_local_off, mt);
     else if (lds <= kTrsvLdsMax && c->trsv_mode == 0)
-        trsv_sub_kernel<T, true><<<nsub, 1024, lds, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
-                                                                c->d_sub_slots, vin, out_local, c->d_local_off, 0);
+        trsv_sub_kernel<T, true><<<nsub, 1024, lds, c->stream>>>(e, F, ord, c->d_sub_slots, vin, out_local,
+                                                                c->d_local_off, 0, mt);
     else
-        trsv_sub_kernel<T, false><<<nsub, 1024, 0, c->stream>>>(e, (const T*)c->d_factor, c->d_sub_order[set],
-                                                               c->d_sub_slots, vin, out_local, c->d_local_off, 0);
+        trsv_sub_kernel<T, false><<<nsub, 1024, meta, c->stream>>>(e, F, ord, c->d_sub_slots, vin, out_local,
+                                                                  c->d_local_off, 0, mt);
     timer_end(c, duals ? "trsv_d" : "trsv_p", bytes);
     timer_end(c, "trsv", bytes);
 }
@@ -1178,21 +1243,29 @@ void trsv_split(gplmm_ctx* c, const T* vin, T* loc) {
     const double bytes = (double)sizeof(T) * (double)c->split_apply_elems + (double)c->prim_rows * (3.0 * sizeof(T) + 4.0);
     timer_begin(c, "trsv");
     timer_begin(c, "trsv_p");
-    const size_t lds1 = (size_t)c->maxT_phase1 * kT * sizeof(T), lds3 = (size_t)c->maxT_phase3 * kT * sizeof(T);
+    const int m1 = c->maxT_phase1, m3 = c->maxT_phase3;
+    const size_t lds1 = (size_t)16 * m1 + (size_t)m1 * kT * sizeof(T);
+    const size_t lds3 = (size_t)16 * m3 + (size_t)m3 * kT * sizeof(T);
+    timer_begin(c, "trsv_p_fwd");
     if (lds1 <= kTrsvLdsMax)
         trsv_sub_kernel<T, true><<<c->n_phase1, 1024, lds1, c->stream>>>(e, F, c->d_phase_order[0], c->d_sub_slots, vin,
-                                                                          loc, c->d_local_off, 1);
+                                                                          loc, c->d_local_off, 1, m1);
     else
-        trsv_sub_kernel<T, false><<<c->n_phase1, 1024, 0, c->stream>>>(e, F, c->d_phase_order[0], c->d_sub_slots, vin,
-                                                                        loc, c->d_local_off, 1);
+        trsv_sub_kernel<T, false><<<c->n_phase1, 1024, (size_t)16 * m1, c->stream>>>(
+            e, F, c->d_phase_order[0], c->d_sub_slots, vin, loc, c->d_local_off, 1, m1);
+    timer_end(c, "trsv_p_fwd", 0.0);
+    timer_begin(c, "trsv_sep");
     sep_solve_kernel<T><<<dim3(nsp, (c->max_sep_ld + 63) / 64), 256, (size_t)c->max_sep_ld * sizeof(T), c->stream>>>(
         e, (const T*)c->d_sinv, loc, c->d_local_off);
+    timer_end(c, "trsv_sep", 0.0);
+    timer_begin(c, "trsv_p_bwd");
     if (lds3 <= kTrsvLdsMax)
         trsv_sub_kernel<T, true><<<c->n_phase3, 1024, lds3, c->stream>>>(e, F, c->d_phase_order[1], c->d_sub_slots, vin,
-                                                                          loc, c->d_local_off, 2);
+                                                                          loc, c->d_local_off, 2, m3);
     else
-        trsv_sub_kernel<T, false><<<c->n_phase3, 1024, 0, c->stream>>>(e, F, c->d_phase_order[1], c->d_sub_slots, vin,
-                                                                        loc, c->d_local_off, 2);
+        trsv_sub_kernel<T, false><<<c->n_phase3, 1024, (size_t)16 * m3, c->stream>>>(
+            e, F, c->d_phase_order[1], c->d_sub_slots, vin, loc, c->d_local_off, 2, m3);
+    timer_end(c, "trsv_p_bwd", 0.0);
     timer_end(c, "trsv_p", bytes);
     timer_end(c, "trsv", bytes);
 }

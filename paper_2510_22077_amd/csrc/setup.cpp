@@ -754,7 +754,7 @@ int build_local_problems(gplmm_ctx* c) {
     }
     // ---- nested dissection of the primaries whose blocks span more than split_tiles tiles
     // (single images; the split parts follow the duals)
-    const int thr = c->opt.split_tiles == 0 ? 128 : c->opt.split_tiles;
+    const int thr = c->opt.split_tiles;   // 0 (default) and -1: never
     if (thr > 0 && c->samples.size() <= 1) {
         for (int i = 0; i < c->Np; ++i) {
             if (c->subs[i].nT <= thr) continue;
@@ -793,6 +793,12 @@ int build_local_problems(gplmm_ctx* c) {
         }
     }
     c->factor_elems = elems;
+    // the solves address a subdomain's tiles by 32-bit offsets from its first diagonal tile
+    for (size_t k = 0; k < c->subs.size(); ++k) {
+        const int64_t end = k + 1 < c->subs.size() ? c->subs[k + 1].diag_off : elems;
+        if (end - c->subs[k].diag_off > (int64_t)INT32_MAX)
+            return fail(c, GPLMM_E_ARG, "a local factor exceeds 2^31 elements");
+    }
     // ---- LU schedules: set 0 = the primaries' Schwarz blocks (split primaries by their two
     // halves, eliminated up to the separator), set 1 = the primaries' closures and the
     // duals, set 2 = the separators' Schur complements
