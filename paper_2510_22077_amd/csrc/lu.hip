@@ -831,6 +831,24 @@ __device__ __forceinline__ Quad<T> ld4(const T* p) {
     return q;
 }
 
+// the four elements at byte_off of a bounds-checked row buffer (zeros past the row)
+template <typename T>
+__device__ __forceinline__ Quad<T> buf_ld4(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 4) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0);
+        return __builtin_bit_cast(Quad<T>, v);
+    } else {
+        struct Two {
+            u32x4 a, b;
+        };
+        Two w;
+        w.a = __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0);
+        w.b = __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off + 16, 0, 0);
+        return __builtin_bit_cast(Quad<T>, w);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T dot4(const Quad<T>& a, const Quad<T>& b) {
     return a.v[0] * b.v[0] + a.v[1] * b.v[1] + a.v[2] * b.v[2] + a.v[3] * b.v[3];
@@ -890,18 +908,17 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     Quad<T> bufA[kPF], bufB[kPF];
     int nA = 0, nB = 0;
     Quad<T> dA, dB;
-    auto load = [&](Quad<T>(&buf)[kPF], const T* src, int n) {
+    // a fixed count of bounds-checked loads per row (see load_row)
+    auto load = [&](Quad<T>(&buf)[kPF], const T* row, int n) {
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, n);
 #pragma unroll
-        for (int t = 0; t < kPF; ++t)
-            if (t < n) buf[t] = ld4(src + (int64_t)t * kTT);
+        for (int t = 0; t < kPF; ++t) buf[t] = buf_ld4<T>(rs, (t * kTT + el) * (int)sizeof(T));
     };
     auto dot = [&](const Quad<T>(&buf)[kPF], const T* y, int n) {
         T acc = 0;
 #pragma unroll
-        for (int t = 0; t < kPF; ++t) {
-            if (t >= n) break;
-            acc += dot4(buf[t], ld4(y + t * kT));
-        }
+        for (int t = 0; t < kPF; ++t)
+            if (t < n) acc += dot4(buf[t], ld4(y + t * kT));
         return acc;
     };
     auto tail = [&](const T* src, const T* y, int t0, int nt) {
@@ -920,12 +937,12 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     auto fetch_l = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = min(I, nT - 1);
         nb = min(Ic - row_u(tfc, Ic), kPF);
-        load(buf, Fd + row_u(lrow, Ic) + el, nb);
+        load(buf, Fd + row_u(lrow, Ic), nb);
     };
     auto fetch_u = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = max(I, 0);
         nb = min(row_u(tlc, Ic) - Ic, kPF);
-        load(buf, Fd + row_u(urow, Ic) + el, nb);
+        load(buf, Fd + row_u(urow, Ic), nb);
     };
     fetch_l(0, bufA, nA);
     fetch_l(1, bufB, nB);
@@ -954,9 +971,11 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
         db = ld4(D + (int64_t)min(I + 2, nT - 1) * kTT);
         __syncthreads();
     };
-    for (int I = 0; I < nT; I += 2) {
+    for (int I = 0;; I += 2) {
         fwd_row(I, bufA, nA, dA);
-        if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
+        if (I + 1 >= nT) break;
+        fwd_row(I + 1, bufB, nB, dB);
+        if (I + 2 >= nT) break;
     }
     // ---- backward: U x = y (inv(U_II) on and above the diagonal)
     auto bwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
@@ -981,9 +1000,11 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     fetch_u(nT - 2, bufB, nB);
     dA = ld4(D + (int64_t)(nT - 1) * kTT);
     dB = ld4(D + (int64_t)max(nT - 2, 0) * kTT);
-    for (int I = nT - 1; I >= 0; I -= 2) {
+    for (int I = nT - 1;; I -= 2) {
         bwd_row(I, bufA, nA, dA);
-        if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+        if (I < 1) break;
+        bwd_row(I - 1, bufB, nB, dB);
+        if (I < 2) break;
     }
     for (int i = tid; i < len; i += 256) xo[i] = x[i];
 }
