@@ -702,15 +702,16 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         db = D[(int64_t)min(I + 2, nT - 1) * kTT];
         __syncthreads();
     };
-    // (every path back to the top of the loops runs both halves of the body, so the
-    // compiler's count of the loads in flight at the top stays exact)
+    // (the loop bodies have no exit between their two rows: a path from the first row back
+    // to the top would make the compiler take the first buffer's loads as the latest at the
+    // top and wait for every load in flight there)
     if (fwd) {
-        for (int I = 0;; I += 2) {
+        int I = 0;
+        for (; I + 1 < nT; I += 2) {
             fwd_row(I, bufA, nA, dA);
-            if (I + 1 >= nT) break;
             fwd_row(I + 1, bufB, nB, dB);
-            if (I + 2 >= nT) break;
         }
+        if (I < nT) fwd_row(I, bufA, nA, dA);
         __syncthreads();
     }
     // ---- backward: U x = y, row-oriented over U's contiguous tile rows (descending)
@@ -733,12 +734,12 @@ __global__ void __launch_bounds__(1024) trsv_sub_kernel(Env e, const T* __restri
         fetch_u(stop - 2, bufB, nB);
         dA = D[(int64_t)(stop - 1) * kTT];
         dB = D[(int64_t)max(stop - 2, 0) * kTT];
-        for (int I = stop - 1;; I -= 2) {
+        int I = stop - 1;
+        for (; I >= 1; I -= 2) {
             bwd_row(I, bufA, nA, dA);
-            if (I < 1) break;
             bwd_row(I - 1, bufB, nB, dB);
-            if (I < 2) break;
         }
+        if (I == 0) bwd_row(0, bufA, nA, dA);
     }
     if (kLds)
         for (int i = tid; i < len; i += 1024) xo[i] = x[i];
@@ -971,12 +972,12 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
         db = ld4(D + (int64_t)min(I + 2, nT - 1) * kTT);
         __syncthreads();
     };
-    for (int I = 0;; I += 2) {
-        fwd_row(I, bufA, nA, dA);
-        if (I + 1 >= nT) break;
-        fwd_row(I + 1, bufB, nB, dB);
-        if (I + 2 >= nT) break;
+    int I0 = 0;
+    for (; I0 + 1 < nT; I0 += 2) {   // no exit between the two rows (see trsv_sub_kernel)
+        fwd_row(I0, bufA, nA, dA);
+        fwd_row(I0 + 1, bufB, nB, dB);
     }
+    if (I0 < nT) fwd_row(I0, bufA, nA, dA);
     // ---- backward: U x = y (inv(U_II) on and above the diagonal)
     auto bwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
         const int nt = row_u(tlc, I) - I;
@@ -1000,12 +1001,12 @@ __global__ void __launch_bounds__(256) trsv_small_kernel(Env e, const T* __restr
     fetch_u(nT - 2, bufB, nB);
     dA = ld4(D + (int64_t)(nT - 1) * kTT);
     dB = ld4(D + (int64_t)max(nT - 2, 0) * kTT);
-    for (int I = nT - 1;; I -= 2) {
-        bwd_row(I, bufA, nA, dA);
-        if (I < 1) break;
-        bwd_row(I - 1, bufB, nB, dB);
-        if (I < 2) break;
+    int I1 = nT - 1;
+    for (; I1 >= 1; I1 -= 2) {
+        bwd_row(I1, bufA, nA, dA);
+        bwd_row(I1 - 1, bufB, nB, dB);
     }
+    if (I1 == 0) bwd_row(0, bufA, nA, dA);
     for (int i = tid; i < len; i += 256) xo[i] = x[i];
 }
 
