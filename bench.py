@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--coarse-increments", type=int, default=3,
                     help="body-force steps of the coarse-scale solver (one step from rest stalls at "
                          "128^3, as Algorithm 1 warns for starts far from the solution)")
+    ap.add_argument("--no-continuation", action="store_true",
+                    help="skip the Re 10 solves (direct, and continuation through half the force)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the extra solve on the finer pore split (about 1.5k pores)")
     ap.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
@@ -369,6 +371,33 @@ def main():
                                 "fine_rel_residual": stc["fine_rel_residual"], "t_build_ms": stc["t_build_ms"],
                                 "E2_p_percent": e_p, "E2_speed_percent": e_u,
                                 "speedup_vs_fine_solve": sec / tc}
+    # Reynolds-number continuation (Section 8's protocol) at Re ~ 10 on the same packing:
+    # one direct Newton solve against raising the force in two steps (half, then full)
+    if not args.no_continuation:
+        log("Re 10: direct solve and continuation ...")
+        wr = make_workload(args.workload, args.seed, re=10.0)
+        sr = Solver(wr["mask"], wr["labels"], rho=wr["rho"], mu=wr["mu"], body=wr["body"],
+                    precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart,
+                    lin_maxit=4000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, sd = sr.newton_solve()
+        torch.cuda.synchronize()
+        td = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, sc_, rcc = sr.continuation([0.5, 1.0])
+        torch.cuda.synchronize()
+        tcn = time.perf_counter() - t0
+        out["re10_continuation"] = {
+            "body_x": wr["body"][0], "re_target": 10.0,
+            "direct": {"s": td, "newton_its": sd["newton_its"], "fgmres_its_total": sd["lin_its_total"],
+                       "converged": sd["converged"]},
+            "continuation_half_full": {"s": tcn, "newton_its": [q["newton_its"] for q in sc_],
+                                       "fgmres_its_total": [q["lin_its_total"] for q in sc_],
+                                       "converged": rcc == 0}}
+        sr.close()
+        del sr
+        torch.cuda.empty_cache()
     if not args.no_fp64_plain:
         log("plain FP64 preconditioner on the same workload ...")
         del s

@@ -338,6 +338,18 @@ typedef struct {
 void gplmm_coarse_default_options(gplmm_coarse_options* opt);
 int gplmm_coarse_solve(gplmm_ctx* ctx, const gplmm_coarse_options* opt, double* x_dev, gplmm_coarse_stats* stats);
 
+/* Reynolds-number continuation (the protocol of Section 8: the driving force raised in
+ * steps, Newton warm-started from the previous step, the preconditioner of each step built
+ * from the previous step's velocity).  The body force of step k is scales[k] times the
+ * context's; scales increase within (0, 1] and end at 1.  Step 0 runs gplmm_newton_solve
+ * from x as given (wind by options.wind_mode); step k > 0 builds once with w = x and runs
+ * Newton from x.  x_dev (device, N doubles) is the initial state in and the solution at the
+ * full force out; stats (host, steps entries) receives each step's statistics (its build
+ * counted in t_build_ms and builds).  Single steady images only.  Returns 0 when every step
+ * converged, 1 when a step stopped unconverged (later steps are not run), < 0 on error;
+ * the context's body force and wind mode are restored either way. */
+int gplmm_continuation(gplmm_ctx* ctx, int steps, const double* scales, double* x_dev, gplmm_stats* stats);
+
 /* Progress report of long solves: fn(user, k, its, rel) is called on the host after every
  * FGMRES restart cycle of Newton step k (its = FGMRES iterations of the step so far,
  * rel = -1) and after every Newton step (its = the step's FGMRES iterations, rel = the

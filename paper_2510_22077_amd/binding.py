@@ -84,7 +84,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_setup_batch", "gplmm_batch_info",
            "gplmm_sample_residuals", "gplmm_layout_info", "gplmm_get_maps",
-           "gplmm_get_duals", "gplmm_get_subdomains", "gplmm_get_split", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
+           "gplmm_get_duals", "gplmm_get_subdomains", "gplmm_get_split", "gplmm_continuation", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
            "gplmm_precond_apply", "gplmm_get_coarse", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
            "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy",
            "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
@@ -138,6 +138,8 @@ def load():
     lib.gplmm_get_subdomains.restype = I
     lib.gplmm_get_split.argtypes = [P, I, P, P]
     lib.gplmm_get_split.restype = I
+    lib.gplmm_continuation.argtypes = [P, I, P, P, P]
+    lib.gplmm_continuation.restype = I
     for f in ("gplmm_residual", "gplmm_matvec"):
         getattr(lib, f).argtypes = [P, P, P, P]
         getattr(lib, f).restype = I
@@ -457,6 +459,17 @@ class Solver:
         d = st.as_dict()
         d["rc"] = rc
         return x, d
+
+    def continuation(self, scales, x0=None):
+        """Reynolds-number continuation (gplmm_continuation): the body force raised through
+        the given fractions (increasing, ending at 1); returns (x, [stats of each step], rc)."""
+        sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64))
+        x = self.zeros() if x0 is None else self._vec(x0).clone()
+        sts = (Stats * len(sc))()
+        rc = self.lib.gplmm_continuation(self.ctx, len(sc), sc.ctypes.data, _ptr(x), sts)
+        if rc < 0:
+            self._check(rc, "continuation")
+        return x, [sts[k].as_dict() for k in range(len(sc))], rc
 
     def coarse_solve(self, increments=1, newton_maxit=50, tol=1e-6):
         """Coarse-scale solver (gplmm_coarse_solve): returns (x, stats)."""

@@ -1420,6 +1420,47 @@ int gplmm_coarse_solve(gplmm_ctx* c, const gplmm_coarse_options* opt, double* x,
     return S->converged ? GPLMM_OK : 1;
 }
 
+int gplmm_continuation(gplmm_ctx* c, int steps, const double* scales, double* x, gplmm_stats* st) {
+    if (!c) return GPLMM_E_ARG;
+    if (!c->ready) return fail(c, GPLMM_E_STATE, "no device state (host-only context)");
+    if (!x || !scales || !st) return GPLMM_E_ARG;
+    if (!c->csamp.empty()) return fail(c, GPLMM_E_ARG, "the continuation takes a single image");
+    if (c->phys.dt > 0.0) return fail(c, GPLMM_E_ARG, "the continuation is for the steady equations");
+    if (steps < 1 || steps > 64) return fail(c, GPLMM_E_ARG, "continuation: 1 <= steps <= 64");
+    for (int k = 0; k < steps; ++k)
+        if (!(scales[k] > (k ? scales[k - 1] : 0.0)) || scales[k] > 1.0)
+            return fail(c, GPLMM_E_ARG, "continuation: scales must increase within (0, 1]");
+    if (scales[steps - 1] != 1.0) return fail(c, GPLMM_E_ARG, "continuation: the last scale must be 1");
+    const Phys full = c->phys;
+    const int mode = c->opt.wind_mode;
+    int rc = GPLMM_OK;
+    for (int k = 0; k < steps; ++k) {
+        for (int a = 0; a < 3; ++a) c->phys.body[a] = full.body[a] * scales[k];
+        std::memset(&st[k], 0, sizeof(gplmm_stats));
+        if (k > 0) {
+            // the preconditioner of each later step is built once from the velocity of the
+            // step before (Section 8's protocol), and Newton starts from that state
+            auto t0 = std::chrono::steady_clock::now();
+            GP_HIP(c, hipMemcpyAsync(c->d_wind, x, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
+            rc = do_build(c);
+            if (rc != GPLMM_OK) break;
+            c->opt.wind_mode = GPLMM_WIND_CALLER;
+            const double tb = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            rc = gplmm_newton_solve(c, nullptr, x, &st[k]);
+            st[k].t_build_ms += tb;
+            st[k].t_total_ms += tb;
+            st[k].builds += 1;
+        } else {
+            rc = gplmm_newton_solve(c, nullptr, x, &st[k]);
+        }
+        c->opt.wind_mode = mode;
+        if (rc != GPLMM_OK) break;
+    }
+    c->phys = full;
+    c->opt.wind_mode = mode;
+    return rc;
+}
+
 int gplmm_sample_residuals(gplmm_ctx* c, const double* x, const double* xprev, double* out) {
     if (!c || !x || !out) return GPLMM_E_ARG;
     if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
