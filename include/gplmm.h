@@ -385,8 +385,8 @@ typedef struct {
     int red_blocks;          /* blocks of the Krylov dot-product / update kernels */
     int stencil_block;       /* threads per block of the stencil kernels */
     int trsv_mode;           /* primary-grid solves: 0 subdomain solution kept in LDS, one element
-                                of each tile per thread; 1 solution in HBM; 2 in LDS, four groups
-                                of 256 threads on interleaved tiles, 16-byte loads */
+                                of each tile per thread; 1 solution in HBM; 2 (default) in LDS,
+                                four groups of 256 threads on interleaved tiles, 16-byte loads */
     int from_cache;          /* 1 when read from the cache file instead of measured */
     double t_reduction_ms;   /* best measured Gram-Schmidt step (half a restart cycle of vectors) */
     double t_stencil_ms;     /* best measured X v + J v */
@@ -396,7 +396,8 @@ typedef struct {
 /* Measure the candidate launch parameters on this problem (reduction blocks 256..2048,
  * stencil blocks 128/256/512, triangular-solve variant when the preconditioner is
  * built) and keep the fastest for every later call on ctx.  cache_path (may be NULL): a
- * text file of earlier results, one line per (architecture, N, Np, Nc, precision); a
+ * text file of earlier results, one line per (architecture, N, Np, Nc, precision, split
+ * primaries); a
  * matching line is used without measuring, a new result is appended.  Calls that
  * overlap on one context race.  Errors: GPLMM_E_STATE (host-only), GPLMM_E_HIP. */
 int gplmm_autotune(gplmm_ctx* ctx, const char* cache_path, gplmm_tuning* out);

@@ -262,7 +262,7 @@ struct gplmm_ctx {
     // launch parameters chosen by gplmm_autotune (defaults until then)
     int red_blocks = 1024;               // blocks of the Krylov reductions (<= 2048)
     int stencil_block = 256;             // threads per block of the stencil kernels (<= 512)
-    int trsv_mode = 0;                   // primary-solve variant (gplmm_tuning.trsv_mode)
+    int trsv_mode = 2;                   // primary-solve variant (gplmm_tuning.trsv_mode)
     // graph of one preconditioner application (captured on first use, replayed after)
     hipGraph_t apply_graph = nullptr;
     hipGraphExec_t apply_exec = nullptr;

@@ -1057,18 +1057,18 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
     Quad<T> dA, dB;
     // this group's tiles of a row of nt tiles: g, g + 4, ... (a count uniform over each wave)
     auto mine = [&](int nt) { return nt > g ? min((nt - g + 3) >> 2, kPF) : 0; };
-    auto load = [&](Quad<T>(&buf)[kPF], const T* src, int n) {
+    // a fixed count of bounds-checked loads per row (see load_row): tiles g, g + 4, ... of
+    // a row of nt tiles
+    auto load = [&](Quad<T>(&buf)[kPF], const T* row, int nt) {
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, min(nt, 4 * kPF));
 #pragma unroll
-        for (int u = 0; u < kPF; ++u)
-            if (u < n) buf[u] = ld4(src + (int64_t)(g + 4 * u) * kTT);
+        for (int u = 0; u < kPF; ++u) buf[u] = buf_ld4<T>(rs, ((g + 4 * u) * kTT + el) * (int)sizeof(T));
     };
     auto dot = [&](const Quad<T>(&buf)[kPF], const T* y, int n) {
         T acc = 0;
 #pragma unroll
-        for (int u = 0; u < kPF; ++u) {
-            if (u >= n) break;
-            acc += dot4(buf[u], ld4(y + (g + 4 * u) * kT));
-        }
+        for (int u = 0; u < kPF; ++u)
+            if (u < n) acc += dot4(buf[u], ld4(y + (g + 4 * u) * kT));
         return acc;
     };
     auto tail = [&](const T* src, const T* y, int nt) {
@@ -1078,13 +1078,15 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
     };
     auto fetch_l = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = min(I, nT - 1);
-        nb = mine(Ic - row_u(tfc, Ic));
-        load(buf, Fd + row_u(lrow, Ic) + el, nb);
+        const int nt = Ic - row_u(tfc, Ic);
+        nb = mine(nt);
+        load(buf, Fd + row_u(lrow, Ic), nt);
     };
     auto fetch_u = [&](int I, Quad<T>(&buf)[kPF], int& nb) {
         const int Ic = max(I, 0);
-        nb = mine(row_u(tlc, Ic) - Ic);
-        load(buf, Fd + row_u(urow, Ic) + el, nb);
+        const int nt = row_u(tlc, Ic) - Ic;
+        nb = mine(nt);
+        load(buf, Fd + row_u(urow, Ic), nt);
     };
     fetch_l(0, bufA, nA);
     fetch_l(1, bufB, nB);
@@ -1127,10 +1129,12 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
         }
         __syncthreads();
     };
-    for (int I = 0; I < nT; I += 2) {
-        fwd_row(I, bufA, nA, dA);
-        if (I + 1 < nT) fwd_row(I + 1, bufB, nB, dB);
+    int I0 = 0;
+    for (; I0 + 1 < nT; I0 += 2) {   // no exit between the two rows (see trsv_sub_kernel)
+        fwd_row(I0, bufA, nA, dA);
+        fwd_row(I0 + 1, bufB, nB, dB);
     }
+    if (I0 < nT) fwd_row(I0, bufA, nA, dA);
     // ---- backward: U x = y (inv(U_II) on and above the diagonal)
     auto bwd_row = [&](int I, Quad<T>(&buf)[kPF], int& nb, Quad<T>& db) {
         const int nt = row_u(tlc, I) - I;
@@ -1158,10 +1162,12 @@ __global__ void __launch_bounds__(1024) trsv_quad_kernel(Env e, const T* __restr
     }
     fetch_u(nT - 1, bufA, nA);
     fetch_u(nT - 2, bufB, nB);
-    for (int I = nT - 1; I >= 0; I -= 2) {
-        bwd_row(I, bufA, nA, dA);
-        if (I >= 1) bwd_row(I - 1, bufB, nB, dB);
+    int I1 = nT - 1;
+    for (; I1 >= 1; I1 -= 2) {
+        bwd_row(I1, bufA, nA, dA);
+        bwd_row(I1 - 1, bufB, nB, dB);
     }
+    if (I1 == 0) bwd_row(0, bufA, nA, dA);
     for (int i = tid; i < len; i += 1024) xo[i] = x[i];
 }
 

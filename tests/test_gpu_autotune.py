@@ -30,6 +30,7 @@ def test_every_variant_gives_the_same_preconditioner(precision):
     s = _solver(precision)
     s.build()
     v = s.residual(torch.randn(s.N, dtype=torch.float64, device="cuda"))
+    s.set_tuning(red_blocks=1024, stencil_block=256, trsv_mode=0)   # the reference: variant 0
     ref = s.precond_apply(v).clone()
     # variants 0 and 1 run the same arithmetic in the same order (bit-identical); variant 2
     # sums each row's tiles in four interleaved groups, a different rounding order: its

@@ -49,7 +49,11 @@ def test_graph_replays_match_eager_launches(precision):
     assert torch.equal(zg, ze)
     # new launch parameters: the graph is captured again
     s.set_tuning(red_blocks=512, stencil_block=128, trsv_mode=1)
-    assert torch.equal(s.precond_apply(v), ze)
+    zg = s.precond_apply(v).clone()
+    s.set_timing(True)
+    ze = s.precond_apply(v).clone()
+    s.set_timing(False)
+    assert torch.equal(zg, ze)
     s.close()
 
 
