@@ -75,6 +75,8 @@ int64_t coarse_pos(const gplmm_ctx* c, int row, int col) {
 int upload_all(gplmm_ctx* c) {
     const int64_t nc = c->ncell, N = c->N;
     const int T = c->tile;
+    // the Krylov kernels address a vector with 32-bit byte offsets
+    if (N > (int64_t)INT32_MAX / 8) return fail(c, GPLMM_E_ARG, "more than 2^28 unknowns");
     // geometry
     GP_TRY(upload(c, &c->d_nb6, c->nbr));
     GP_TRY(upload(c, &c->d_tag, c->tagcell));

@@ -170,15 +170,35 @@ __global__ void __launch_bounds__(kThreads) multidot2_kernel(const double* __res
         double ax[kGroup], ay[kGroup];
 #pragma unroll
         for (int q = 0; q < kGroup; ++q) ax[q] = ay[q] = 0.0;
-        for (int64_t r = r0; r < n; r += stride) {
-            const double xr = x[r], yr = y[r];
+        // two rows per trip through bounds-checked buffers (one per column, x and y: loads
+        // past the end or of columns past k return zero), twenty loads in flight per thread
+        // with one row offset each
+        __amdgpu_buffer_rsrc_t rv[kGroup];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q)
-                if (q < kk) {
-                    const double v = Vg[(int64_t)q * ldv + r];
-                    ax[q] += v * xr;
-                    ay[q] += v * yr;
-                }
+        for (int q = 0; q < kGroup; ++q)
+            rv[q] = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(Vg + (int64_t)q * ldv), 0,
+                                                      q < kk ? (int)(n * 8) : 0, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(x), 0, (int)(n * 8), 0x00020000);
+        const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(y), 0, (int)(n * 8), 0x00020000);
+        auto ld = [](__amdgpu_buffer_rsrc_t rs, int64_t row) {
+            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(row * 8), 0, 0));
+        };
+        for (int64_t r = r0; r < n; r += 2 * stride) {
+            const int64_t r2 = r + stride;
+            double v1[kGroup], v2[kGroup];
+            const double x1 = ld(rx, r), y1 = ld(ry, r), x2 = ld(rx, r2), y2 = ld(ry, r2);
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                v1[q] = ld(rv[q], r);
+                v2[q] = ld(rv[q], r2);
+            }
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                ax[q] += v1[q] * x1;
+                ay[q] += v1[q] * y1;
+                ax[q] += v2[q] * x2;
+                ay[q] += v2[q] * y2;
+            }
         }
         wave_sums16(ax, ay, lane, sh[wv]);
         __syncthreads();
