@@ -157,11 +157,11 @@ def _train_mlp(m, feats, targets, epochs=60, seed=0):
     return float(loss), float(np.var(T))
 
 
-def _measured_traffic(workload, precision):
+def _measured_traffic(kernel, workload, precision):
     """HBM bytes per launch of the skyline-solve kernel from the committed PMC summary, if
     it was taken on this workload and precision with the current kernel source."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "trsv_sub_kernel_traffic_%s_%s.txt" % (workload, precision))
+    path = os.path.join(ROOT, "profiles", "%s_traffic_%s_%s.txt" % (kernel, workload, precision))
     src = os.path.join(ROOT, "paper_2510_22077_amd", "csrc", "lu.hip")
     if not os.path.exists(path):
         return None
@@ -175,6 +175,37 @@ def _measured_traffic(workload, precision):
     if kv.get("source_sha256") != sha:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def _sensitivity(args):
+    """FGMRES iterations of the steady solve of the 64^3 corner of the packing against the
+    dual-grid dilations (0, 1, 2; tag layers 1) and the tag layers (0, 1, 2; no dilation),
+    at Re 1, 10 and 20 (FP32 preconditioner, restart 256, at most 600 FGMRES iterations per
+    Newton step and 12 Newton steps).  One JSON line."""
+    import torch
+    from synth import make_workload
+    from paper_2510_22077_amd import Solver
+    rows = []
+    for re in (1.0, 10.0, 20.0):
+        w = make_workload(args.workload, args.seed, re=re)
+        m, lab = w["mask"][:64, :64, :64].copy(), w["labels"][:64, :64, :64].copy()
+        for dd, tl in ((0, 0), (0, 1), (0, 2), (1, 1), (2, 1)):
+            s = Solver(m, lab, rho=w["rho"], mu=w["mu"], body=w["body"], precision="fp32", restart=256,
+                       dual_dilations=dd, tag_layers=tl, newton_tol=1e-8, lin_tol=1e-9, lin_maxit=600,
+                       newton_maxit=12)
+            s.set_progress(lambda k, its, r: print("  newton %d: %d its, rel %.2e" % (k, its, r), file=sys.stderr,
+                                                   flush=True) if r >= 0 else None)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = s.newton_solve()
+            torch.cuda.synchronize()
+            row = {"re": re, "dual_dilations": dd, "tag_layers": tl, "converged": bool(st["converged"]),
+                   "newton_its": st["newton_its"], "fgmres_its": st["lin_its"], "fgmres_total": st["lin_its_total"],
+                   "s": time.perf_counter() - t0}
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            rows.append(row)
+            s.close()
+    print(json.dumps({"sensitivity": rows, "workload": "%s seed %d, 64^3 corner" % (args.workload, args.seed)}))
 
 
 def main():
@@ -202,6 +233,9 @@ def main():
     ap.add_argument("--coarse-increments", type=int, default=3,
                     help="body-force steps of the coarse-scale solver (one step from rest stalls at "
                          "128^3, as Algorithm 1 warns for starts far from the solution)")
+    ap.add_argument("--sensitivity", action="store_true",
+                    help="only run the decomposition sensitivity study on the 64^3 corner of the packing: "
+                         "FGMRES iterations against dual dilations and tag layers at Re 1, 10 and 20")
     ap.add_argument("--no-continuation", action="store_true",
                     help="skip the Re 10 solves (direct, and continuation through half the force)")
     ap.add_argument("--no-variants", action="store_true",
@@ -219,6 +253,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
+    if args.sensitivity:
+        _sensitivity(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path (it would shard "
@@ -300,7 +337,11 @@ def main():
     nb = stt["builds"]
     ph = {k: kt[k]["avg_ms"] * kt[k]["samples"] / max(nb, 1) for k in
           ("build_closure_dual_lu", "build_shape", "build_primary_lu", "build_coarse")}
-    tr = kt["trsv_p"]   # trsv_sub_kernel: the primary grids' solves, the dominant launch
+    tr = kt["trsv_p"]   # the primary grids' solves, the dominant launch
+    # the variant that ran: four-group 16-byte loads (2, the default) or one element per thread
+    trsv_mode = tuning["trsv_mode"] if tuning else 2
+    # (FP64 factors of a primary over 255 tiles exceed the LDS bound: one-element variant)
+    trsv_kernel = "trsv_quad_kernel" if trsv_mode == 2 and args.precision == "fp32" else "trsv_sub_kernel"
     achieved = tr["bytes"] / (tr["avg_ms"] * 1e-3) / 1e9 if tr["avg_ms"] > 0 else 0.0
     ap_ = kt["precond_apply"]
     apply_gbs = ap_["bytes"] / (ap_["avg_ms"] * 1e-3) / 1e9 if ap_["avg_ms"] > 0 else 0.0
@@ -334,10 +375,10 @@ def main():
         "reynolds": re,
         "precond_apply_ms": ap_["avg_ms"],
         "precond_apply_GBps": apply_gbs,
-        "roofline": {"bound": "hbm", "kernel": "trsv_sub_kernel (batched skyline triangular solves of the primary grids)",
+        "roofline": {"bound": "hbm", "kernel": "%s (batched skyline triangular solves of the primary grids)" % trsv_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _measured_traffic(args.workload, args.precision),
+                     "traffic": _measured_traffic(trsv_kernel, args.workload, args.precision),
                      "avg_launch_ms": tr["avg_ms"], "algorithmic_bytes_per_launch": tr["bytes"],
                      "launches": tr["samples"]},
         "kernel_times": kt,
