@@ -17,7 +17,13 @@ Paper:
   over every row of the primary (the 0/1 pattern of C^T) (Section 3.2.2);
 * compact form M_G^-1 = Phat (Rhat A Phat)^-1 Rhat with A in place of the
   column-summed operator (Section 3.2.2, Remark 1); Phat leaves the f-faces
-  at zero;
+  at zero (``mg_form=0``, the default);
+* or the full form of Eq. iMG (``mg_form=1``): the coarse operator
+  Rhat Acheck Phat from the column-summed matrix Acheck (the p and c rows after
+  both reductions: f columns, and for primary rows the other primaries'
+  columns, summed onto the diagonal), and the f unknowns recovered by the
+  back-substitution of Eq. xf, x^f = (A^f_f)^-1 (b^f - A^f_p x^p - A^f_c x^c),
+  i.e. x^f = (A^f_f)^-1 (b - A x)^f with x^f = 0 in x;
 * dual-primary smoother M_dp^-1 = M_d^-1 + M_p^-1 (I - A M_d^-1), with the
   additive-Schwarz sums over primaries and duals (Section 3.2.3).
 
@@ -48,6 +54,8 @@ class GPLMM:
     lu_p: list
     lu_d: list
     Abar: list
+    mg_form: int = 0                  # 0: Remark 1; 1: Eq. iMG with the x^f back-substitution
+    lu_f: object = None               # mg_form 1: LU of A^f_f
     t_mg: float = 0.0                 # seconds spent on M_G (closures, shape vectors, Ao)
     t_ml: float = 0.0                 # seconds spent on the smoother's local factorisations
 
@@ -64,7 +72,29 @@ def closure_matrix(X, S, cols_summed, exempt=None):
     return (XS + sp.diags(extra)).tocsc()
 
 
-def build(X, dc: Decomp, bB):
+def column_summed(X, dc: Decomp, owner_all):
+    """The p and c rows of Acheck (Eq. iMG): row s keeps its columns in its own
+    primary and in the interface cells (a primary row) or outside the f-faces (an
+    interface-cell row); the columns it drops are summed onto its diagonal (the two
+    reductions of Section 3.2.2), except on rows of faces in wall-free groups, which
+    drop them.  f rows are zero (Rhat has no f columns)."""
+    g = dc.g
+    Xc = sp.coo_matrix(X)
+    r, c, v = Xc.row, Xc.col, Xc.data
+    orow, ocol = owner_all[r], owner_all[c]
+    prow = orow >= 0
+    crow = orow == -2
+    keep = (prow & ((ocol == orow) | (ocol == -2))) | (crow & (ocol != -1))
+    move = (prow & ~keep) | (crow & (ocol == -1))
+    exempt = np.zeros(g.N, dtype=bool)
+    exempt[:g.nu] = dc.free
+    move &= ~exempt[r]
+    diag = np.bincount(r[move], weights=v[move], minlength=g.N)
+    A = sp.csr_matrix((v[keep], (r[keep], c[keep])), shape=X.shape)
+    return (A + sp.diags(diag)).tocsr()
+
+
+def build(X, dc: Decomp, bB, mg_form=0):
     import time
     t0 = time.perf_counter()
     X = sp.csr_matrix(X)
@@ -129,14 +159,21 @@ def build(X, dc: Decomp, bB):
         Rc.append(dc.S[i])
     R = sp.csr_matrix((np.ones(sum(a.size for a in Rr)), (np.concatenate(Rr), np.concatenate(Rc))),
                       shape=(nco, N))
-    Ao = (R @ X @ P).toarray()
+    lu_f = None
+    if mg_form == 1:
+        Ao = (R @ column_summed(X, dc, owner_all) @ P).toarray()
+        F = np.asarray(dc.f_faces, dtype=np.int64)
+        if F.size:
+            lu_f = spla.splu(X[F][:, F].tocsc())
+    else:
+        Ao = (R @ X @ P).toarray()
     Ao_lu = _dense_lu(Ao)
     t1 = time.perf_counter()
     lu_p = [spla.splu(X[S][:, S].tocsc()) for S in dc.S]
     lu_d = [spla.splu(X[D][:, D].tocsc()) for D in dc.D]
     t2 = time.perf_counter()
     return GPLMM(X=X, dc=dc, phi=phi, chi=chi, ycols=ycols, P=P, R=R, Ao=Ao, Ao_lu=Ao_lu,
-                 lu_p=lu_p, lu_d=lu_d, Abar=Abar, t_mg=t1 - t0, t_ml=t2 - t1)
+                 lu_p=lu_p, lu_d=lu_d, Abar=Abar, mg_form=mg_form, lu_f=lu_f, t_mg=t1 - t0, t_ml=t2 - t1)
 
 
 def _dense_lu(A):
@@ -154,8 +191,12 @@ def coarse_solve(M: GPLMM, rhs):
 
 
 def apply_MG(M: GPLMM, v):
-    """z_G = Phat (Rhat X Phat)^-1 Rhat v."""
-    return M.P @ coarse_solve(M, M.R @ v)
+    """z_G = Phat Ao^-1 Rhat v; with Eq. iMG the f entries then follow from Eq. xf."""
+    z = M.P @ coarse_solve(M, M.R @ v)
+    if M.mg_form == 1 and M.lu_f is not None:
+        F = np.asarray(M.dc.f_faces, dtype=np.int64)
+        z[F] = M.lu_f.solve((v - M.X @ z)[F])
+    return z
 
 
 def apply_Md(M: GPLMM, r):

@@ -34,8 +34,13 @@ def csum(B):
     return B.sum(axis=1) if B.shape[1] else np.zeros(B.shape[0])
 
 
-def literal_preconditioner(Ahat, dc, bB):
-    """Dense M^-1 (N x N) and M_G^-1 built literally from the paper's matrices."""
+def literal_preconditioner(Ahat, dc, bB, mg_form=0):
+    """Dense M^-1 (N x N) and M_G^-1 built literally from the paper's matrices.
+
+    mg_form 0: the Remark-1 form Phat (Rhat A_hat Phat)^-1 Rhat.  mg_form 1: Eq. iMG,
+    Phat (Rhat Acheck Phat)^-1 Rhat with Acheck = W C(W^T A_hat W) W^T, where C(.) is
+    the two reductions (so Rhat Acheck Phat = R Q^T Abar Q P), followed by Eq. xf for
+    the f unknowns: x^f = (A^f_f)^-1 (b^f - A^f_p x^p - A^f_c x^c)."""
     Ahat = np.asarray(Ahat, dtype=float)
     g = dc.g
     N = g.N
@@ -123,7 +128,16 @@ def literal_preconditioner(Ahat, dc, bB):
     RQ = np.zeros((Nc + ny, N))
     RQ[:, :npf + ncf] = R @ Q.T
     Rhat = RQ @ W.T
-    MG = Phat @ np.linalg.solve(Rhat @ Ahat @ Phat, Rhat)
+    if mg_form == 1:
+        MG = Phat @ np.linalg.solve(R @ AM @ P, Rhat)
+        if F_.stop > F_.start:
+            # x^f from Eq. xf, in the original order: z_f = A_ff^-1 (b - A_hat z)_f
+            Ef = W[:, F_]
+            Aff = A[F_, F_]
+            Sf = Ef @ np.linalg.solve(Aff, Ef.T)
+            MG = (np.eye(N) - Sf @ Ahat) @ MG + Sf
+    else:
+        MG = Phat @ np.linalg.solve(Rhat @ Ahat @ Phat, Rhat)
     # --- additive Schwarz smoothers
     def schwarz(sets):
         out = np.zeros((N, N))

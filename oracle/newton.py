@@ -38,7 +38,7 @@ class NewtonStats:
     converged: bool = False
 
 
-def build_precond(ops, dc, phys, wind, build="geometric"):
+def build_precond(ops, dc, phys, wind, build="geometric", mg_form=0):
     """gPLMM from X = J~_w (Section 4), or, with build="jacobian", the algebraic aPLMM
     from the Newton Jacobian at the state w (no tags; w = None gives the Stokes
     matrix, i.e. aPLMM_S)."""
@@ -49,14 +49,14 @@ def build_precond(ops, dc, phys, wind, build="geometric"):
         X = build_matrix(ops, phys, wind=wind, tags=dc.tags)
     bB = origin_rhs(ops, phys)
     t_asm = time.perf_counter() - t
-    M = G.build(X, dc, bB)
+    M = G.build(X, dc, bB, mg_form=mg_form)
     M.t_mg += t_asm            # assembling X counts with the M_G build
     return M
 
 
 def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
           maxit=30, restart=30, lin_maxit=600, wind="stokes", wind_vec=None,
-          precond="gplmm", stats=None, line_search=False, build="geometric"):
+          precond="gplmm", stats=None, line_search=False, build="geometric", mg_form=0):
     """Newton-FGMRES with gPLMM.  ``precond``: "gplmm" or "exact" (spsolve).
 
     ``build``: "geometric" (gPLMM, Section 4) or "jacobian" (aPLMM from the Newton
@@ -79,7 +79,7 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
     M = None
     if precond == "gplmm":
         w = wind_vec if wind == "caller" else None
-        M = build_precond(ops, dc, phys, w, build)
+        M = build_precond(ops, dc, phys, w, build, mg_form)
         st.t_mg += M.t_mg
         st.t_ml += M.t_ml
     r = residual(ops, x, phys, x_old=x_old)
@@ -90,7 +90,7 @@ def solve(ops, dc, phys: Phys, x0=None, x_old=None, tol=1e-8, lin_tol=None,
             st.converged = True
             break
         if k == 1 and precond == "gplmm" and wind == "stokes":
-            M = build_precond(ops, dc, phys, x, build)
+            M = build_precond(ops, dc, phys, x, build, mg_form)
             st.t_mg += M.t_mg
             st.t_ml += M.t_ml
         J = jacobian(ops, x, phys)

@@ -53,14 +53,17 @@ def _tiny_3d(seed=1):
     return m, lab
 
 
+@pytest.mark.parametrize("mg_form", [0, 1])
 @pytest.mark.parametrize("maker,wind_seed,dt", [(_tiny_2d, None, None), (_tiny_2d, 5, None),
                                                 (_tiny_3d, None, None), (_tiny_3d, 7, 0.5)])
-def test_sparse_gplmm_matches_literal_matrices(maker, wind_seed, dt):
+def test_sparse_gplmm_matches_literal_matrices(maker, wind_seed, dt, mg_form):
     m, lab = maker()
     g, ops, dc, ph, X, bB = _case(m, lab, body=(1.0, 0.2, 0.1), wind_seed=wind_seed, dt=dt)
     assert dc.Np >= 2 and dc.Nc >= 1
-    M = G.build(X, dc, bB)
-    Mlit, MGlit = literal_preconditioner(X.toarray(), dc, bB)
+    if mg_form == 1:
+        assert dc.f_faces.size >= 1      # the back-substitution of Eq. xf has work to do
+    M = G.build(X, dc, bB, mg_form=mg_form)
+    Mlit, MGlit = literal_preconditioner(X.toarray(), dc, bB, mg_form=mg_form)
     rng = np.random.default_rng(0)
     for _ in range(3):
         v = rng.standard_normal(g.N)
@@ -88,7 +91,8 @@ def test_single_pore_preconditioner_is_exact_inverse():
 @pytest.mark.parametrize("dims,per", [((1, 8, 24), (True, False, False)),
                                       ((6, 8, 24), (True, False, False)),
                                       ((6, 8, 24), (True, False, True))])
-def test_slab_channel_coarse_solve_is_poiseuille(dims, per):
+@pytest.mark.parametrize("mg_form", [0, 1])
+def test_slab_channel_coarse_solve_is_poiseuille(dims, per, mg_form):
     nz, ny, nx = dims
     m = channel(nx, ny, nz)
     lab = np.zeros_like(m, dtype=np.int32)
@@ -96,7 +100,7 @@ def test_slab_channel_coarse_solve_is_poiseuille(dims, per):
         lab[:, :, s * 6:(s + 1) * 6] = s + 1
     g, ops, dc, ph, X, bB = _case(m, lab, periodic=per)
     assert dc.Np == 4 and dc.Nc == 4
-    M = G.build(X, dc, bB)
+    M = G.build(X, dc, bB, mg_form=mg_form)
     xg = G.apply_MG(M, bB)
     xs = spla.spsolve(X.tocsc(), bB)
     assert np.linalg.norm(xg - xs) <= 1e-12 * np.linalg.norm(xs)
@@ -113,6 +117,25 @@ def test_remark1_coarse_operator_is_a_projection():
     a = G.apply_MG(M, X @ v)
     b = G.apply_MG(M, X @ a)
     assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(a)
+
+
+def test_column_summed_form_is_not_a_projection():
+    """Proposition 1: with the column-summed operator of Eq. iMG, M_G^-1 A is not a
+    projection (it is one in the Remark-1 form, previous test); the x^f of Eq. xf makes
+    A z_G and the right-hand side agree on the f rows."""
+    m, lab = _tiny_3d()
+    g, ops, dc, ph, X, bB = _case(m, lab, wind_seed=3)
+    M = G.build(X, dc, bB, mg_form=1)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal(g.N)
+    a = G.apply_MG(M, X @ v)
+    b = G.apply_MG(M, X @ a)
+    assert np.linalg.norm(a - b) >= 1e-6 * np.linalg.norm(a)
+    F = dc.f_faces
+    assert F.size >= 1
+    w = rng.standard_normal(g.N)
+    z = G.apply_MG(M, w)
+    assert np.linalg.norm((X @ z - w)[F]) <= 1e-11 * np.linalg.norm(w)
 
 
 def test_correction_sign_does_not_change_coarse_operator():
@@ -278,3 +301,19 @@ def test_aplmm_ns_from_the_newton_jacobian_converges():
     assert np.linalg.norm(xa - xe) <= 1e-9 * np.linalg.norm(xe)
     assert np.linalg.norm(xg - xe) <= 1e-9 * np.linalg.norm(xe)
     print("FGMRES its gPLMM %s, aPLMM_NS %s" % (sg.lin_its, sa.lin_its))
+
+
+def test_column_summed_form_newton_converges_to_the_same_solution():
+    """Newton-FGMRES with the Eq. iMG coarse correction ends at the solution the
+    Remark-1 form reaches (the preconditioner changes the iterations, not the answer)."""
+    from oracle import newton
+    w = make_workload("disks2d_32", 2, re=10.0)
+    m = largest_component(w["mask"], (True, False, False))
+    g = MacGrid(m, periodic=(True, False, False))
+    ops = Operators(g)
+    dc = decompose(g, w["labels"])
+    ph = Phys(w["rho"], w["mu"], tuple(w["body"]), None, dc.pin)
+    x0, s0 = newton.solve(ops, dc, ph, tol=1e-11)
+    x1, s1 = newton.solve(ops, dc, ph, tol=1e-11, mg_form=1)
+    assert s0.res_hist[-1] <= 1e-11 and s1.res_hist[-1] <= 1e-11
+    assert np.linalg.norm(x1 - x0) <= 1e-8 * np.linalg.norm(x0)
