@@ -225,6 +225,9 @@ def main():
     ap.add_argument("--split-tiles", type=int, default=0,
                     help="primaries spanning more tiles are solved by nested dissection (0, the library "
                          "default, and -1: never)")
+    ap.add_argument("--mg-form", type=int, default=0, choices=[0, 1, 2],
+                    help="coarse correction: 0 the compact form of Remark 1 (default), 1 Eq. iMG with the "
+                         "back-substitution of Eq. xf, 2 the compact form with that back-substitution")
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-scale solver leg")
     ap.add_argument("--no-aplmm", action="store_true", help="skip the aPLMM_S / aPLMM_NS comparison solves")
     ap.add_argument("--no-pnm", action="store_true", help="skip the gPNM (pore-network decomposition) solve")
@@ -277,7 +280,7 @@ def main():
     t0 = time.perf_counter()
     s = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"],
                precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart,
-               split_tiles=args.split_tiles)
+               split_tiles=args.split_tiles, mg_form=args.mg_form)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = s.info()
@@ -325,7 +328,7 @@ def main():
     l = (nvox - mask.sum()) / aw
     re = w["rho"] * (ud / phi) * l / w["mu"]
 
-    kt = {k: s.kernel_time(k) for k in ("trsv_p", "trsv_p_fwd", "trsv_sep", "trsv_p_bwd", "trsv_d",
+    kt = {k: s.kernel_time(k) for k in ("trsv_p", "trsv_p_fwd", "trsv_sep", "trsv_p_bwd", "trsv_d", "trsv_f",
                                          "precond_apply", "jv", "arnoldi", "lu",
                                          "build_closure_dual_lu", "build_shape", "build_primary_lu",
                                          "build_coarse")}
@@ -362,7 +365,8 @@ def main():
                                "seed %d, body force for Re~1, periodic x, steady NS" % (args.workload, phi, args.seed),
                    "unknowns": info["N"], "pores": info["Np"], "interfaces": info["Nc"],
                    "split_pores": info["nsplit"], "separator_unknowns": info["sep_unknowns"],
-                   "precision": args.precision, "restart": args.restart},
+                   "precision": args.precision, "restart": args.restart, "mg_form": args.mg_form,
+                   "f_blocks": info.get("nfblock", 0)},
         "newton_its": st["newton_its"],
         "fgmres_its": st["lin_its"],
         "fgmres_its_total": st["lin_its_total"],
@@ -553,6 +557,32 @@ def main():
                                            "interfaces": sv.info()["Nc"], "newton_its": stv["newton_its"],
                                            "fgmres_its_total": stv["lin_its_total"], "t_build_ms": stv["t_build_ms"]}
         del sv
+        torch.cuda.empty_cache()
+    if not args.no_variants and args.mg_form == 0:
+        # the same solve with the f-faces' unknowns of the coarse correction recovered by the
+        # back-substitution of Eq. xf (mg_form 2) instead of left at zero
+        log("coarse correction with the Eq. xf back-substitution ...")
+        sx = Solver(w["mask"], w["labels"], rho=w["rho"], mu=w["mu"], body=w["body"],
+                    precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart, mg_form=2)
+        if not args.no_autotune:
+            sx.build()
+            sx.autotune()
+        for k in range(args.warmup):
+            sx.newton_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            xx_, stx = sx.newton_solve()
+        torch.cuda.synchronize()
+        tx = (time.perf_counter() - t0) / args.steps
+        dx = float((xx_ - x).norm().item() / x.norm().item())
+        out["variant_eq_xf_back_substitution"] = {
+            "s": tx, "speedup_vs_value": sec / tx, "mg_form": 2, "f_blocks": sx.info()["nfblock"],
+            "f_unknowns": sx.info()["f_unknowns"], "newton_its": stx["newton_its"], "fgmres_its": stx["lin_its"],
+            "fgmres_its_total": stx["lin_its_total"], "t_build_ms": stx["t_build_ms"],
+            "final_rel_residual": stx["res_hist"][-1], "rel_diff_to_value_solution": dx}
+        log("Eq. xf variant: %s" % json.dumps(out["variant_eq_xf_back_substitution"]))
+        del sx
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a %d^3 crop) ..." % args.cpu_crop)

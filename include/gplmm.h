@@ -126,6 +126,15 @@ typedef struct {
                                 complement); 0 (default) or -1 = never.  Single images only.  It
                                 shortens the longest substitution chain but adds the separator
                                 rows and a second launch: slower on the 128^3 packing */
+    int mg_form;             /* coarse correction: 0 (default) the compact form of Remark 1,
+                                Phat (Rhat X Phat)^-1 Rhat with the f unknowns left at zero;
+                                1 the full form of Eq. iMG, the coarse operator Rhat Xcheck Phat
+                                from the column-summed matrix (the two reductions of Section
+                                3.2.2 applied to X) and the f unknowns from the back-substitution
+                                of Eq. xf; 2 the compact form followed by the same
+                                back-substitution of Eq. xf.  With 1 and 2 every application
+                                solves the diagonal blocks of A^f_f and applies X once more.
+                                Single images only; not with split_tiles */
 } gplmm_options;
 
 typedef struct {
@@ -142,6 +151,9 @@ typedef struct {
                                 product of the closure, dual, primary and separator LU schedules */
     int nsplit;              /* primaries solved by nested dissection (options.split_tiles) */
     int64_t sep_unknowns;    /* unknowns on their separators */
+    int nfblock;             /* options.mg_form 1, 2: diagonal blocks of A^f_f (connected f-face sets) */
+    int max_fblock;          /* unknowns of the largest of them */
+    int64_t f_unknowns;      /* f-faces (velocity unknowns owned by no primary) */
 } gplmm_layout;
 
 typedef struct {
@@ -258,6 +270,14 @@ int gplmm_get_subdomains(const gplmm_ctx* ctx, int32_t* n, int64_t* factor_elems
  * of range. */
 int gplmm_get_split(const gplmm_ctx* ctx, int k, int32_t* info, int32_t* slots);
 
+/* Diagonal blocks of A^f_f used by the back-substitution of Eq. xf (options.mg_form 1, 2):
+ * the f-faces (velocity unknowns owned by no primary) grouped into the connected sets of
+ * X's couplings among them, so that A^f_f is block diagonal over the blocks.  ptr
+ * (layout.nfblock + 1 entries) gets the offsets of the blocks in slots; slots
+ * (layout.f_unknowns entries, may be NULL) the record slots of each block, ascending.
+ * Host arrays owned by the caller; with mg_form 0 there are no blocks (ptr[0] = 0). */
+int gplmm_get_fblocks(const gplmm_ctx* ctx, int64_t* ptr, int32_t* slots);
+
 /* r = r(x): the MAC residual of the momentum and mass equations (Section 1;
  * backward Euler against x_prev when dt > 0, x_prev may be NULL = 0; the pinned
  * cell's mass row is p = 0).  All pointers are device vectors of N doubles. */
@@ -367,7 +387,8 @@ int gplmm_set_timing(gplmm_ctx* ctx, int on);
  * with HIP events on the context's stream (see gplmm_set_timing); used for
  * roofline reporting.  name: "precond_apply", "trsv" (all local solves),
  * "trsv_p" (primary grids; with split primaries its three phases "trsv_p_fwd",
- * "trsv_sep" and "trsv_p_bwd" also, bytes 0), "trsv_d" (dual grids), "jv", "arnoldi" (one
+ * "trsv_sep" and "trsv_p_bwd" also, bytes 0), "trsv_d" (dual grids), "trsv_f" (the blocks
+ * of A^f_f of options.mg_form 1 and 2), "jv", "arnoldi" (one
  * Gram-Schmidt step), "lu" (one factorisation schedule), and the build phases
  * "build_closure_dual_lu", "build_shape", "build_primary_lu", "build_coarse".
  * Returns the number of samples. */
@@ -454,7 +475,8 @@ const char* gplmm_mlp_last_error(const gplmm_mlp* mlp);
  * (see gplmm_coarse_entries); an operator that cannot be factorised falls back to the
  * exact one, and gplmm_newton_solve redoes a Newton step with the exact operator when
  * FGMRES misses its tolerance.  The model stays owned by the caller and must outlive
- * its use. */
+ * its use.  GPLMM_E_ARG for a context with options.mg_form 1 (the model predicts the
+ * entries of Rhat X Phat). */
 int gplmm_set_coarse_model(gplmm_ctx* ctx, gplmm_mlp* model);
 
 /* The structural entries of the coarse operator (row, col: coarse ids, interfaces first,

@@ -24,6 +24,8 @@ Paper:
   columns, summed onto the diagonal), and the f unknowns recovered by the
   back-substitution of Eq. xf, x^f = (A^f_f)^-1 (b^f - A^f_p x^p - A^f_c x^c),
   i.e. x^f = (A^f_f)^-1 (b - A x)^f with x^f = 0 in x;
+* or (``mg_form=2``) the compact coarse operator of Remark 1 followed by the
+  same back-substitution of Eq. xf for the f unknowns;
 * dual-primary smoother M_dp^-1 = M_d^-1 + M_p^-1 (I - A M_d^-1), with the
   additive-Schwarz sums over primaries and duals (Section 3.2.3).
 
@@ -54,8 +56,9 @@ class GPLMM:
     lu_p: list
     lu_d: list
     Abar: list
-    mg_form: int = 0                  # 0: Remark 1; 1: Eq. iMG with the x^f back-substitution
-    lu_f: object = None               # mg_form 1: LU of A^f_f
+    mg_form: int = 0                  # 0: Remark 1; 1: Eq. iMG with the x^f back-substitution;
+                                      # 2: Remark 1 with the x^f back-substitution
+    lu_f: object = None               # mg_form 1, 2: LU of A^f_f
     t_mg: float = 0.0                 # seconds spent on M_G (closures, shape vectors, Ao)
     t_ml: float = 0.0                 # seconds spent on the smoother's local factorisations
 
@@ -162,11 +165,12 @@ def build(X, dc: Decomp, bB, mg_form=0):
     lu_f = None
     if mg_form == 1:
         Ao = (R @ column_summed(X, dc, owner_all) @ P).toarray()
+    else:
+        Ao = (R @ X @ P).toarray()
+    if mg_form in (1, 2):
         F = np.asarray(dc.f_faces, dtype=np.int64)
         if F.size:
             lu_f = spla.splu(X[F][:, F].tocsc())
-    else:
-        Ao = (R @ X @ P).toarray()
     Ao_lu = _dense_lu(Ao)
     t1 = time.perf_counter()
     lu_p = [spla.splu(X[S][:, S].tocsc()) for S in dc.S]
@@ -191,9 +195,9 @@ def coarse_solve(M: GPLMM, rhs):
 
 
 def apply_MG(M: GPLMM, v):
-    """z_G = Phat Ao^-1 Rhat v; with Eq. iMG the f entries then follow from Eq. xf."""
+    """z_G = Phat Ao^-1 Rhat v; with mg_form 1 or 2 the f entries then follow from Eq. xf."""
     z = M.P @ coarse_solve(M, M.R @ v)
-    if M.mg_form == 1 and M.lu_f is not None:
+    if M.mg_form in (1, 2) and M.lu_f is not None:
         F = np.asarray(M.dc.f_faces, dtype=np.int64)
         z[F] = M.lu_f.solve((v - M.X @ z)[F])
     return z

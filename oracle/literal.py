@@ -40,7 +40,8 @@ def literal_preconditioner(Ahat, dc, bB, mg_form=0):
     mg_form 0: the Remark-1 form Phat (Rhat A_hat Phat)^-1 Rhat.  mg_form 1: Eq. iMG,
     Phat (Rhat Acheck Phat)^-1 Rhat with Acheck = W C(W^T A_hat W) W^T, where C(.) is
     the two reductions (so Rhat Acheck Phat = R Q^T Abar Q P), followed by Eq. xf for
-    the f unknowns: x^f = (A^f_f)^-1 (b^f - A^f_p x^p - A^f_c x^c)."""
+    the f unknowns: x^f = (A^f_f)^-1 (b^f - A^f_p x^p - A^f_c x^c).  mg_form 2: the
+    Remark-1 form followed by the same Eq. xf."""
     Ahat = np.asarray(Ahat, dtype=float)
     g = dc.g
     N = g.N
@@ -128,8 +129,11 @@ def literal_preconditioner(Ahat, dc, bB, mg_form=0):
     RQ = np.zeros((Nc + ny, N))
     RQ[:, :npf + ncf] = R @ Q.T
     Rhat = RQ @ W.T
-    if mg_form == 1:
-        MG = Phat @ np.linalg.solve(R @ AM @ P, Rhat)
+    if mg_form in (1, 2):
+        if mg_form == 1:
+            MG = Phat @ np.linalg.solve(R @ AM @ P, Rhat)
+        else:
+            MG = Phat @ np.linalg.solve(Rhat @ Ahat @ Phat, Rhat)
         if F_.stop > F_.start:
             # x^f from Eq. xf, in the original order: z_f = A_ff^-1 (b - A_hat z)_f
             Ef = W[:, F_]

@@ -27,7 +27,8 @@ class Options(ctypes.Structure):
                 ("lin_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int),
                 ("lin_maxit", ctypes.c_int), ("tile", ctypes.c_int), ("host_only", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("line_search", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("build_matrix", ctypes.c_int), ("split_tiles", ctypes.c_int)]
+                ("build_matrix", ctypes.c_int), ("split_tiles", ctypes.c_int),
+                ("mg_form", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -42,7 +43,8 @@ class Layout(ctypes.Structure):
                 ("Nc", ctypes.c_int), ("Ny", ctypes.c_int), ("pin", ctypes.c_int64),
                 ("ndual_cells", ctypes.c_int64), ("local_unknowns", ctypes.c_int64),
                 ("factor_bytes", ctypes.c_int64), ("ncolors", ctypes.c_int), ("lu_flops", ctypes.c_double),
-                ("nsplit", ctypes.c_int), ("sep_unknowns", ctypes.c_int64)]
+                ("nsplit", ctypes.c_int), ("sep_unknowns", ctypes.c_int64), ("nfblock", ctypes.c_int),
+                ("max_fblock", ctypes.c_int), ("f_unknowns", ctypes.c_int64)]
 
 
 class CoarseOptions(ctypes.Structure):
@@ -84,7 +86,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["gplmm_default_options", "gplmm_setup", "gplmm_setup_batch", "gplmm_batch_info",
            "gplmm_sample_residuals", "gplmm_layout_info", "gplmm_get_maps",
-           "gplmm_get_duals", "gplmm_get_subdomains", "gplmm_get_split", "gplmm_continuation", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
+           "gplmm_get_duals", "gplmm_get_subdomains", "gplmm_get_split", "gplmm_get_fblocks", "gplmm_continuation", "gplmm_residual", "gplmm_matvec", "gplmm_build_matvec", "gplmm_build",
            "gplmm_precond_apply", "gplmm_get_coarse", "gplmm_newton_solve", "gplmm_set_timing", "gplmm_kernel_time",
            "gplmm_reset_timers", "gplmm_last_error", "gplmm_destroy",
            "gplmm_mlp_create", "gplmm_mlp_num_params", "gplmm_mlp_set_params", "gplmm_mlp_get_params",
@@ -138,6 +140,8 @@ def load():
     lib.gplmm_get_subdomains.restype = I
     lib.gplmm_get_split.argtypes = [P, I, P, P]
     lib.gplmm_get_split.restype = I
+    lib.gplmm_get_fblocks.argtypes = [P, P, P]
+    lib.gplmm_get_fblocks.restype = I
     lib.gplmm_continuation.argtypes = [P, I, P, P, P]
     lib.gplmm_continuation.restype = I
     for f in ("gplmm_residual", "gplmm_matvec"):
@@ -237,7 +241,7 @@ class Solver:
     def _prepare(self, nx, ny, nz, h=1.0, periodic=(1, 0, 0), precision="fp64", wind="stokes", tag_layers=1,
                  dual_dilations=-1, restart=30, newton_tol=1e-8, lin_tol=1e-9, newton_maxit=30, lin_maxit=600,
                  host_only=False, stream=None, line_search=False, use_graph=True, build_matrix="geometric",
-                 split_tiles=0):
+                 split_tiles=0, mg_form=0):
         lib = load()
         self.lib = lib
         self.ctx = ctypes.c_void_p()
@@ -261,6 +265,7 @@ class Solver:
         o.use_graph = 1 if use_graph else 0
         o.build_matrix = {"geometric": 0, "jacobian": 1}[build_matrix]
         o.split_tiles = int(split_tiles)
+        o.mg_form = int(mg_form)
         self.torch = None
         if not host_only:
             import torch
@@ -373,6 +378,14 @@ class Solver:
             self._check(self.lib.gplmm_get_split(self.ctx, k, info.ctypes.data, slots.ctypes.data), "get_split")
             out.append(dict(prim=int(info[0]), nA=int(info[1]), nB=int(info[2]), nS=int(info[3]), slots=slots))
         return out
+
+    def fblocks(self):
+        """Blocks of A^f_f for the back-substitution of Eq. xf (mg_form 1, 2): a list of
+        arrays of record slots, one per block."""
+        ptr = np.zeros(self.layout.nfblock + 1, np.int64)
+        slots = np.zeros(max(int(self.layout.f_unknowns), 1), np.int32)
+        self._check(self.lib.gplmm_get_fblocks(self.ctx, ptr.ctypes.data, slots.ctypes.data), "get_fblocks")
+        return [slots[ptr[k]:ptr[k + 1]].copy() for k in range(self.layout.nfblock)]
 
     # ---- device vectors
     def zeros(self):

@@ -204,8 +204,18 @@ int upload_all(gplmm_ctx* c) {
         }
         for (const Split& sp : c->splits) used += (int64_t)sp.ld * sp.nS;
         c->split_apply_elems = used;
-        c->split_row0 = c->subs[nsub].slot_off;
+        c->split_row0 = c->subs[c->nsub_main].slot_off;
         c->split_row1 = (int64_t)c->sub_slots.size();
+    }
+    // the blocks of A^f_f (mg_form 1, 2): after the duals, largest first
+    if (c->n_fsub > 0) {
+        std::vector<int32_t> fo;
+        for (int s = nsub; s < nsub + c->n_fsub; ++s) fo.push_back(s);
+        std::stable_sort(fo.begin(), fo.end(), [&](int a, int b) { return c->subs[a].nT > c->subs[b].nT; });
+        c->maxT_f = c->subs[fo[0]].nT;
+        GP_TRY(upload(c, &c->d_fsub_order, fo));
+        c->f_row0 = c->subs[nsub].slot_off;
+        c->f_row1 = nsub + c->n_fsub < nall ? c->subs[nsub + c->n_fsub].slot_off : (int64_t)c->sub_slots.size();
     }
     c->prim_factor_elems = nall > c->Np ? c->subs[c->Np].diag_off : c->factor_elems;
     c->prim_rows = nall > c->Np ? c->subs[c->Np].slot_off : (int64_t)c->sub_slots.size();
@@ -805,6 +815,9 @@ static int check_options(gplmm_ctx* c, const gplmm_options* opt, double rho, dou
     if (c->opt.build_matrix != GPLMM_BUILD_GEOMETRIC && c->opt.build_matrix != GPLMM_BUILD_JACOBIAN)
         return fail(c, GPLMM_E_ARG, "build_matrix must be GPLMM_BUILD_GEOMETRIC or GPLMM_BUILD_JACOBIAN");
     if (c->opt.split_tiles < -1) return fail(c, GPLMM_E_ARG, "split_tiles must be -1, 0 or positive");
+    if (c->opt.mg_form < 0 || c->opt.mg_form > 2) return fail(c, GPLMM_E_ARG, "mg_form must be 0, 1 or 2");
+    if (c->opt.mg_form != 0 && c->opt.split_tiles > 0)
+        return fail(c, GPLMM_E_ARG, "mg_form 1 and 2 do not combine with split_tiles");
     if (opt->nx <= 0 || opt->ny <= 0 || opt->nz <= 0) return fail(c, GPLMM_E_ARG, "image dimensions must be positive");
     if (opt->nx > 1024 || opt->ny > 1024 || opt->nz > 1024)
         return fail(c, GPLMM_E_ARG, "image dimensions must be <= 1024");
@@ -899,6 +912,7 @@ int gplmm_setup_batch(int nsamples, const uint8_t* const* masks, const int32_t* 
     gplmm_ctx* c = new gplmm_ctx();
     c->opt = *opt;
     *out = c;
+    if (opt->mg_form != 0) return fail(c, GPLMM_E_ARG, "mg_form 1 and 2 take a single image");
     c->stream = (hipStream_t)opt->stream;
     if (nsamples > kMaxSamples) return fail(c, GPLMM_E_ARG, "at most 1024 samples per batch");
     int rc0 = check_options(c, opt, rho[0], mu[0]);
@@ -984,6 +998,12 @@ int gplmm_layout_info(const gplmm_ctx* c, gplmm_layout* o) {
     o->lu_flops = c->lu_flops[0] + c->lu_flops[1] + c->lu_flops[2];
     o->nsplit = (int)c->splits.size();
     for (const Split& sp : c->splits) o->sep_unknowns += sp.nS;
+    o->nfblock = c->n_fsub;
+    for (int k = 0; k < c->n_fsub; ++k) {
+        const Sub& sb = c->subs[c->Np + c->Nc + k];
+        o->max_fblock = std::max(o->max_fblock, sb.n);
+        o->f_unknowns += sb.n;
+    }
     return GPLMM_OK;
 }
 
@@ -1025,6 +1045,20 @@ int gplmm_get_split(const gplmm_ctx* c, int k, int32_t* info, int32_t* slots) {
         std::copy(sa, sa + sp.nA, slots);
         std::copy(sb, sb + sp.nB, slots + sp.nA);
         std::copy(sa + sp.nA, sa + sp.nA + sp.nS, slots + sp.nA + sp.nB);
+    }
+    return GPLMM_OK;
+}
+
+int gplmm_get_fblocks(const gplmm_ctx* c, int64_t* ptr, int32_t* slots) {
+    if (!c || !ptr) return GPLMM_E_ARG;
+    ptr[0] = 0;
+    for (int k = 0; k < c->n_fsub; ++k) {
+        const Sub& sb = c->subs[c->Np + c->Nc + k];
+        ptr[k + 1] = ptr[k] + sb.n;
+        if (slots) {   // each block's local order is its slot order
+            const int32_t* sl = c->sub_slots.data() + sb.slot_off;
+            std::copy(sl, sl + sb.n, slots + ptr[k]);
+        }
     }
     return GPLMM_OK;
 }
@@ -1083,6 +1117,8 @@ int gplmm_set_coarse_model(gplmm_ctx* c, gplmm_mlp* model) {
     if (!c->ready) return gp::fail(c, GPLMM_E_STATE, "no device state (host-only context)");
     if (model && (gp::mlp_width_in(model) != gp::kCoarseFeatures || gp::mlp_width_out(model) != 1))
         return gp::fail(c, GPLMM_E_ARG, "the coarse model must map 16 features to one value");
+    if (model && c->opt.mg_form == 1)
+        return gp::fail(c, GPLMM_E_ARG, "the coarse model predicts Rhat X Phat, not the operator of mg_form 1");
     c->coarse_model = model;
     return GPLMM_OK;
 }
@@ -1536,7 +1572,7 @@ void gplmm_destroy(gplmm_ctx* c) {
     void* ptrs[] = {c->d_co_pinned, c->d_panel, c->d_gin, c->d_gout, c->d_cl_row, c->d_cl_col, c->d_cl_feat, c->d_cl_pred, c->d_cl_scale, c->d_nb6, c->d_xcoef, c->d_xcoef_f, c->d_tag, c->d_sub_slots, c->d_subs, c->d_tfc, c->d_tfr, c->d_lrow,
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_step_pairs[2], c->d_sub_list[2], c->d_splits, c->d_phase_order[0], c->d_phase_order[1],
-                    c->d_sep_ids, c->d_sinv_off, c->d_sinv_ncols, c->d_sinv,
+                    c->d_sep_ids, c->d_sinv_off, c->d_sinv_ncols, c->d_sinv, c->d_fsub_order,
                     c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_r, c->d_tmp,

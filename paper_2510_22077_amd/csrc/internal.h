@@ -135,7 +135,10 @@ struct gplmm_ctx {
     std::vector<int32_t> lu_sub_list[3];
     double lu_flops[3] = {0.0, 0.0, 0.0};   // flops of the tile products of each schedule (2 T^3 each)
     std::vector<gp::Split> splits;       // primaries solved by nested dissection
-    int nsub_main = 0;                   // Np + Nc: the subdomains before the split parts
+    int nsub_main = 0;                   // Np + Nc + Nf: the subdomains before the split parts
+    int n_fsub = 0, maxT_f = 0;          // mg_form 1: blocks of A^f_f (components of the f-faces)
+    int64_t f_row0 = 0, f_row1 = 0;      // their rows in the slot lists
+    int32_t* d_fsub_order = nullptr;     // their subdomain ids, largest first
     int64_t sinv_elems = 0;              // separators' inverses, all splits
     int64_t split_apply_elems = 0;       // factor and inverse elements one primary solve reads
     int max_sep_ld = 0;                  // largest padded separator
@@ -312,6 +315,8 @@ int mlp_width_in(const gplmm_mlp* m);
 int mlp_width_out(const gplmm_mlp* m);
 int coarse_features(gplmm_ctx* c, const double* wind_host, std::vector<float>& feat, std::vector<float>& scale);
 void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s);
+// y = Xcheck v: the primary and interface-cell rows of the column-summed build matrix (FP64)
+void launch_xcheck_v(gplmm_ctx* c, const double* v, double* y, hipStream_t s);
 
 // krylov.hip
 double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n);

@@ -1256,6 +1256,32 @@ void trsv_gather(gplmm_ctx* c, const int32_t* sub_ids_dev, int nsub, const T* vi
     timer_end(c, "trsv", bytes);
 }
 
+// Eq. xf: x_f = (A^f_f)^-1 r_f, one workgroup per diagonal block of A^f_f (the f-faces'
+// connected sets; blocks of a few tiles, so the dual-block kernel).
+template <typename T>
+void trsv_fblocks(gplmm_ctx* c, const T* vin, T* out_local) {
+    if (c->n_fsub <= 0) return;
+    Env e = make_env(c);
+    const int s0 = c->Np + c->Nc, s1 = s0 + c->n_fsub;
+    const int64_t e0 = c->subs[s0].diag_off;
+    const int64_t e1 = s1 < (int)c->subs.size() ? c->subs[s1].diag_off : c->factor_elems;
+    const double bytes = (double)sizeof(T) * (double)(e1 - e0) + (double)(c->f_row1 - c->f_row0) * (3.0 * sizeof(T) + 4.0);
+    timer_begin(c, "trsv");
+    timer_begin(c, "trsv_f");
+    const int mt = c->maxT_f;
+    const size_t meta = (size_t)16 * mt;
+    const size_t lds = meta + (size_t)mt * kT * sizeof(T);
+    const T* F = (const T*)c->d_factor;
+    if (lds <= kTrsvLdsMax)
+        trsv_small_kernel<T><<<c->n_fsub, 256, lds, c->stream>>>(e, F, c->d_fsub_order, c->d_sub_slots, vin, out_local,
+                                                                 c->d_local_off, mt);
+    else
+        trsv_sub_kernel<T, false><<<c->n_fsub, 1024, meta, c->stream>>>(e, F, c->d_fsub_order, c->d_sub_slots, vin,
+                                                                       out_local, c->d_local_off, 0, mt);
+    timer_end(c, "trsv_f", bytes);
+    timer_end(c, "trsv", bytes);
+}
+
 // The primaries' solves with split primaries: phase 1 (unsplit primaries whole, halves
 // forward), the separators, phase 2 (halves backward).  The halves' local vectors then
 // hold [x_A, x_S] and [x_B, x_S].
@@ -1333,6 +1359,8 @@ template int factor_set<float>(gplmm_ctx*, int);
 template int factor_set<double>(gplmm_ctx*, int);
 template void trsv_gather<float>(gplmm_ctx*, const int32_t*, int, const float*, float*);
 template void trsv_gather<double>(gplmm_ctx*, const int32_t*, int, const double*, double*);
+template void trsv_fblocks<float>(gplmm_ctx*, const float*, float*);
+template void trsv_fblocks<double>(gplmm_ctx*, const double*, double*);
 template void trsv_split<float>(gplmm_ctx*, const float*, float*);
 template void trsv_split<double>(gplmm_ctx*, const double*, double*);
 template int build_separators<float>(gplmm_ctx*);

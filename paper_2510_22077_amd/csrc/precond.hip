@@ -154,6 +154,17 @@ __global__ void scatter_split_kernel(const int32_t* __restrict__ slots, const in
     z[slots[t]] = loc[local_off[s] + r];
 }
 
+// z[slot] = local solution for the rows row0 .. row1 of the slot lists (disjoint blocks)
+template <typename T>
+__global__ void scatter_rows_kernel(const int32_t* __restrict__ slots, const int32_t* __restrict__ row_sub,
+                                    const Sub* __restrict__ subs, const int64_t* __restrict__ local_off,
+                                    const T* __restrict__ loc, T* __restrict__ z, int64_t row0, int64_t row1) {
+    const int64_t t = row0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= row1) return;
+    const int s = row_sub[t];
+    z[slots[t]] = loc[local_off[s] + (t - subs[s].slot_off)];
+}
+
 // zd[slot] = sum over the dual grids containing the slot, in a fixed order
 template <typename T>
 __global__ void gather_dual_kernel(const int64_t* __restrict__ ptr, const int64_t* __restrict__ src,
@@ -266,6 +277,8 @@ template <typename T>
 int factor_set(gplmm_ctx* c, int set);
 template <typename T>
 void trsv_split(gplmm_ctx* c, const T* vin, T* loc);
+template <typename T>
+void trsv_fblocks(gplmm_ctx* c, const T* vin, T* out_local);
 template <typename T>
 int build_separators(gplmm_ctx* c);
 
@@ -398,6 +411,7 @@ int build_precond(gplmm_ctx* c) {
     GP_HIP(c, hipMemsetAsync(F, 0, sizeof(T) * c->factor_elems, s));
     assemble_subs<T>(c, 0, c->Np, true);
     assemble_subs<T>(c, c->Np, c->Nc, false);
+    if (c->n_fsub > 0) assemble_subs<T>(c, c->Np + c->Nc, c->n_fsub, false);   // A^f_f (Eq. xf)
     factor_set<T>(c, 1);
     timer_end(c, "build_closure_dual_lu", c->lu_flops[1]);
     // 2. shape and correction vectors: Abar_i^-1 [g_i1 .. g_im, b_B]
@@ -447,7 +461,10 @@ int build_precond(gplmm_ctx* c) {
     }
     if (nco > 0) {
         timer_begin(c, "build_coarse");
-        probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_xv<double>(c, pv, xv, nullptr, s); });
+        if (c->opt.mg_form == 1)   // Eq. iMG: Rhat Xcheck Phat
+            probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_xcheck_v(c, pv, xv, s); });
+        else
+            probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_xv<double>(c, pv, xv, nullptr, s); });
         GP_HIP(c, hipGetLastError());
         GP_HIP(c, hipStreamSynchronize(s));
         c->last_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
@@ -489,6 +506,13 @@ int apply_precond(gplmm_ctx* c, const double* v, double* z) {
     }
     // r1 = v - X z_G ; z_d = M_d^-1 r1 (overlapping duals, deterministic gather-sum)
     launch_xv<T>(c, zG, r1, vin, s);
+    if (c->n_fsub > 0) {   // Eq. xf: z_G's f entries (zero so far) = (A^f_f)^-1 r1_f, then r1 again
+        trsv_fblocks<T>(c, r1, loc);
+        const int64_t nr = c->f_row1 - c->f_row0;
+        scatter_rows_kernel<T><<<nb(nr), kB, 0, s>>>(c->d_sub_slots, c->d_row_sub, c->d_subs, c->d_local_off, loc, zG,
+                                                     c->f_row0, c->f_row1);
+        launch_xv<T>(c, zG, r1, vin, s);
+    }
     if (c->Nc > 0) {
         trsv_gather<T>(c, c->d_sub_ids + c->Np, c->Nc, r1, loc);
         gather_dual_kernel<T><<<nb(N), kB, 0, s>>>(c->d_dinv_ptr, c->d_dinv, loc, zd, N);

@@ -752,6 +752,47 @@ int build_local_problems(gplmm_ctx* c) {
         for (size_t t = 0; t < u.size(); ++t) ordered[t] = keyed[t].second;
         add_sub(sb, ordered, false);
     }
+    // ---- Eq. xf (mg_form 1, 2): the f-faces' block A^f_f, one subdomain per connected
+    // component of the f-faces under X's couplings, unknowns in slot order
+    c->n_fsub = 0;
+    if (c->opt.mg_form != 0) {
+        std::vector<int64_t> fslots;
+        for (int64_t sl = 0; sl < c->N; ++sl)
+            if ((int)(sl % c->nrec) < c->ndim && c->owner[sl] == -1) fslots.push_back(sl);
+        const int64_t nf = (int64_t)fslots.size();
+        auto fidx = [&](int64_t sl) -> int64_t {
+            auto it = std::lower_bound(fslots.begin(), fslots.end(), sl);
+            return (it != fslots.end() && *it == sl) ? (int64_t)(it - fslots.begin()) : -1;
+        };
+        UF uf(nf);
+        for (int64_t k = 0; k < nf; ++k) {
+            row_pattern(c, fslots[k], cols);
+            for (int64_t cl : cols) {
+                const int64_t m = fidx(cl);
+                if (m >= 0) uf.unite(k, m);
+            }
+        }
+        std::vector<int64_t> comp_of(nf, -1);
+        std::vector<std::vector<int64_t>> comps;
+        for (int64_t k = 0; k < nf; ++k) {   // components numbered by their first slot
+            const int64_t r = uf.find(k);
+            if (comp_of[r] < 0) {
+                comp_of[r] = (int64_t)comps.size();
+                comps.emplace_back();
+            }
+            comps[comp_of[r]].push_back(fslots[k]);
+        }
+        for (size_t k = 0; k < comps.size(); ++k) {
+            Sub sb{};
+            sb.kind = 4;
+            sb.id = (int)k;
+            sb.split = -1;
+            add_sub(sb, comps[k], false);
+            c->subs.push_back(sb);
+        }
+        c->n_fsub = (int)comps.size();
+        c->nsub_main = nsub + c->n_fsub;
+    }
     // ---- nested dissection of the primaries whose blocks span more than split_tiles tiles
     // (single images; the split parts follow the duals)
     const int thr = c->opt.split_tiles;   // 0 (default) and -1: never
@@ -819,7 +860,7 @@ int build_local_problems(gplmm_ctx* c) {
         for (int s = 0; s < (int)c->subs.size(); ++s) {
             const Sub& sb = c->subs[s];
             const bool in = set == 0 ? ((sb.kind == 0 && sb.split < 0) || sb.kind == 2)
-                                     : (set == 1 ? s < nsub : sb.kind == 3);
+                                     : (set == 1 ? s < c->nsub_main : sb.kind == 3);
             if (in) members.push_back(s);
         }
         auto& off = c->lu_step_off[set];

@@ -190,6 +190,81 @@ __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restric
     y[s] = a ? (T)(a[s] - m) : m;
 }
 
+// y = Xcheck b, the rows of Eq. iMG's column-summed operator that the restriction Rhat
+// reads (Section 3.2.2): a row of a primary's unknown keeps its columns in that primary
+// and on interface cells, an interface cell's mass row keeps every column but the
+// f-faces; each dropped column's coefficient is added to the row's diagonal (both
+// reduction steps), except on faces of wall-free groups, which drop it.  Every other row
+// (f-faces, inactive faces) is zero.  cls: per slot, owner primary, -1 f-face, -4
+// interface cell; keep: per slot, 1 = no diagonal sums.
+template <int ND, bool kJac>
+__global__ void __launch_bounds__(kBlock) xcheck_kernel(DevGeo g, const double* __restrict__ coef,
+                                                        const int32_t* __restrict__ cls,
+                                                        const uint8_t* __restrict__ keep,
+                                                        const double* __restrict__ b, double* __restrict__ y) {
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    constexpr int nr = ND + 1;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const int64_t nce = g.ncell;
+    const double ih = 1.0 / g.h;
+#pragma unroll
+    for (int ax = 0; ax <= ND; ++ax) {
+        const int64_t s = nr * c + ax;
+        const int32_t rc = cls[s];
+        const bool prow = rc >= 0, crow = rc == -4;
+        double acc = 0.0, dsum = 0.0;
+        auto add = [&](int64_t col, double w) {
+            const int32_t cc = cls[col];
+            const bool kept = prow ? (cc == rc || cc == -4) : cc != -1;
+            if (kept) acc += w * b[col];
+            else dsum += w;
+        };
+        if (!(prow || crow)) {
+            y[s] = 0.0;
+            continue;
+        }
+        if (ax < ND) {
+            const int32_t L = nc.n[ax][0];
+            if (L >= 0) {
+                acc = coef[ax * nce + c] * b[s];
+                add(nr * c + ND, ih);
+                add((int64_t)nr * L + ND, -ih);
+#pragma unroll
+                for (int d = 0; d < ND; ++d)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const double w = coef[((1 + 2 * d + t) * ND + ax) * nce + c];
+                        const int32_t P = nc.n[d][t];
+                        if (w != 0.0 && P >= 0) add((int64_t)nr * P + ax, w);
+                    }
+                if (kJac) {
+                    const Nb<ND> nl = load_nb<ND>(g, L);
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) {
+                        if (d == ax) continue;
+                        const int dd = d < ax ? d : d - 1;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const double w = coef[((1 + 2 * ND + 4 * dd + q) * ND + ax) * nce + c];
+                            if (w != 0.0) add((int64_t)nr * jac_col_cell<ND>(nc, nl, c, L, d, q) + d, w);
+                        }
+                    }
+                }
+            }
+        } else if ((g.tag[c] & kPinBit)) {
+            acc = b[s];
+        } else {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                if (nc.n[d][0] >= 0) add(nr * c + d, ih);
+                if (nc.n[d][1] >= 0) add((int64_t)nr * nc.n[d][1] + d, -ih);
+            }
+        }
+        y[s] = keep[s] ? acc : acc + dsum * b[s];
+    }
+}
+
 // b_B = -r(u = 0, p = 0) of the steady equations: rho * body on every active face.
 template <int ND>
 __global__ void bB_kernel(DevGeo g, Phys ph0, double* __restrict__ out) {
@@ -263,6 +338,20 @@ void launch_xv(gplmm_ctx* c, const T* v, T* y, const T* sub_from, hipStream_t s)
     } else {
         if (jac) xv_kernel<2, T, true><<<gr, b, 0, s>>>(c->geo, cf, sub_from, v, y);
         else xv_kernel<2, T, false><<<gr, b, 0, s>>>(c->geo, cf, sub_from, v, y);
+    }
+}
+
+void launch_xcheck_v(gplmm_ctx* c, const double* v, double* y, hipStream_t s) {
+    const dim3 gr = grid_for(c->ncell, c->stencil_block);
+    const int b = c->stencil_block;
+    const bool jac = c->opt.build_matrix == GPLMM_BUILD_JACOBIAN;
+    const double* cf = c->d_xcoef;
+    if (c->ndim == 3) {
+        if (jac) xcheck_kernel<3, true><<<gr, b, 0, s>>>(c->geo, cf, c->d_slot_class, c->d_noclose, v, y);
+        else xcheck_kernel<3, false><<<gr, b, 0, s>>>(c->geo, cf, c->d_slot_class, c->d_noclose, v, y);
+    } else {
+        if (jac) xcheck_kernel<2, true><<<gr, b, 0, s>>>(c->geo, cf, c->d_slot_class, c->d_noclose, v, y);
+        else xcheck_kernel<2, false><<<gr, b, 0, s>>>(c->geo, cf, c->d_slot_class, c->d_noclose, v, y);
     }
 }
 

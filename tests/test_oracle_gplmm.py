@@ -53,14 +53,14 @@ def _tiny_3d(seed=1):
     return m, lab
 
 
-@pytest.mark.parametrize("mg_form", [0, 1])
+@pytest.mark.parametrize("mg_form", [0, 1, 2])
 @pytest.mark.parametrize("maker,wind_seed,dt", [(_tiny_2d, None, None), (_tiny_2d, 5, None),
                                                 (_tiny_3d, None, None), (_tiny_3d, 7, 0.5)])
 def test_sparse_gplmm_matches_literal_matrices(maker, wind_seed, dt, mg_form):
     m, lab = maker()
     g, ops, dc, ph, X, bB = _case(m, lab, body=(1.0, 0.2, 0.1), wind_seed=wind_seed, dt=dt)
     assert dc.Np >= 2 and dc.Nc >= 1
-    if mg_form == 1:
+    if mg_form >= 1:
         assert dc.f_faces.size >= 1      # the back-substitution of Eq. xf has work to do
     M = G.build(X, dc, bB, mg_form=mg_form)
     Mlit, MGlit = literal_preconditioner(X.toarray(), dc, bB, mg_form=mg_form)
@@ -91,7 +91,7 @@ def test_single_pore_preconditioner_is_exact_inverse():
 @pytest.mark.parametrize("dims,per", [((1, 8, 24), (True, False, False)),
                                       ((6, 8, 24), (True, False, False)),
                                       ((6, 8, 24), (True, False, True))])
-@pytest.mark.parametrize("mg_form", [0, 1])
+@pytest.mark.parametrize("mg_form", [0, 1, 2])
 def test_slab_channel_coarse_solve_is_poiseuille(dims, per, mg_form):
     nz, ny, nx = dims
     m = channel(nx, ny, nz)
@@ -303,6 +303,26 @@ def test_aplmm_ns_from_the_newton_jacobian_converges():
     print("FGMRES its gPLMM %s, aPLMM_NS %s" % (sg.lin_its, sa.lin_its))
 
 
+def test_remark1_form_with_back_substitution():
+    """mg_form 2: the Remark-1 coarse correction with the f entries from Eq. xf.  On the
+    p and c unknowns it is the Remark-1 correction itself; on the f rows A z_G equals the
+    right-hand side; and it differs from the Remark-1 correction (which leaves x^f = 0)."""
+    m, lab = _tiny_3d()
+    g, ops, dc, ph, X, bB = _case(m, lab, wind_seed=3)
+    M0 = G.build(X, dc, bB, mg_form=0)
+    M2 = G.build(X, dc, bB, mg_form=2)
+    F = dc.f_faces
+    assert F.size >= 1
+    notf = np.setdiff1d(np.arange(g.N), F)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal(g.N)
+    z0, z2 = G.apply_MG(M0, w), G.apply_MG(M2, w)
+    assert np.array_equal(z0[notf], z2[notf])
+    assert np.all(z0[F] == 0.0)
+    assert np.linalg.norm(z2[F]) >= 1e-3 * np.linalg.norm(z2)
+    assert np.linalg.norm((X @ z2 - w)[F]) <= 1e-11 * np.linalg.norm(w)
+
+
 def test_column_summed_form_newton_converges_to_the_same_solution():
     """Newton-FGMRES with the Eq. iMG coarse correction ends at the solution the
     Remark-1 form reaches (the preconditioner changes the iterations, not the answer)."""
@@ -314,6 +334,7 @@ def test_column_summed_form_newton_converges_to_the_same_solution():
     dc = decompose(g, w["labels"])
     ph = Phys(w["rho"], w["mu"], tuple(w["body"]), None, dc.pin)
     x0, s0 = newton.solve(ops, dc, ph, tol=1e-11)
-    x1, s1 = newton.solve(ops, dc, ph, tol=1e-11, mg_form=1)
-    assert s0.res_hist[-1] <= 1e-11 and s1.res_hist[-1] <= 1e-11
-    assert np.linalg.norm(x1 - x0) <= 1e-8 * np.linalg.norm(x0)
+    for mg_form in (1, 2):
+        x1, s1 = newton.solve(ops, dc, ph, tol=1e-11, mg_form=mg_form)
+        assert s0.res_hist[-1] <= 1e-11 and s1.res_hist[-1] <= 1e-11
+        assert np.linalg.norm(x1 - x0) <= 1e-8 * np.linalg.norm(x0)
