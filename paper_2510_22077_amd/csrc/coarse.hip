@@ -23,6 +23,7 @@ constexpr int kPT = 1024;      // panel workgroup
 constexpr int kS = 8;          // sub-panel width inside a panel
 constexpr int kBig = 128;      // columns (rows) per rank-kBig trailing update
 constexpr int kGT = 64;        // update tile (kGT x kGT outputs, 256 threads, 4 x 4 each)
+constexpr int kTr = 4;         // 32 x 32 blocks per pass of the register panel's transposes
 
 // Factor columns [k0, k0 + w) of rows [k0, n) (row-major A, leading dimension n) through
 // a column-major copy P (w columns of length n, so that every pass over the panel is a
@@ -175,6 +176,264 @@ __global__ void __launch_bounds__(kPT) panel_kernel(double* __restrict__ A, int 
     }
 }
 
+// The factorisation of panel_kernel with each S-column sub-panel held in registers
+// (S = kS: the same pivots and operations in the same order, so the same bits; S < kS
+// where R kS values would not fit): thread t owns rows k0 + t + kPT q (q < R, so
+// n - k0 <= R kPT) and reads them from the row-major matrix itself (each thread's S
+// values of a row are contiguous; no column-major copy).  A pivot step touches no memory but the
+// block's candidates and the two interchanged rows, which pass through LDS (two
+// barriers); the sub-panel's interchanges reach the panel's other columns in one
+// permutation of the few rows involved at its end.
+template <int R, int S>
+__global__ void __launch_bounds__(kPT) panel_reg_kernel(double* __restrict__ A, int n, int k0, int w,
+                                                        int32_t* __restrict__ piv, int* __restrict__ flag,
+                                                        double* __restrict__ P) {
+    __shared__ double bv[kPT / 64];
+    __shared__ int bi[kPT / 64];
+    __shared__ double rowA[S], rowB[S];
+    __shared__ int pvs[S];
+    __shared__ int arow[2 * S], asrc[2 * S];
+    __shared__ int na_s;
+    __shared__ double xbuf[2 * S][kNB];
+    __shared__ double tile[kTr][kNB][kNB + 1];
+    __shared__ double Ub[S][kNB];
+    __shared__ double Lb[S][S];
+    constexpr int kC = R <= 3 ? 4 : 2;   // columns per pass of the rank update
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ty = tid >> 5, tx = tid & 31;
+    // the panel into the column-major copy, kTr 32 x 32 blocks per pass through LDS
+    for (int rb = k0; rb < n; rb += kTr * kNB) {
+#pragma unroll
+        for (int u = 0; u < kTr; ++u) {
+            const int r = rb + u * kNB + ty;
+            tile[u][ty][tx] = (r < n && tx < w) ? A[(int64_t)r * n + k0 + tx] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTr; ++u) {
+            const int rr = rb + u * kNB + tx;
+            if (rr < n && ty < w) P[(int64_t)ty * n + rr] = tile[u][tx][ty];
+        }
+        __syncthreads();
+    }
+    for (int sb = 0; sb < w; sb += S) {
+        const int se = min(sb + S, w);
+        double v[R][S];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = k0 + tid + kPT * q;
+#pragma unroll
+            for (int t = 0; t < S; ++t) v[q][t] = (r < n && sb + t < se) ? P[(int64_t)(sb + t) * n + r] : 0.0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < S; ++jj) {
+            if (sb + jj >= se) break;
+            const int col = k0 + sb + jj;
+            double best = -1.0;
+            int bidx = n;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {   // own rows in increasing order: ties keep the lower
+                const int r = k0 + tid + kPT * q;
+                if (r >= col && r < n) {
+                    const double a = fabs(v[q][jj]);
+                    if (a > best) {
+                        best = a;
+                        bidx = r;
+                    }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_down(best, off, 64);
+                const int oi = __shfl_down(bidx, off, 64);
+                if (ov > best || (ov == best && oi < bidx)) {
+                    best = ov;
+                    bidx = oi;
+                }
+            }
+            if (lane == 0) {
+                bv[wv] = best;
+                bi[wv] = bidx;
+            }
+            __syncthreads();
+            double b = bv[0];
+            int p = bi[0];
+            for (int u = 1; u < kPT / 64; ++u)
+                if (bv[u] > b || (bv[u] == b && bi[u] < p)) {
+                    b = bv[u];
+                    p = bi[u];
+                }
+            const bool bad = !(b > 0.0) || !isfinite(b) || p >= n;
+            if (bad) p = col;
+            if (tid == 0) {
+                if (bad) atomicOr(flag, 2);
+                piv[col] = p;
+                pvs[jj] = p;
+            }
+            // interchange rows col and p of the sub-panel through LDS; rowB is the pivot row
+            const int oc = col - k0, op = p - k0;
+            if (tid == oc % kPT) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (q == oc / kPT)
+#pragma unroll
+                        for (int t = 0; t < S; ++t) rowA[t] = v[q][t];
+            }
+            if (tid == op % kPT) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (q == op / kPT)
+#pragma unroll
+                        for (int t = 0; t < S; ++t) rowB[t] = v[q][t];
+            }
+            __syncthreads();
+            if (p != col) {
+                if (tid == oc % kPT) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        if (q == oc / kPT)
+#pragma unroll
+                            for (int t = 0; t < S; ++t) v[q][t] = rowB[t];
+                }
+                if (tid == op % kPT) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        if (q == op / kPT)
+#pragma unroll
+                            for (int t = 0; t < S; ++t) v[q][t] = rowA[t];
+                }
+            }
+            const double d = rowB[jj];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = k0 + tid + kPT * q;
+                if (r > col && r < n) {
+                    const double l = v[q][jj] / d;
+                    v[q][jj] = l;
+#pragma unroll
+                    for (int t = jj + 1; t < S; ++t)
+                        if (sb + t < se) v[q][t] -= l * rowB[t];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = k0 + tid + kPT * q;
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                if (r < n && sb + t < se) P[(int64_t)(sb + t) * n + r] = v[q][t];
+        }
+        // the multipliers of the sub-panel's own rows k0 + sb + i (thread sb + i, first slot)
+        if (tid >= sb && tid < se) {
+#pragma unroll
+            for (int t = 0; t < S; ++t) Lb[tid - sb][t] = v[0][t];
+        }
+        // the sub-panel's interchanges, in order, on the panel's other columns: the rows they
+        // touch and the row each one's final value comes from
+        if (tid == 0) {
+            int na = 0;
+            for (int jj = 0; jj < se - sb; ++jj) {
+                const int r1 = k0 + sb + jj, r2 = pvs[jj];
+                int a1 = -1, a2 = -1;
+                for (int a = 0; a < na; ++a) {
+                    if (arow[a] == r1) a1 = a;
+                    if (arow[a] == r2) a2 = a;
+                }
+                if (a1 < 0) {
+                    arow[na] = r1;
+                    asrc[na] = r1;
+                    a1 = na++;
+                }
+                if (a2 < 0) {
+                    arow[na] = r2;
+                    asrc[na] = r2;
+                    a2 = na++;
+                }
+                const int tsrc = asrc[a1];
+                asrc[a1] = asrc[a2];
+                asrc[a2] = tsrc;
+            }
+            na_s = na;
+        }
+        __syncthreads();
+        const int na = na_s;
+        for (int x = tid; x < na * w; x += kPT) {
+            const int a = x / w, cc = x % w;
+            if (cc < sb || cc >= se) xbuf[a][cc] = P[(int64_t)cc * n + asrc[a]];
+        }
+        __syncthreads();
+        for (int x = tid; x < na * w; x += kPT) {
+            const int a = x / w, cc = x % w;
+            if (cc < sb || cc >= se) P[(int64_t)cc * n + arow[a]] = xbuf[a][cc];
+        }
+        __syncthreads();
+        if (se < w) {
+            // U block: rows k0 + [sb, se) of columns [se, w) (unit-lower forward substitution,
+            // the column's entries loaded together)
+            if (tid < w - se) {
+                const int c = se + tid;
+                double u[S];
+#pragma unroll
+                for (int i = 0; i < S; ++i) u[i] = sb + i < se ? P[(int64_t)c * n + k0 + sb + i] : 0.0;
+#pragma unroll
+                for (int i = 0; i < S; ++i) {
+                    if (sb + i >= se) break;
+                    double x = u[i];
+#pragma unroll
+                    for (int t = 0; t < i; ++t) x -= Lb[i][t] * u[t];
+                    u[i] = x;
+                    P[(int64_t)c * n + k0 + sb + i] = x;
+                    Ub[i][c] = x;
+                }
+            }
+            __syncthreads();
+            // rank-(se - sb) update of the rows below in columns [se, w), kC columns per pass,
+            // every held row's loads of a pass in flight together; the multipliers are the
+            // held values of the sub-panel
+            const int ks = se - sb;
+            for (int c0 = se; c0 < w; c0 += kC) {
+                double x[R][kC];
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const int r = k0 + tid + kPT * q;
+#pragma unroll
+                    for (int u = 0; u < kC; ++u)
+                        x[q][u] = (r >= k0 + se && r < n && c0 + u < w) ? P[(int64_t)(c0 + u) * n + r] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const int r = k0 + tid + kPT * q;
+                    if (r < k0 + se || r >= n) continue;
+#pragma unroll
+                    for (int u = 0; u < kC; ++u)
+                        if (c0 + u < w) {
+                            double acc = x[q][u];
+#pragma unroll
+                            for (int t = 0; t < S; ++t)
+                                if (t < ks) acc -= v[q][t] * Ub[t][c0 + u];
+                            P[(int64_t)(c0 + u) * n + r] = acc;
+                        }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    for (int rb = k0; rb < n; rb += kTr * kNB) {
+#pragma unroll
+        for (int u = 0; u < kTr; ++u) {
+            const int rr = rb + u * kNB + tx;
+            tile[u][tx][ty] = (rr < n && ty < w) ? P[(int64_t)ty * n + rr] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTr; ++u) {
+            const int r = rb + u * kNB + ty;
+            if (r < n && tx < w) A[(int64_t)r * n + k0 + tx] = tile[u][ty][tx];
+        }
+        __syncthreads();
+    }
+}
+
 // Apply the interchanges of rows k0 .. k0 + w - 1 (in order) to every column outside
 // [k0, k0 + w), one thread per column.
 __global__ void swap_kernel(double* __restrict__ A, int n, int k0, int w, const int32_t* __restrict__ piv) {
@@ -320,7 +579,15 @@ static void invert_block(gplmm_ctx* c, double* A, double* X, int n) {
         const int K1 = std::min(K0 + kBig, n);
         for (int k0 = K0; k0 < K1; k0 += kNB) {
             const int w = std::min(kNB, K1 - k0);
-            panel_kernel<<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel);
+            switch ((n - k0 + kPT - 1) / kPT) {   // rows per thread of the register-held variant
+                case 1: panel_reg_kernel<1, kS><<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel); break;
+                case 2: panel_reg_kernel<2, kS><<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel); break;
+                case 3: panel_reg_kernel<3, kS><<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel); break;
+                case 4: panel_reg_kernel<4, 4><<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel); break;
+                case 5: panel_reg_kernel<5, 4><<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel); break;
+                case 6: panel_reg_kernel<6, 4><<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel); break;
+                default: panel_kernel<<<1, kPT, 0, s>>>(A, n, k0, w, c->d_piv, c->d_flag, c->d_panel);
+            }
             swap_kernel<<<blocks(n, 256), 256, 0, s>>>(A, n, k0, w, c->d_piv);
             const int r = k0 + w;
             if (r < K1) {
