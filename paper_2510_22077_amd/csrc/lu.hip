@@ -184,6 +184,7 @@ __global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, 
                                                       int K, int* __restrict__ flag, double* __restrict__ inv64) {
     __shared__ double A[kT][kT + 1];
     __shared__ double X[kT][kT + 1];
+    __shared__ double W[kT][kT + 1];
     const int sub = list[blockIdx.x];
     const Sub sb = e.subs[sub];
     const int tid = threadIdx.x;
@@ -192,11 +193,15 @@ __global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, 
     __syncthreads();
     // one barrier per elimination step: every thread forms the multipliers of its own
     // rows (the same division), and the multipliers are kept in X until the end, since
-    // column k of A is still read during step k
+    // column k of A is still read during step k.  The block is 256 threads: each takes
+    // its four entries of a step together
+    static_assert(kTT % 256 == 0, "four entries per thread");
     for (int k = 0; k < kT; ++k) {
         const double piv = A[k][k];
         if (tid == 0 && (!(piv == piv) || piv == 0.0 || fabs(piv) > 1e300)) atomicOr(flag, 1);
-        for (int x = tid; x < kTT; x += blockDim.x) {
+#pragma unroll
+        for (int u = 0; u < kTT / 256; ++u) {
+            const int x = tid + 256 * u;
             const int i = x / kT, j = x % kT;
             if (i > k && j >= k) {
                 const double l = A[i][k] / piv;
@@ -206,36 +211,50 @@ __global__ void __launch_bounds__(256) lu_diag_kernel(Env e, T* __restrict__ F, 
         }
         __syncthreads();
     }
-    for (int x = tid; x < kTT; x += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < kTT / 256; ++u) {
+        const int x = tid + 256 * u;
         const int i = x / kT, j = x % kT;
         if (i > j) A[i][j] = X[i][j];
     }
     __syncthreads();
-    // packed inverses by substitution, one column per thread (c: inv(L) e_c below the
-    // diagonal, 32 + c: inv(U) e_c on and above it), in column (axpy) form on the column's
-    // own entries of X, so that nothing is held in registers: at step k entry k is final
-    // and is subtracted, times column k of the factor, from the entries still open
-    if (tid < 2 * kT) {
-        const int c = tid & 31;
-        if (tid < kT) {
-            for (int i = c + 1; i < kT; ++i) X[i][c] = 0.0;
-            for (int k = c; k < kT - 1; ++k) {
-                const double xk = k == c ? 1.0 : X[k][c];
-                for (int i = k + 1; i < kT; ++i) X[i][c] -= A[i][k] * xk;
-            }
-        } else {
-            for (int i = 0; i <= c; ++i) X[i][c] = i == c ? 1.0 : 0.0;
-            for (int k = c; k >= 0; --k) {
-                const double xk = X[k][c] / A[k][k];
-                X[k][c] = xk;
-                for (int i = 0; i < k; ++i) X[i][c] -= A[i][k] * xk;
-            }
-        }
+#pragma unroll
+    for (int u = 0; u < kTT / 256; ++u) {
+        const int x = tid + 256 * u;
+        X[x / kT][x % kT] = x / kT == x % kT ? 1.0 : 0.0;
     }
     __syncthreads();
+    // packed inverses by substitution in column (axpy) form, both in the same 32 steps,
+    // every entry of a step on its own thread: step s is step k = s of inv(L) (entries
+    // (i > k, c <= k) of X lose L_ik X_kc, X_kk = 1 implied) and step k = 31 - s of inv(U)
+    // (row k of inv(U) is X_k. / U_kk, written to W, and entries (i < k, c >= k) lose
+    // U_ik times it).  Each entry sees its updates in the same order as a column-by-column
+    // substitution, so the values are those of one.
+    for (int st = 0; st < kT; ++st) {
+        const int kl = st, ku = kT - 1 - st;
+        const int nl = (kT - 1 - kl) * (kl + 1);   // inv(L) entries of this step
+        const int nu = (ku + 1) * (kT - ku);       // inv(U) row ku and the rows above it
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int t = tid + 256 * u;
+            if (t < nl) {
+                const int i = kl + 1 + t / (kl + 1), c = t % (kl + 1);
+                X[i][c] -= A[i][kl] * (c == kl ? 1.0 : X[kl][c]);
+            } else if (t < nl + nu) {
+                const int t2 = t - nl;
+                const int i = t2 / (kT - ku), c = ku + t2 % (kT - ku);
+                const double xk = X[ku][c] / A[ku][ku];
+                if (i == ku) W[ku][c] = xk;
+                else X[i][c] -= A[i][ku] * xk;
+            }
+        }
+        __syncthreads();
+    }
     for (int x = tid; x < kTT; x += blockDim.x) {
-        dp[x] = (T)X[x / kT][x % kT];
-        inv64[(int64_t)sub * kTT + x] = X[x / kT][x % kT];   // FP64 copy for the L panel of this step
+        const int i = x / kT, j = x % kT;
+        const double pv = i > j ? X[i][j] : W[i][j];
+        dp[x] = (T)pv;
+        inv64[(int64_t)sub * kTT + x] = pv;   // FP64 copy for the L panel of this step
     }
     const int32_t* tfr = e.tfr + sb.env_off;
     int J1 = K + 1;
