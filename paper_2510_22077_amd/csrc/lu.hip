@@ -421,13 +421,33 @@ __global__ void __launch_bounds__(256) trsv_kernel(Env e, const T* __restrict__ 
     const int r = tid >> 3, q = tid & 7;      // row within a tile, 4-column chunk
     // forward: L y = b (unit lower), L stored by tile rows
     for (int I = 0; I < sb.nT; ++I) {
-        T acc = 0;
-        for (int J = tfc[I]; J < I; ++J) {
+        // four tiles per pass with separate sums, so that their loads are in flight together
+        T acc4[4] = {0, 0, 0, 0};
+        int J = tfc[I];
+        for (; J + 4 <= I; J += 4) {
+            T lv[4][4], yv[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const T* lt = tile_ptr(const_cast<T*>(F), e, sb, I, J + u);
+                const T* yj = x + (J + u) * kT;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    lv[u][m] = lt[r * kT + q * 4 + m];
+                    yv[u][m] = yj[q * 4 + m];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) acc4[u] += lv[u][m] * yv[u][m];
+        }
+        for (; J < I; ++J) {
             const T* lt = tile_ptr(const_cast<T*>(F), e, sb, I, J);
             const T* yj = x + J * kT;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) acc += lt[r * kT + q * 4 + m] * yj[q * 4 + m];
+            for (int m = 0; m < 4; ++m) acc4[0] += lt[r * kT + q * 4 + m] * yj[q * 4 + m];
         }
+        T acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
         acc = wave_sum8(acc);
         if (q == 0) {
             int gr = I * kT + r;
@@ -465,7 +485,25 @@ __global__ void __launch_bounds__(256) trsv_kernel(Env e, const T* __restrict__ 
         }
         __syncthreads();
         if (tid < kT) x[J * kT + tid] = yt[tid];
-        for (int I = tfr[J]; I < J; ++I) {
+        int I = tfr[J];
+        for (; I + 4 <= J; I += 4) {   // four tiles per pass, loads in flight together
+            T uv[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const T* ut = tile_ptr(const_cast<T*>(F), e, sb, I + u, J);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) uv[u][m] = ut[r * kT + q * 4 + m];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                T acc = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) acc += uv[u][m] * yt[q * 4 + m];
+                acc = wave_sum8(acc);
+                if (q == 0) x[(I + u) * kT + r] -= acc;
+            }
+        }
+        for (; I < J; ++I) {
             const T* ut = tile_ptr(const_cast<T*>(F), e, sb, I, J);
             T acc = 0;
 #pragma unroll
