@@ -220,7 +220,9 @@ def _batch(args):
     from synth import make_batch
     from paper_2510_22077_amd import BatchSolver
     t0 = time.perf_counter()
-    ws = make_batch(args.batch, args.seed)
+    ws = make_batch(args.batch, args.seed, progress=lambda k, w: print(
+        "sample %d: %s, Re target %.2f" % (k, "x".join(str(v) for v in w["mask"].shape), w["re_target"]),
+        file=sys.stderr, flush=True))
     tg = time.perf_counter() - t0
     print("batch of %d generated in %.1f s" % (len(ws), tg), file=sys.stderr, flush=True)
     t0 = time.perf_counter()

@@ -271,6 +271,19 @@ int upload_all(gplmm_ctx* c) {
     GP_TRY(upload(c, &c->d_phi_ncols, phi_ncols));
     GP_TRY(upload(c, &c->d_phi_cols, c->phi_cols));
     GP_TRY(upload(c, &c->d_phi_cols_off, c->phi_cols_off));
+    {   // prolongation workgroups: each primary's rows in chunks of 256
+        std::vector<int32_t> pb;
+        c->max_pcols = 0;
+        for (int i = 0; i < c->Np; ++i) {
+            for (int ch = 0; ch * 256 < c->subs[i].n; ++ch) {
+                pb.push_back(i);
+                pb.push_back(ch);
+            }
+            c->max_pcols = std::max(c->max_pcols, (int)(c->phi_cols_off[i + 1] - c->phi_cols_off[i]));
+        }
+        c->n_prolong_blk = (int)(pb.size() / 2);
+        GP_TRY(upload(c, &c->d_prolong_blk, pb));
+    }
     // row groups of Rhat: interfaces (their cells' pressures), then corrections (every slot of S_i)
     std::vector<int64_t> gptr(1, 0);
     std::vector<int32_t> gslot;
@@ -1573,7 +1586,7 @@ void gplmm_destroy(gplmm_ctx* c) {
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_step_pairs[2], c->d_sub_list[2], c->d_splits, c->d_phase_order[0], c->d_phase_order[1],
                     c->d_sep_ids, c->d_sinv_off, c->d_sinv_ncols, c->d_sinv, c->d_fsub_order,
-                    c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off,
+                    c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off, c->d_prolong_blk,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_r, c->d_tmp,
                     c->d_dx, c->d_zero, c->d_V, c->d_Z, c->d_red, c->d_pv, c->d_local, c->d_cv, c->d_row_sub,

@@ -205,6 +205,8 @@ struct gplmm_ctx {
     int32_t* d_phi_ncols = nullptr;
     int32_t* d_phi_cols = nullptr;
     int64_t* d_phi_cols_off = nullptr;
+    int32_t* d_prolong_blk = nullptr;    // prolongation workgroups: (primary, 256-row chunk) pairs
+    int n_prolong_blk = 0, max_pcols = 0;
     int64_t* d_grp_ptr = nullptr;        // Rhat row groups: interfaces, then corrections
     int32_t* d_grp_slot = nullptr;
     int64_t* d_dinv_ptr = nullptr;       // per slot: local rows of the dual grids holding it

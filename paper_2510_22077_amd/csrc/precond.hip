@@ -43,47 +43,63 @@ __global__ void restrict_kernel(const V* __restrict__ v, const int64_t* __restri
     __shared__ double sh[16];
     const int g = blockIdx.x;
     double acc = 0.0;
-    for (int64_t t = gptr[g] + threadIdx.x; t < gptr[g + 1]; t += blockDim.x) acc += (double)v[gslot[t]];
+    const int64_t e = gptr[g + 1];
+    int64_t t = gptr[g] + threadIdx.x;
+    // four entries per pass, their index and value loads in flight together
+    for (; t + 3 * (int64_t)blockDim.x < e; t += 4 * (int64_t)blockDim.x) {
+        int32_t q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = gslot[t + u * (int64_t)blockDim.x];
+        double w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = (double)v[q[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += w[u];
+    }
+    for (; t < e; t += blockDim.x) acc += (double)v[gslot[t]];
     double s = block_sum(acc, sh);
     if (threadIdx.x == 0) out[g] = s;
 }
 
-// z on the primaries' slots: sum_k phi_k coef[col_k]; one thread per primary row
-// (flat over all primaries, so large pores do not serialise the launch).
+// z on the primaries' slots: sum_k phi_k coef[col_k] over the primary's shape and
+// correction vectors, one workgroup per 256-row chunk of one primary (blk: (primary,
+// chunk) pairs): the primary's column indices and coefficients are read once per
+// workgroup into LDS, and each thread issues its row's shape-vector loads eight at a
+// time; the sum keeps the column order and skips zero coefficients.
 template <typename T, typename O>
-__global__ void prolong_prim_kernel(const T* __restrict__ phi, const int64_t* __restrict__ phi_off,
-                                    const int64_t* __restrict__ pcol_off, const int32_t* __restrict__ pcols,
-                                    const Sub* __restrict__ subs, const int32_t* __restrict__ row_sub,
-                                    const int32_t* __restrict__ slots, const double* __restrict__ coef,
-                                    O* __restrict__ z, int64_t nrows, int kT) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nrows) return;
-    const int i = row_sub[t];
+__global__ void __launch_bounds__(256) prolong_blk_kernel(const T* __restrict__ phi, const int64_t* __restrict__ phi_off,
+                                                          const int64_t* __restrict__ pcol_off,
+                                                          const int32_t* __restrict__ pcols,
+                                                          const Sub* __restrict__ subs, const int32_t* __restrict__ blk,
+                                                          const int32_t* __restrict__ slots,
+                                                          const double* __restrict__ coef, O* __restrict__ z, int kT) {
+    extern __shared__ double acoef[];
+    const int i = blk[2 * blockIdx.x], chunk = blk[2 * blockIdx.x + 1];
     const Sub sb = subs[i];
-    const int r = (int)(t - sb.slot_off);
+    const int64_t c0 = pcol_off[i];
+    const int nc = (int)(pcol_off[i + 1] - c0);
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+        const int32_t cl = pcols[c0 + k];
+        acoef[k] = cl >= 0 ? coef[cl] : 0.0;
+    }
+    __syncthreads();
+    const int r = chunk * 256 + (int)threadIdx.x;
+    if (r >= sb.n) return;
     const int64_t ld = (int64_t)sb.nT * kT;
-    const int64_t c0 = pcol_off[i], c1 = pcol_off[i + 1];
     const T* ph = phi + phi_off[i] + r;
     double acc = 0.0;
-    // eight columns at a time: their indices, then their coefficients, then the shape
-    // vector entries of the nonzero ones are each issued together (three dependent
-    // loads per group instead of per column); the sum keeps the column order
-    for (int64_t k = c0; k < c1; k += 8) {
-        const int m = (int)min((int64_t)8, c1 - k);
-        int32_t cl[8];
-        double a[8];
+    int k = 0;
+    for (; k + 8 <= nc; k += 8) {
         T p[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cl[u] = u < m ? pcols[k + u] : -1;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = cl[u] >= 0 ? coef[cl[u]] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] = a[u] != 0.0 ? ph[(k + u - c0) * ld] : (T)0;
+        for (int u = 0; u < 8; ++u) p[u] = ph[(int64_t)(k + u) * ld];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (a[u] != 0.0) acc += a[u] * (double)p[u];
+            if (acoef[k + u] != 0.0) acc += acoef[k + u] * (double)p[u];
     }
-    z[slots[t]] = (O)acc;
+    for (; k < nc; ++k)
+        if (acoef[k] != 0.0) acc += acoef[k] * (double)ph[(int64_t)k * ld];
+    z[slots[sb.slot_off + r]] = (O)acc;
 }
 
 // z on interface cells' pressures: the coarse pressure of their interface.
@@ -193,7 +209,23 @@ __global__ void gemv_kernel(const double* __restrict__ A, CoBlk cb, const double
     const double* a = A + cb.moff[b] + (int64_t)cb.loc[i] * n;
     const int32_t* idx = cb.idx + cb.ioff[b];
     double acc = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) acc += a[j] * x[idx[j]];
+    int j = threadIdx.x;
+    // four entries per pass, their loads in flight together
+    for (; j + 3 * (int)blockDim.x < n; j += 4 * (int)blockDim.x) {
+        double av[4];
+        int32_t iv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            av[u] = a[j + u * blockDim.x];
+            iv[u] = idx[j + u * blockDim.x];
+        }
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = x[iv[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += av[u] * xv[u];
+    }
+    for (; j < n; j += blockDim.x) acc += a[j] * x[idx[j]];
     double s = block_sum(acc, sh);
     if (threadIdx.x == 0) y[i] = s;
 }
@@ -295,10 +327,10 @@ static T* pvec(gplmm_ctx* c, int k) {
 template <typename T, typename O>
 static void prolong(gplmm_ctx* c, const double* coef, O* z) {
     zero_fill<O>(c, z, c->N);
-    if (c->Np > 0)
-        prolong_prim_kernel<T, O><<<nb(c->prim_rows), kB, 0, c->stream>>>(
-            (const T*)c->d_phi, c->d_phi_off, c->d_phi_cols_off, c->d_phi_cols, c->d_subs, c->d_row_sub,
-            c->d_sub_slots, coef, z, c->prim_rows, c->tile);
+    if (c->n_prolong_blk > 0)
+        prolong_blk_kernel<T, O><<<c->n_prolong_blk, 256, sizeof(double) * std::max(c->max_pcols, 1), c->stream>>>(
+            (const T*)c->d_phi, c->d_phi_off, c->d_phi_cols_off, c->d_phi_cols, c->d_subs, c->d_prolong_blk,
+            c->d_sub_slots, coef, z, c->tile);
     if (c->Nc > 0)
         prolong_iface_kernel<O><<<c->Nc, 64, 0, c->stream>>>(c->d_grp_ptr, c->d_grp_slot, c->Nc, coef, z);
 }

@@ -99,12 +99,13 @@ def make_workload(name, seed=0, re=None, **over):
 
 
 def make_batch(nsamples, seed=0, sizes=(48, 96), porosity=(0.3, 0.6), re=(0.1, 20.0), mean_r=8.0,
-               sigma=0.3, ndim=3, footprint=5, min_size=200, max_size=1500, block=8):
+               sigma=0.3, ndim=3, footprint=5, min_size=200, max_size=1500, block=8, progress=None):
     """A batch of independent samples of uneven size: per sample, each axis drawn
     uniformly from sizes[0]..sizes[1] voxels, the porosity uniformly from ``porosity``
     and the target Re log-uniformly from ``re``; overlapping lognormal grains (Boolean
     model, the grain law of the 3D packings above), labelled by the same watershed.
-    Returns a list of workload dicts (as make_workload)."""
+    Returns a list of workload dicts (as make_workload); progress(k, sample), if given, is
+    called after each sample."""
     rng = np.random.default_rng(1000003 + seed)
     out = []
     for k in range(nsamples):
@@ -118,4 +119,6 @@ def make_batch(nsamples, seed=0, sizes=(48, 96), porosity=(0.3, 0.6), re=(0.1, 2
         bx = body_force_for_re(mask, re_t)
         out.append(dict(mask=mask, labels=labels, rho=1.0, mu=1.0, body=(bx, 0.0, 0.0),
                         name="batch%d_%d" % (seed, k), seed=seed, re_target=re_t, porosity=phi))
+        if progress is not None:
+            progress(k, out[-1])
     return out
