@@ -212,8 +212,9 @@ def _batch(args):
     """The many-sample configuration: args.batch independent samples (each axis 48..96
     voxels, porosity 0.3..0.6, target Re log-uniform in 0.1..20, seed args.seed) in one
     context, every subdomain of every sample in the same launches, one Newton-FGMRES over
-    the batch with per-sample Krylov coefficients (FP32 preconditioner, restart 64, at
-    most args.batch_maxit FGMRES iterations per Newton step, 12 Newton steps).  One JSON
+    the batch with per-sample Krylov coefficients (FP32 preconditioner, restart
+    args.batch_restart, at most args.batch_maxit FGMRES iterations per Newton step, 12
+    Newton steps).  One JSON
     line: wall time, per-sample relative residuals and convergence."""
     import numpy as np
     import torch
@@ -228,7 +229,8 @@ def _batch(args):
     t0 = time.perf_counter()
     B = BatchSolver([w["mask"] for w in ws], [w["labels"] for w in ws], rho=[w["rho"] for w in ws],
                     mu=[w["mu"] for w in ws], bodies=[w["body"] for w in ws], precision=args.precision,
-                    restart=64, newton_tol=1e-8, lin_tol=1e-9, lin_maxit=args.batch_maxit, newton_maxit=12)
+                    restart=args.batch_restart, newton_tol=1e-8, lin_tol=1e-9, lin_maxit=args.batch_maxit,
+                    newton_maxit=12)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = B.info()
@@ -244,7 +246,7 @@ def _batch(args):
     rs = B.sample_residuals(x)
     out = {"metric": "batch solve wall time", "value": el, "unit": "s", "samples": len(ws), "unknowns": info["N"],
            "pores": info["Np"], "interfaces": info["Nc"], "setup_s": setup_s, "precision": args.precision,
-           "restart": 64, "lin_maxit": args.batch_maxit, "newton_its": st["newton_its"], "fgmres_its": st["lin_its"],
+           "restart": args.batch_restart, "lin_maxit": args.batch_maxit, "newton_its": st["newton_its"], "fgmres_its": st["lin_its"],
            "fgmres_its_total": st["lin_its_total"], "converged": bool(st["converged"]),
            "samples_converged": int((rs <= 1e-8).sum()), "sample_rel_residual": [float(v) for v in rs],
            "sample_re_target": [w["re_target"] for w in ws], "sample_shape": [list(w["mask"].shape) for w in ws],
@@ -294,6 +296,7 @@ def main():
                     help="only run the many-sample configuration with this many samples (64: each axis "
                          "48..96, porosity 0.3..0.6, Re 0.1..20)")
     ap.add_argument("--batch-maxit", type=int, default=2000, help="FGMRES iterations per Newton step (--batch)")
+    ap.add_argument("--batch-restart", type=int, default=128, help="FGMRES restart length (--batch)")
     args = ap.parse_args()
     if args.batch:
         _batch(args)
