@@ -497,6 +497,21 @@ def main():
         sr.close()
         del sr
         torch.cuda.empty_cache()
+        # the direct Re 10 solve with the Eq. xf step in the coarse correction (mg_form 2)
+        sr = Solver(wr["mask"], wr["labels"], rho=wr["rho"], mu=wr["mu"], body=wr["body"],
+                    precision=args.precision, newton_tol=1e-8, lin_tol=1e-9, restart=args.restart,
+                    lin_maxit=4000, mg_form=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, sx2 = sr.newton_solve()
+        torch.cuda.synchronize()
+        out["re10_continuation"]["direct_eq_xf"] = {"s": time.perf_counter() - t0, "newton_its": sx2["newton_its"],
+                                                    "fgmres_its_total": sx2["lin_its_total"],
+                                                    "converged": sx2["converged"]}
+        log("Re 10 with Eq. xf: %s" % json.dumps(out["re10_continuation"]["direct_eq_xf"]))
+        sr.close()
+        del sr
+        torch.cuda.empty_cache()
     if not args.no_fp64_plain:
         log("plain FP64 preconditioner on the same workload ...")
         del s
