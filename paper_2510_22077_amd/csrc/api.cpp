@@ -331,6 +331,7 @@ int upload_all(gplmm_ctx* c) {
     GP_TRY(upload(c, &c->d_cblk_ioff, c->cblk_ioff));
     GP_TRY(upload(c, &c->d_cblk_moff, c->cblk_moff));
     GP_TRY(alloc(c, (void**)&c->d_cv, sizeof(double) * 2 * std::max(nco, 1)));
+    GP_TRY(alloc(c, (void**)&c->d_probe_e, sizeof(double) * 2 * kProbeColors * std::max(nco, 1)));
     GP_TRY(alloc(c, (void**)&c->d_flag, sizeof(int) * 4));
     // vectors
     const int m = c->opt.restart;
@@ -1586,7 +1587,7 @@ void gplmm_destroy(gplmm_ctx* c) {
                     c->d_urow, c->d_tlc, c->d_step_pairs[0], c->d_step_pairs[1], c->d_sub_list[0], c->d_sub_list[1],
                     c->d_step_pairs[2], c->d_sub_list[2], c->d_splits, c->d_phase_order[0], c->d_phase_order[1],
                     c->d_sep_ids, c->d_sinv_off, c->d_sinv_ncols, c->d_sinv, c->d_fsub_order,
-                    c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off, c->d_prolong_blk,
+                    c->d_factor, c->d_phi, c->d_phi_rhs, c->d_phi_off, c->d_phi_cols, c->d_phi_cols_off, c->d_prolong_blk, c->d_probe_e,
                     c->d_phi_ncols, c->d_grp_ptr, c->d_grp_slot, c->d_dinv_ptr, c->d_dinv, c->d_Ao, c->d_Aowork,
                     c->d_piv, c->d_probe, c->d_color_cols, c->d_flag, c->d_wind, c->d_r, c->d_tmp,
                     c->d_dx, c->d_zero, c->d_V, c->d_Z, c->d_red, c->d_pv, c->d_local, c->d_cv, c->d_row_sub,

@@ -206,6 +206,7 @@ struct gplmm_ctx {
     int32_t* d_phi_cols = nullptr;
     int64_t* d_phi_cols_off = nullptr;
     int32_t* d_prolong_blk = nullptr;    // prolongation workgroups: (primary, 256-row chunk) pairs
+    double* d_probe_e = nullptr;         // probing: kProbeColors coarse indicator and image vectors
     int n_prolong_blk = 0, max_pcols = 0;
     int64_t* d_grp_ptr = nullptr;        // Rhat row groups: interfaces, then corrections
     int32_t* d_grp_slot = nullptr;
@@ -319,6 +320,9 @@ int coarse_features(gplmm_ctx* c, const double* wind_host, std::vector<float>& f
 void launch_bB(gplmm_ctx* c, double* bB, hipStream_t s);
 // y = Xcheck v: the primary and interface-cell rows of the column-summed build matrix (FP64)
 void launch_xcheck_v(gplmm_ctx* c, const double* v, double* y, hipStream_t s);
+// y = X v for kProbeColors vectors interleaved per slot (FP64, the tabulated rows read once)
+constexpr int kProbeColors = 8;
+void launch_xv_multi(gplmm_ctx* c, const double* v, double* y, hipStream_t s);
 
 // krylov.hip
 double dot(gplmm_ctx* c, const double* a, const double* b, int64_t n);

@@ -111,6 +111,108 @@ __global__ void prolong_iface_kernel(const int64_t* __restrict__ gptr, const int
     for (int64_t t = gptr[j] + threadIdx.x; t < gptr[j + 1]; t += blockDim.x) z[gslot[t]] = (O)coef[j];
 }
 
+// Probing K colours at once (K = 1, or K = kProbeColors with the colours of a slot
+// interleaved: vector q of slot s at z[s K + q], nb <= K of them in use and the rest zero;
+// coarse vectors at stride nco): the same sums as the single-vector prolongation and
+// restriction for every colour, each in its own order, with the shared reads (shape
+// vectors, slot lists) done once and every load unconditional.
+template <typename T, int K>
+__global__ void __launch_bounds__(256) prolong_blk_multi_kernel(const T* __restrict__ phi,
+                                                                const int64_t* __restrict__ phi_off,
+                                                                const int64_t* __restrict__ pcol_off,
+                                                                const int32_t* __restrict__ pcols,
+                                                                const Sub* __restrict__ subs,
+                                                                const int32_t* __restrict__ blk,
+                                                                const int32_t* __restrict__ slots,
+                                                                const double* __restrict__ coef, int nco, int nb,
+                                                                double* __restrict__ z, int kT) {
+    extern __shared__ double acoefm[];   // [column][colour]
+    const int i = blk[2 * blockIdx.x], chunk = blk[2 * blockIdx.x + 1];
+    const Sub sb = subs[i];
+    const int64_t c0 = pcol_off[i];
+    const int nc = (int)(pcol_off[i + 1] - c0);
+    for (int x = threadIdx.x; x < nc * K; x += blockDim.x) {
+        const int k = x / K, q = x % K;
+        const int32_t cl = pcols[c0 + k];
+        acoefm[x] = (cl >= 0 && q < nb) ? coef[(int64_t)q * nco + cl] : 0.0;
+    }
+    __syncthreads();
+    const int r = chunk * 256 + (int)threadIdx.x;
+    if (r >= sb.n) return;
+    const int64_t ld = (int64_t)sb.nT * kT;
+    const T* ph = phi + phi_off[i] + r;
+    double acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    for (int k = 0; k < nc; ++k) {
+        const double p = (double)ph[(int64_t)k * ld];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double a = acoefm[k * K + q];
+            if (a != 0.0) acc[q] += a * p;
+        }
+    }
+    const int64_t sl = slots[sb.slot_off + r];
+#pragma unroll
+    for (int q = 0; q < K; ++q) z[sl * K + q] = acc[q];
+}
+
+template <int K>
+__global__ void prolong_iface_multi_kernel(const int64_t* __restrict__ gptr, const int32_t* __restrict__ gslot,
+                                           int Nc, const double* __restrict__ coef, int nco, int nb,
+                                           double* __restrict__ z) {
+    const int j = blockIdx.x;
+    if (j >= Nc) return;
+    for (int64_t t = gptr[j] + threadIdx.x; t < gptr[j + 1]; t += blockDim.x) {
+        const int64_t sl = gslot[t];
+#pragma unroll
+        for (int q = 0; q < K; ++q) z[sl * K + q] = q < nb ? coef[(int64_t)q * nco + j] : 0.0;
+    }
+}
+
+template <int K>
+__global__ void restrict_multi_kernel(const double* __restrict__ v, int nb, const int64_t* __restrict__ gptr,
+                                      const int32_t* __restrict__ gslot, double* __restrict__ out, int nco) {
+    __shared__ double sh[16][K];
+    const int g = blockIdx.x;
+    double acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    for (int64_t t = gptr[g] + threadIdx.x; t < gptr[g + 1]; t += blockDim.x) {
+        const int64_t sl = gslot[t];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += v[sl * K + q];
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_down(acc[q], off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) sh[wv][q] = acc[q];
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w][threadIdx.x];
+        out[(int64_t)threadIdx.x * nco + g] = t;
+    }
+}
+
+// e_q = indicator of colour k0 + q's columns, for q < nb (cols of the colours [k0, k0 + nb)
+// are contiguous: off[q] .. off[q + 1] relative to off[0])
+struct ColorSpan {
+    int64_t off[kProbeColors + 1];
+};
+
+__global__ void set_ones_multi_kernel(const int32_t* __restrict__ cols, ColorSpan sp, int nb, double* __restrict__ e,
+                                      int nco) {
+    const int64_t k = sp.off[0] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= sp.off[nb]) return;
+    int q = 0;
+    while (k >= sp.off[q + 1]) ++q;
+    e[(int64_t)q * nco + cols[k]] = 1.0;
+}
+
 // Block-diagonal coarse storage: one dense row-major block per sample over the coarse
 // indices idx[ioff[b] .. ioff[b+1]); blk/loc give each coarse index's block and position.
 struct CoBlk {
@@ -127,18 +229,15 @@ __device__ __forceinline__ int64_t co_pos(const CoBlk& cb, int row, int col) {
     return cb.moff[b] + (int64_t)cb.loc[row] * cb.n[b] + cb.loc[col];
 }
 
-// Ao[row, col] = t[row] for the colour's (row, col) entries.
-__global__ void probe_scatter_kernel(const ProbeEntry* __restrict__ ent, int64_t n, const double* __restrict__ t,
-                                     double* __restrict__ Ao, CoBlk cb) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    ProbeEntry p = ent[k];
-    Ao[co_pos(cb, p.row, p.col)] = t[p.row];
-}
-
-__global__ void set_ones_kernel(const int32_t* __restrict__ cols, int64_t n, double* __restrict__ e, double val) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) e[cols[k]] = val;
+// Ao[row, col] = t_q[row] for the (row, col) entries of colour k0 + q.
+__global__ void probe_scatter_multi_kernel(const ProbeEntry* __restrict__ ent, ColorSpan sp, int nb,
+                                           const double* __restrict__ t, int nco, double* __restrict__ Ao, CoBlk cb) {
+    const int64_t k = sp.off[0] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= sp.off[nb]) return;
+    int q = 0;
+    while (k >= sp.off[q + 1]) ++q;
+    const ProbeEntry p = ent[k];
+    Ao[co_pos(cb, p.row, p.col)] = t[(int64_t)q * nco + p.row];
 }
 
 // zp[slot] = local solution (primaries are disjoint)
@@ -385,29 +484,44 @@ static int learned_coarse(gplmm_ctx* c) {
     return GPLMM_OK;
 }
 
-// The coarse blocks <- Rhat A Phat by probing: each colour's columns are prolonged together,
-// A is applied by mv(pv, xv) (FP64 vectors), the result restricted and scattered into
-// the entries of those columns.  Scratch: the first two Krylov basis vectors, which hold
-// nothing between FGMRES solves (the Newton residual and step vectors must survive a
-// rebuild).
-template <typename T, typename MV>
-static void probe_coarse(gplmm_ctx* c, MV mv) {
+// The coarse blocks <- Rhat A Phat by probing: the columns of one colour are prolonged
+// together, A is applied, the result restricted and scattered into the entries of those
+// columns.  K colours go through each pass side by side, interleaved per slot
+// (mvm(pv, xv, nq) applies A to them); K = 1 is one plain vector per colour.  Scratch:
+// the first 2K Krylov basis vectors, which hold nothing between FGMRES solves (the
+// Newton residual and step vectors must survive a rebuild).
+template <typename T, int K, typename MVM>
+static void probe_coarse(gplmm_ctx* c, MVM mvm) {
     hipStream_t s = c->stream;
     const int nco = c->nco;
+    const int64_t N = c->N;
     hipMemsetAsync(c->d_Ao, 0, sizeof(double) * c->co_elems, s);
-    double* e = c->d_cv;
-    double* tco = c->d_cv + nco;
+    double* E = c->d_probe_e;
+    double* tc = c->d_probe_e + (int64_t)kProbeColors * nco;
     double* pv = c->d_V;
-    double* xv = c->d_V + c->N;
-    for (int k = 0; k < c->ncolors; ++k) {
-        int64_t c0 = c->color_col_off[k], c1 = c->color_col_off[k + 1];
-        hipMemsetAsync(e, 0, sizeof(double) * nco, s);
-        set_ones_kernel<<<nb(c1 - c0), kB, 0, s>>>(c->d_color_cols + c0, c1 - c0, e, 1.0);
-        prolong<T, double>(c, e, pv);
-        mv(pv, xv);
-        restrict_<double>(c, xv, tco);
-        int64_t p0 = c->color_off[k], p1 = c->color_off[k + 1];
-        probe_scatter_kernel<<<nb(p1 - p0), kB, 0, s>>>(c->d_probe + p0, p1 - p0, tco, c->d_Ao, coblk(c));
+    double* xv = c->d_V + (int64_t)K * N;
+    for (int k0 = 0; k0 < c->ncolors; k0 += K) {
+        const int nq = std::min(K, c->ncolors - k0);
+        ColorSpan cs{}, ps{};
+        for (int q = 0; q <= nq; ++q) {
+            cs.off[q] = c->color_col_off[k0 + q];
+            ps.off[q] = c->color_off[k0 + q];
+        }
+        zero_fill<double>(c, E, (int64_t)nq * nco);
+        if (cs.off[nq] > cs.off[0])
+            set_ones_multi_kernel<<<nb(cs.off[nq] - cs.off[0]), kB, 0, s>>>(c->d_color_cols, cs, nq, E, nco);
+        zero_fill<double>(c, pv, (int64_t)K * N);
+        if (c->n_prolong_blk > 0)
+            prolong_blk_multi_kernel<T, K><<<c->n_prolong_blk, 256, sizeof(double) * K * std::max(c->max_pcols, 1), s>>>(
+                (const T*)c->d_phi, c->d_phi_off, c->d_phi_cols_off, c->d_phi_cols, c->d_subs, c->d_prolong_blk,
+                c->d_sub_slots, E, nco, nq, pv, c->tile);
+        if (c->Nc > 0)
+            prolong_iface_multi_kernel<K><<<c->Nc, 64, 0, s>>>(c->d_grp_ptr, c->d_grp_slot, c->Nc, E, nco, nq, pv);
+        mvm(pv, xv, nq);
+        if (nco > 0) restrict_multi_kernel<K><<<nco, kB, 0, s>>>(xv, nq, c->d_grp_ptr, c->d_grp_slot, tc, nco);
+        if (ps.off[nq] > ps.off[0])
+            probe_scatter_multi_kernel<<<nb(ps.off[nq] - ps.off[0]), kB, 0, s>>>(c->d_probe, ps, nq, tc, nco, c->d_Ao,
+                                                                               coblk(c));
     }
 }
 
@@ -417,7 +531,7 @@ static void probe_coarse(gplmm_ctx* c, MV mv) {
 // X stays inside one primary, so the pattern is the same) and inverted in place.
 template <typename T>
 int coarse_jacobian(gplmm_ctx* c, const double* xk) {
-    probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_jv(c, xk, pv, xv, c->stream, true); });
+    probe_coarse<T, 1>(c, [&](const double* pv, double* xv, int) { launch_jv(c, xk, pv, xv, c->stream, true); });
     return coarse_invert(c);
 }
 
@@ -494,9 +608,11 @@ int build_precond(gplmm_ctx* c) {
     if (nco > 0) {
         timer_begin(c, "build_coarse");
         if (c->opt.mg_form == 1)   // Eq. iMG: Rhat Xcheck Phat
-            probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_xcheck_v(c, pv, xv, s); });
+            probe_coarse<T, 1>(c, [&](const double* pv, double* xv, int) { launch_xcheck_v(c, pv, xv, s); });
+        else if (c->opt.restart + 1 >= 2 * kProbeColors)
+            probe_coarse<T, kProbeColors>(c, [&](const double* pv, double* xv, int) { launch_xv_multi(c, pv, xv, s); });
         else
-            probe_coarse<T>(c, [&](const double* pv, double* xv) { launch_xv<double>(c, pv, xv, nullptr, s); });
+            probe_coarse<T, 1>(c, [&](const double* pv, double* xv, int) { launch_xv<double>(c, pv, xv, nullptr, s); });
         GP_HIP(c, hipGetLastError());
         GP_HIP(c, hipStreamSynchronize(s));
         c->last_coarse_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();

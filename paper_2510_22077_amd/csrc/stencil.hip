@@ -190,6 +190,103 @@ __global__ void __launch_bounds__(kBlock) xv_kernel(DevGeo g, const T* __restric
     y[s] = a ? (T)(a[s] - m) : m;
 }
 
+// y = X b for kProbeColors vectors interleaved per slot (vector q of slot s at s K + q,
+// FP64): the operation of xv_kernel with a = nullptr on each vector, in the same order, the
+// tabulated coefficients and the neighbour table read once and each neighbour's K values
+// read as one contiguous 64-byte run (the probing of the coarse operator).
+template <int ND, bool kJac>
+__global__ void __launch_bounds__(kBlock) xv_multi_kernel(DevGeo g, const double* __restrict__ coef,
+                                                          const double* __restrict__ b, double* __restrict__ y) {
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    constexpr int nr = ND + 1;
+    constexpr int K = kProbeColors;
+    const Nb<ND> nc = load_nb<ND>(g, c);
+    const int64_t nce = g.ncell;
+    const double ih = 1.0 / g.h;
+    auto ldv = [&](int64_t slot, double (&out)[K]) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) out[q] = b[slot * K + q];
+    };
+    double pc[K];
+    ldv(nr * c + ND, pc);
+#pragma unroll
+    for (int ax = 0; ax < ND; ++ax) {
+        const int64_t s = nr * c + ax;
+        double acc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] = 0.0;
+        const int32_t L = nc.n[ax][0];
+        if (L >= 0) {
+            const double cd = coef[ax * nce + c];
+            double bs[K], bl[K];
+            ldv(s, bs);
+            ldv((int64_t)nr * L + ND, bl);
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = cd * bs[q] + ih * (pc[q] - bl[q]);
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const double w = coef[((1 + 2 * d + t) * ND + ax) * nce + c];
+                    const int32_t P = nc.n[d][t];
+                    if (w != 0.0 && P >= 0) {
+                        double bp[K];
+                        ldv((int64_t)nr * P + ax, bp);
+#pragma unroll
+                        for (int q = 0; q < K; ++q) acc[q] += w * bp[q];
+                    }
+                }
+            if (kJac) {
+                const Nb<ND> nl = load_nb<ND>(g, L);
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    if (d == ax) continue;
+                    const int dd = d < ax ? d : d - 1;
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const double w = coef[((1 + 2 * ND + 4 * dd + q4) * ND + ax) * nce + c];
+                        if (w != 0.0) {
+                            double bj[K];
+                            ldv((int64_t)nr * jac_col_cell<ND>(nc, nl, c, L, d, q4) + d, bj);
+#pragma unroll
+                            for (int q = 0; q < K; ++q) acc[q] += w * bj[q];
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) y[s * K + q] = acc[q];
+    }
+    const int64_t sp = nr * c + ND;
+    if ((g.tag[c] & kPinBit)) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) y[sp * K + q] = pc[q];
+    } else {
+        double m[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) m[q] = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < ND; ++ax) {
+            if (nc.n[ax][0] >= 0) {
+                double bv[K];
+                ldv(nr * c + ax, bv);
+#pragma unroll
+                for (int q = 0; q < K; ++q) m[q] += ih * bv[q];
+            }
+            if (nc.n[ax][1] >= 0) {
+                double bv[K];
+                ldv((int64_t)nr * nc.n[ax][1] + ax, bv);
+#pragma unroll
+                for (int q = 0; q < K; ++q) m[q] -= ih * bv[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) y[sp * K + q] = m[q];
+    }
+}
+
 // y = Xcheck b, the rows of Eq. iMG's column-summed operator that the restriction Rhat
 // reads (Section 3.2.2): a row of a primary's unknown keeps its columns in that primary
 // and on interface cells, an interface cell's mass row keeps every column but the
@@ -352,6 +449,20 @@ void launch_xcheck_v(gplmm_ctx* c, const double* v, double* y, hipStream_t s) {
     } else {
         if (jac) xcheck_kernel<2, true><<<gr, b, 0, s>>>(c->geo, cf, c->d_slot_class, c->d_noclose, v, y);
         else xcheck_kernel<2, false><<<gr, b, 0, s>>>(c->geo, cf, c->d_slot_class, c->d_noclose, v, y);
+    }
+}
+
+void launch_xv_multi(gplmm_ctx* c, const double* v, double* y, hipStream_t s) {
+    const dim3 gr = grid_for(c->ncell, c->stencil_block);
+    const int b = c->stencil_block;
+    const bool jac = c->opt.build_matrix == GPLMM_BUILD_JACOBIAN;
+    const double* cf = c->d_xcoef;
+    if (c->ndim == 3) {
+        if (jac) xv_multi_kernel<3, true><<<gr, b, 0, s>>>(c->geo, cf, v, y);
+        else xv_multi_kernel<3, false><<<gr, b, 0, s>>>(c->geo, cf, v, y);
+    } else {
+        if (jac) xv_multi_kernel<2, true><<<gr, b, 0, s>>>(c->geo, cf, v, y);
+        else xv_multi_kernel<2, false><<<gr, b, 0, s>>>(c->geo, cf, v, y);
     }
 }
 
