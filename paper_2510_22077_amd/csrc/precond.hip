@@ -198,8 +198,8 @@ __global__ void restrict_multi_kernel(const double* __restrict__ v, int nb, cons
     }
 }
 
-// e_q = indicator of colour k0 + q's columns, for q < nb (cols of the colours [k0, k0 + nb)
-// are contiguous: off[q] .. off[q + 1] relative to off[0])
+// e_q = indicator of colour k0 + q's columns, for q < nb: the colours' entries are
+// contiguous in the column (or probe-entry) list, colour k0 + q at [off[q], off[q + 1])
 struct ColorSpan {
     int64_t off[kProbeColors + 1];
 };
